@@ -1,0 +1,175 @@
+"""Seeded synthetic workloads for the oblate transit light curve.
+
+This module only draws inputs: parameter blocks, time grids, CSR offsets and
+supersampling factors.  It holds none of the flux arithmetic, so that both the
+GPU path and the CPU oracle can be fed from it without sharing any of the
+method.
+
+Parameter block layout (SoA, ``float64[10][n_sets]``):
+    k, f, theta, phi, b, a/R*, P (days), t0 (days), q1, q2
+``k`` is the equatorial radius ratio, ``theta`` the angle between spin axis
+and line of sight, ``phi`` the sky rotation of the projected spin axis, and
+``q1, q2`` the Kipping (2013) limb-darkening parameters (the paper fits these,
+Section 3).
+
+The workloads stand in for the paper's data (K2 long cadence at ~30 min,
+K2 short cadence at 1 min, JWST at 1-2 min; Section 3 and Section 5.3), which
+are not used here: every value is drawn from a seed.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+NPARAM = 10
+K, F, THETA, PHI, B, ARS, P, T0, Q1, Q2 = range(NPARAM)
+PARAM_NAMES = ("k", "f", "theta", "phi", "b", "ars", "P", "t0", "q1", "q2")
+
+PERIOD_DAYS = 500.0
+MINUTE = 1.0 / 1440.0
+
+
+@dataclass
+class Workload:
+    """A batch in the library's layout.
+
+    ``offsets is None``: shared grid, ``out`` has shape ``[n_sets, n_times]``.
+    Otherwise CSR: set ``s`` owns ``times[offsets[s]:offsets[s+1]]``.
+    """
+    name: str
+    params: np.ndarray                 # float64 [10, n_sets]
+    times: np.ndarray                  # float64 [n_times] or [offsets[-1]]
+    offsets: np.ndarray | None         # int64 [n_sets + 1] or None
+    n_ss: np.ndarray                   # int32 [n_sets]
+    t_exp: np.ndarray                  # float64 [n_sets]
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_sets(self) -> int:
+        return self.params.shape[1]
+
+    @property
+    def n_out(self) -> int:
+        if self.offsets is None:
+            return self.n_sets * self.times.shape[0]
+        return int(self.offsets[-1])
+
+    @property
+    def n_sub(self) -> int:
+        """Number of sub-samples (outputs times their supersampling factor)."""
+        if self.offsets is None:
+            return int(self.times.shape[0] * np.sum(self.n_ss, dtype=np.int64))
+        seg = np.diff(self.offsets)
+        return int(np.sum(seg * self.n_ss.astype(np.int64)))
+
+
+def q_from_u(u1: float, u2: float) -> tuple[float, float]:
+    """Kipping's (q1, q2) for given quadratic coefficients (used only to state
+    a workload quoted in u1, u2 in the library's q1, q2 layout)."""
+    s = u1 + u2
+    return s * s, u1 / (2.0 * s)
+
+
+def full_duration(k, b, ars, period):
+    """First-to-fourth-contact time of a sphere of radius k (days): the
+    textbook circular-orbit duration, used here only to size time grids."""
+    k, b, ars = np.asarray(k), np.asarray(b), np.asarray(ars)
+    sin_i = np.sqrt(1.0 - (b / ars) ** 2)
+    arg = np.sqrt(np.maximum((1.0 + k) ** 2 - b ** 2, 0.0)) / (ars * sin_i)
+    return period / math.pi * np.arcsin(np.minimum(arg, 1.0))
+
+
+def draw_params(rng: np.random.Generator, n: int, f_max: float = 0.9) -> np.ndarray:
+    """MCMC-walker priors: k~U[0.05,0.12], f~U[0,f_max], theta~U[0,pi],
+    phi~U[0,2pi), b~U[0,0.9], a/R*~U[100,300], q1,q2~U[0,1]; drawn column by
+    column in that order.  P = 500 d, t0 = 0."""
+    p = np.empty((NPARAM, n))
+    p[K] = rng.uniform(0.05, 0.12, n)
+    p[F] = rng.uniform(0.0, f_max, n)
+    p[THETA] = rng.uniform(0.0, math.pi, n)
+    p[PHI] = rng.uniform(0.0, 2.0 * math.pi, n)
+    p[B] = rng.uniform(0.0, 0.9, n)
+    p[ARS] = rng.uniform(100.0, 300.0, n)
+    p[Q1] = rng.uniform(0.0, 1.0, n)
+    p[Q2] = rng.uniform(0.0, 1.0, n)
+    p[P] = PERIOD_DAYS
+    p[T0] = 0.0
+    return p
+
+
+def single_transit(n_times: int = 1000) -> Workload:
+    """One parameter set: k=0.1, f=0.3, theta=60 deg, phi=30 deg, b=0.3,
+    a/R*=200, P=500 d, u1=0.4, u2=0.25; times uniform over +-1 transit
+    duration around mid-transit; no supersampling."""
+    q1, q2 = q_from_u(0.4, 0.25)
+    p = np.array([[0.1], [0.3], [math.pi / 3], [math.pi / 6], [0.3], [200.0],
+                  [PERIOD_DAYS], [0.0], [q1], [q2]])
+    t14 = float(full_duration(0.1, 0.3, 200.0, PERIOD_DAYS))
+    times = np.linspace(-t14, t14, n_times)
+    return Workload("single_transit", p, times, None, np.ones(1, np.int32),
+                    np.zeros(1), {"t14": t14})
+
+
+def walker_batch(n_sets: int = 4096, n_times: int = 3000, n_ss: int = 15,
+                 seed: int = 2) -> Workload:
+    """MCMC-walker batch: shared grid at 29.4-min cadence centred on the
+    transit, each point box-averaged over n_ss midpoint sub-samples spanning
+    the cadence (K2-long-cadence-shaped)."""
+    rng = np.random.default_rng(seed)
+    p = draw_params(rng, n_sets)
+    dt = 29.4 * MINUTE
+    times = (np.arange(n_times) - (n_times - 1) / 2.0) * dt
+    return Workload("walker_batch", p, times, None,
+                    np.full(n_sets, n_ss, np.int32), np.full(n_sets, dt),
+                    {"cadence_days": dt, "seed": seed})
+
+
+def high_cadence(n_sets: int = 512, n_times: int = 65536, seed: int = 3) -> Workload:
+    """High-cadence deep-transit batch: f~U[0,0.2], 60-s cadence around the
+    transit, no supersampling (JWST/K2-short-cadence-shaped)."""
+    rng = np.random.default_rng(seed)
+    p = draw_params(rng, n_sets, f_max=0.2)
+    dt = 60.0 / 86400.0
+    times = (np.arange(n_times) - (n_times - 1) / 2.0) * dt
+    return Workload("high_cadence", p, times, None, np.ones(n_sets, np.int32),
+                    np.zeros(n_sets), {"cadence_days": dt, "seed": seed})
+
+
+def uneven_batch(n_sets: int = 16384, seed: int = 4, n_min: int = 200,
+                 n_max: int = 20000) -> Workload:
+    """Uneven batch: each walker has its own grid linspace(-T14, T14, n_w)
+    with n_w log-uniform in [n_min, n_max] and supersampling factor in
+    {1, 5, 15}; exposure = grid spacing; CSR layout."""
+    rng = np.random.default_rng(seed)
+    p = draw_params(rng, n_sets)
+    n_w = np.floor(np.exp(rng.uniform(math.log(n_min), math.log(n_max), n_sets))).astype(np.int64)
+    n_w = np.maximum(n_w, 2)
+    ss = rng.choice(np.array([1, 5, 15], np.int32), n_sets)
+    t14 = full_duration(p[K], p[B], p[ARS], p[P])
+    offsets = np.zeros(n_sets + 1, np.int64)
+    offsets[1:] = np.cumsum(n_w)
+    times = np.empty(int(offsets[-1]))
+    t_exp = np.empty(n_sets)
+    for s in range(n_sets):
+        g = np.linspace(-t14[s], t14[s], int(n_w[s]))
+        times[offsets[s]:offsets[s + 1]] = g
+        t_exp[s] = g[1] - g[0]
+    return Workload("uneven_batch", p, times, offsets, ss.astype(np.int32), t_exp,
+                    {"seed": seed})
+
+
+def surrogate_samples(n: int, seed: int, window: float = 0.6):
+    """Training / calibration samples for the residual surrogate: walker
+    priors, one time per sample drawn uniformly in +-window*T14."""
+    rng = np.random.default_rng(seed)
+    p = draw_params(rng, n)
+    t14 = full_duration(p[K], p[B], p[ARS], p[P])
+    t = rng.uniform(-window, window, n) * t14
+    return p, t
+
+
+def by_name(name: str, **kw) -> Workload:
+    return {"single_transit": single_transit, "walker_batch": walker_batch,
+            "high_cadence": high_cadence, "uneven_batch": uneven_batch}[name](**kw)
