@@ -1,0 +1,156 @@
+/*
+ * gl.h -- C ABI of the MI355X oblate-planet transit light-curve library.
+ *
+ * The library computes, for every (parameter set, time sample) pair, the
+ * relative stellar flux of a star with quadratic limb darkening while the
+ * sky-projected ellipse of an oblate spheroid on a circular orbit passes in
+ * front of it (Price et al., arXiv:2410.05408, Section 2 "Ellipsoid Transit
+ * Model": the coordinate map eq. coord-map, the projected boundary eqs. dx,
+ * dy1, dy2, and the Green's-theorem integrands for quadratic limb darkening).
+ * All arithmetic on the path is FP64 in hand-written HIP kernels for gfx950.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers marked "device" must point to device memory of the context's
+ *    GPU (for example torch tensors on that device).  The library never frees
+ *    or keeps caller pointers beyond the call; all work is only enqueued on
+ *    `stream` (a hipStream_t, NULL = default stream) and runs asynchronously.
+ *  - A context owns its workspace and launch plan and is used by one host
+ *    thread at a time.  Calls that overlap on one context race.
+ *  - Host-checkable errors (NULL pointers, sizes) return immediately and
+ *    enqueue nothing.  Per-element domain errors (see gl_lightcurve_batch)
+ *    write NaN to the affected outputs and set a device status word that
+ *    gl_ctx_sync_status reports.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef GL_H
+#define GL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GL_OK = 0,
+    GL_ERR_NULL = -1,    /* a required pointer is NULL */
+    GL_ERR_SIZE = -2,    /* a size or count is out of range */
+    GL_ERR_DOMAIN = -3,  /* device-side: some parameter set or grid was invalid */
+    GL_ERR_DEVICE = -4,  /* a HIP runtime call failed (message in last_error) */
+    GL_ERR_STATE = -5,   /* context not usable for this call */
+    GL_ERR_NOMEM = -6    /* workspace allocation failed */
+} gl_status;
+
+/* Parameter block rows (SoA, double[GL_NPARAM][n_sets]):
+ *  GL_K      equatorial radius / stellar radius, 0 < k < 1 (polar radius is k(1-f))
+ *  GL_F      flattening (R_eq - R_pol)/R_eq, eq. 1, 0 <= f < 1
+ *  GL_THETA  angle between spin axis and line of sight, rad (the paper's
+ *            eta = pi/2 - theta)
+ *  GL_PHI    sky rotation of the projected spin axis, rad (the paper's xi)
+ *  GL_B      impact parameter, |b| < a/R*
+ *  GL_ARS    orbital distance a/R* (the paper's d), > 1 + k
+ *  GL_P      orbital period, days, > 0
+ *  GL_T0     mid-transit time, days
+ *  GL_Q1, GL_Q2  Kipping (2013) quadratic limb-darkening parameters in [0, 1]
+ */
+enum { GL_K, GL_F, GL_THETA, GL_PHI, GL_B, GL_ARS, GL_P, GL_T0, GL_Q1, GL_Q2, GL_NPARAM };
+
+typedef struct gl_ctx gl_ctx;
+
+/* Creates a context on HIP device `device` (sets it current for the call).
+ * *ctx receives the context or NULL on failure. */
+gl_status gl_ctx_create(gl_ctx **ctx, int device);
+
+/* Releases the context's workspace; NULL is ignored.  Waits for the device. */
+void gl_ctx_destroy(gl_ctx *ctx);
+
+/* Light curves for a batch of parameter sets (Section 2: coordinate map,
+ * projected ellipse, Green's-theorem flux with quadratic limb darkening).
+ *
+ *  params   device, double[GL_NPARAM][n_sets] (row GL_K first), see above.
+ *  n_sets   number of parameter sets, >= 1.
+ *  times    device, days.  Shared grid (offsets == NULL): double[n_times],
+ *           the same times for every set.  CSR (offsets != NULL): the
+ *           concatenated per-set grids, double[n_times].
+ *  offsets  device, int64[n_sets + 1] or NULL.  CSR segment of set s is
+ *           [offsets[s], offsets[s+1]); offsets[0] must be 0, offsets must be
+ *           non-decreasing and offsets[n_sets] == n_times.
+ *  n_times  shared-grid length, or total CSR length; >= 1 (shared) / >= 0 (CSR).
+ *  n_ss     device int32[n_sets] supersampling factor in [1, 64], or NULL (1).
+ *  t_exp    device double[n_sets] exposure time in days (>= 0), or NULL (0).
+ *           Output i is the mean of the instantaneous flux at the n_ss
+ *           midpoints t_i + ((j + 1/2)/n_ss - 1/2) t_exp, j = 0..n_ss-1.
+ *  out      device double: shared grid [n_sets][n_times] (row-major);
+ *           CSR indexed like times.  Relative flux in [0, 1].
+ *  stream   hipStream_t to enqueue on (NULL: default stream).
+ *
+ * Domain errors (NaN/Inf parameters, k not in (0,1), f not in [0,1),
+ * a/R* <= 1 + k, |b| >= a/R*, P <= 0, q outside [0,1], n_ss outside [1,64],
+ * t_exp < 0, a CSR segment out of order or out of range): that set's outputs
+ * are NaN (a broken segment is skipped) and the status word is set.
+ * Returns GL_OK once the work is enqueued. */
+gl_status gl_lightcurve_batch(gl_ctx *ctx, const double *params, int64_t n_sets,
+                              const double *times, const int64_t *offsets,
+                              int64_t n_times, const int32_t *n_ss,
+                              const double *t_exp, double *out, void *stream);
+
+/* Waits for the context's device, then returns GL_ERR_DOMAIN if any batch
+ * since the last call met a domain error (and clears the flag), else GL_OK. */
+gl_status gl_ctx_sync_status(gl_ctx *ctx);
+
+/* Message of the last host-side error on this context ("" if none).  The
+ * string is owned by the context and valid until its next call. */
+const char *gl_ctx_last_error(const gl_ctx *ctx);
+
+/* Launch-plan autotuner: times the candidate persistent-grid sizes of the
+ * exact kernel on a representative batch (same arguments as
+ * gl_lightcurve_batch; `out` is overwritten) and keeps the fastest in the
+ * context's plan.  Synchronises `stream`.  Quadrature orders are not a plan
+ * setting: every sample picks its own (self-checking rules). */
+gl_status gl_autotune(gl_ctx *ctx, const double *params, int64_t n_sets,
+                      const double *times, const int64_t *offsets, int64_t n_times,
+                      const int32_t *n_ss, const double *t_exp, double *out,
+                      void *stream);
+
+/* Current plan: persistent wavefronts per compute unit of the compute kernel. */
+gl_status gl_ctx_get_plan(const gl_ctx *ctx, int *waves_per_cu);
+
+/* Sets the plan; waves_per_cu in [1, 32] (default 8). */
+gl_status gl_ctx_set_plan(gl_ctx *ctx, int waves_per_cu);
+
+/* When on != 0, later batches replay a captured HIP graph of the whole
+ * pipeline if their arguments equal the previous batch's (default on). */
+gl_status gl_ctx_set_graph(gl_ctx *ctx, int on);
+
+/* Instrumentation: with n_slots > 0, the next n_slots batches are launched
+ * directly (no graph) with HIP events recorded on their stream around the
+ * whole pipeline and around the compute kernel.  n_slots = 0 turns it off. */
+gl_status gl_ctx_set_timing(gl_ctx *ctx, int n_slots);
+
+/* Waits for the recorded batches and returns the summed compute-kernel and
+ * pipeline times (ms) and how many batches were timed; frees the slots for
+ * reuse.  Any output pointer may be NULL. */
+gl_status gl_ctx_get_timing(gl_ctx *ctx, double *compute_ms, double *pipeline_ms, int *n);
+
+/* Work census: runs the batch once (same arguments and results as
+ * gl_lightcurve_batch) with a counting variant of the compute kernel, waits,
+ * and writes counts[8] (host memory): in-window sub-samples, samples with the
+ * whole ellipse on the star, intersecting samples, in-window samples off the
+ * star, periodic-trapezoid nodes, 21-node Gauss-Kronrod pieces, Newton steps
+ * of the intersection solver, limb arcs. */
+gl_status gl_census(gl_ctx *ctx, const double *params, int64_t n_sets, const double *times,
+                    const int64_t *offsets, int64_t n_times, const int32_t *n_ss,
+                    const double *t_exp, double *out, void *stream, int64_t *counts);
+
+/* Algorithmic FP64 operations per census item (add/sub/mul/div/sqrt/
+ * transcendental = 1, fused multiply-add = 2), counted from the kernel source:
+ * per_item[8] (host memory) lines up with the census counts. */
+gl_status gl_flop_model(int64_t *per_item);
+
+/* Library version, e.g. "0.1.0". */
+const char *gl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

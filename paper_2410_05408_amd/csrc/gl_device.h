@@ -1,0 +1,870 @@
+// gl_device.h -- per-sample FP64 flux of an oblate planet (device and host).
+//
+// Computes, for one parameter set and one time, the fraction of quadratically
+// limb-darkened stellar flux blocked by the sky-projected ellipse of an oblate
+// spheroid on a circular orbit (Price et al. 2024, Section 2).
+//
+// Method (the paper's Green's-theorem boundary form, Section 2, with exact
+// intersections instead of limb snapping):
+//  * The projected ellipse is the paper's parametric curve
+//      x = x0 + dx cos(th),  y = y0 + dy1 cos(th) + dy2 sin(th)      (eqs. dx, dy1, dy2)
+//    with x0 = d cos(alpha) sin(beta), y0 = d sin(alpha).
+//  * The occulted region E cap D is bounded by ellipse arcs inside the stellar
+//    disk and limb arcs inside the ellipse.  Ellipse/limb intersections are the
+//    real roots of |p(th)|^2 - 1, a quartic in t = tan((th - th0)/2); they are
+//    isolated between the critical points of the quartic (roots of its cubic
+//    derivative, themselves isolated by the roots of the quadratic second
+//    derivative) and polished by safeguarded Newton, so no root is missed.
+//  * The three Green's integrands of the paper (f_flat, f_lin, f_quad) give the
+//    integrals of 1, mu and r^2 over the region.  On ellipse arcs they are
+//    integrated by Gauss-Legendre in a tangent half-angle variable with nodes
+//    clustered at both arc ends (the f_lin integrand behaves like
+//    (th - th_root)^(3/2) there); on limb arcs they have closed forms.  When
+//    the whole ellipse is on the star the flat and r^2 integrals are closed
+//    forms (ellipse area and second moment) and f_lin uses a full-turn rule
+//    clustered at the point nearest the limb.
+//  * The quadratic law I = 1 - u1(1-mu) - u2(1-mu)^2 = c0 + c1 mu + c2 r^2,
+//    normalised by Phi = pi (1 - u1/3 - u2/6), gives the occulted fraction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "gl_tables.h"
+
+#define GL_HD __host__ __device__ __forceinline__
+// heavy stages keep their own register allocation on the GPU
+#define GL_HD_CALL __host__ __device__ __attribute__((noinline))
+
+namespace gl {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 6.28318530717958647692;
+
+// Derived per-parameter-set constants (built once per set, kept in LDS/SGPRs).
+struct SetConst {
+    double A, B, C;        // dx, dy1, dy2 of the projected ellipse
+    double AC;             // dx * dy2 = k^2 q (area / pi)
+    double M2;             // dx^2 + dy1^2 + dy2^2 = k^2 (1 + q^2)
+    double K3, K4;         // (dx^2 + dy1^2 - dy2^2)/2 and dy1 * dy2
+    double k;              // largest semi-axis
+    double xb;             // d sin(beta) = b: x0 = xb cos(alpha)
+    double d;              // orbital distance: y0 = d sin(alpha)
+    double w_orb;          // 2 pi / P
+    double P, t0;
+    double half_win;       // instantaneous overlap needs |t - t0 - nP| < half_win
+    double c0, c1, c2;     // I = c0 + c1 mu + c2 r^2
+    double inv_phi;        // 1 / Phi
+    double t_exp;          // exposure (days)
+    int n_ss;              // midpoint sub-samples per output
+    int valid;             // 0: domain error, outputs are NaN
+};
+
+// ---------------------------------------------------------------- helpers
+GL_HD double sqr(double x) { return x * x; }
+
+// finite (not NaN, not +-inf); NaN fails every comparison
+GL_HD bool finite_d(double x) { return fabs(x) <= 1.7976931348623157e308; }
+
+// 1/x for the quadrature nodes: the hardware FP64 reciprocal estimate refined
+// by two Newton steps (relative error near one ulp; x is never 0, inf or
+// denormal here).  The host build uses the IEEE division.
+GL_HD double rcp(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+#else
+    return 1.0 / x;
+#endif
+}
+
+// sqrt(x) for x >= 0 from the hardware reciprocal-square-root estimate and
+// two Goldschmidt/Newton refinements; arguments below 1e-300 return 0.
+GL_HD double sqrt_nn(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    if (!(x > 1e-300)) return 0.0;
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    const double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    const double d2 = fma(-g, g, x);
+    return fma(d2, h, g);
+#else
+    return x > 0.0 ? sqrt(x) : 0.0;
+#endif
+}
+
+// sin and cos of a in [-pi, pi] (orbital phase): a = k pi/2 + r with
+// |r| <= pi/4 (pi/2 split in two parts, Cody-Waite style), Taylor series of
+// sin r and cos r to r^17 and r^16 (the next terms are below 1e-17), then the
+// quadrant turn.
+GL_HD void sincos_pi(double a, double& sn, double& cs)
+{
+    const double k = rint(a * 0.63661977236758134308);  // 2/pi
+    const double r = fma(-k, 1.5707963267948966e+00, fma(-k, 6.123233995736766e-17, a));
+    const double r2 = r * r;
+    double ps = 1.0 / 355687428096000.0;                       // 1/17!
+    ps = fma(ps, -r2, 1.0 / 1307674368000.0);                  // 1/15!
+    ps = fma(ps, r2, -1.0 / 6227020800.0);                     // 1/13!
+    ps = fma(ps, r2, 1.0 / 39916800.0);                        // 1/11!
+    ps = fma(ps, r2, -1.0 / 362880.0);                         // 1/9!
+    ps = fma(ps, r2, 1.0 / 5040.0);                            // 1/7!
+    ps = fma(ps, r2, -1.0 / 120.0);                            // 1/5!
+    ps = fma(ps, r2, 1.0 / 6.0);                               // 1/3!
+    const double s0 = fma(-r * r2, ps, r);
+    double pc = 1.0 / 20922789888000.0;                        // 1/16!
+    pc = fma(pc, -r2, 1.0 / 87178291200.0);                    // 1/14!
+    pc = fma(pc, r2, -1.0 / 479001600.0);                      // 1/12!
+    pc = fma(pc, r2, 1.0 / 3628800.0);                         // 1/10!
+    pc = fma(pc, r2, -1.0 / 40320.0);                          // 1/8!
+    pc = fma(pc, r2, 1.0 / 720.0);                             // 1/6!
+    pc = fma(pc, r2, -1.0 / 24.0);                             // 1/4!
+    pc = fma(pc, r2, 0.5);                                     // 1/2!
+    const double c0 = fma(-r2, pc, 1.0);
+    const int q = ((int)k) & 3;
+    sn = (q == 0) ? s0 : (q == 1) ? c0 : (q == 2) ? -s0 : -c0;
+    cs = (q == 0) ? c0 : (q == 1) ? -s0 : (q == 2) ? -c0 : s0;
+}
+
+// atan(z) for |z| <= 1: atan z = pi/6 + atan((z - 1/sqrt 3)/(1 + z/sqrt 3))
+// brings |z| below tan(pi/12); then the Taylor series to z^31.
+GL_HD double atan_unit(double z)
+{
+    const double az = fabs(z);
+    double base = 0.0, u = az;
+    if (az > 0.26794919243112270) {  // tan(pi/12)
+        const double is3 = 0.57735026918962576451;  // 1/sqrt(3)
+        u = (az - is3) / fma(az, is3, 1.0);
+        base = 0.52359877559829887308;               // pi/6
+    }
+    const double u2 = u * u;
+    double p = 1.0 / 31.0;
+#pragma unroll
+    for (int n = 29; n >= 1; n -= 2) p = fma(p, -u2, 1.0 / n);
+    const double r = base + u * p;
+    return z < 0.0 ? -r : r;
+}
+
+// atan2(y, x) in (-pi, pi] from atan_unit.
+GL_HD double atan2_d(double y, double x)
+{
+    const double ay = fabs(y), ax = fabs(x);
+    double a;
+    if (ay <= ax) {
+        a = (ax > 0.0) ? atan_unit(ay / ax) : 0.0;
+    } else {
+        a = 1.57079632679489661923 - atan_unit(ax / ay);
+    }
+    if (x < 0.0) a = 3.14159265358979323846 - a;
+    return (y < 0.0) ? -a : a;
+}
+
+// The paper's rotation R(zeta=0, eta, xi) = Ry(eta) Rz(xi) entries r1..r9 and
+// eqs. dx, dy1, dy2 with polar semi-axis a = k(1-f) (body x') and b = c = k.
+GL_HD void projected_ellipse(double k, double f, double theta, double phi,
+                             double& A, double& B, double& C)
+{
+    const double eta = 0.5 * kPi - theta;
+    const double ce = cos(eta), se = sin(eta), cx = cos(phi), sx = sin(phi);
+    // R = Ry(eta) Rz(xi)
+    const double r1 = ce * cx, r2 = -ce * sx, r3 = se;
+    const double r4 = sx, r5 = cx, r6 = 0.0;
+    const double r7 = -se * cx, r8 = se * sx, r9 = ce;
+    const double a = k * (1.0 - f), b = k, c = k;
+    const double a2 = a * a, b2 = b * b, c2 = c * c;
+    A = sqrt(a2 * r1 * r1 + b2 * r4 * r4 + c2 * r7 * r7);
+    B = (a2 * r1 * r2 + b2 * r4 * r5 + c2 * r7 * r8) / A;
+    C = sqrt(a2 * b2 * r9 * r9 + a2 * c2 * r6 * r6 + b2 * c2 * r3 * r3) / A;
+}
+
+// Builds SetConst from the parameter block values (k, f, theta, phi, b, a/R*,
+// P, t0, q1, q2).  Returns false on a domain error.
+GL_HD bool make_set_const(const double* p, double t_exp, int n_ss, SetConst& s)
+{
+    const double k = p[0], f = p[1], theta = p[2], phi = p[3], b = p[4];
+    const double d = p[5], P = p[6], t0 = p[7], q1 = p[8], q2 = p[9];
+    bool ok = true;
+    for (int i = 0; i < 10; ++i) ok = ok && finite_d(p[i]);
+    ok = ok && (k > 0.0) && (k < 1.0) && (f >= 0.0) && (f < 1.0) && (d > 1.0 + k) &&
+         (fabs(b) < d) && (P > 0.0) && (q1 >= 0.0) && (q1 <= 1.0) && (q2 >= 0.0) &&
+         (q2 <= 1.0) && finite_d(t_exp) && (t_exp >= 0.0) && (n_ss >= 1) && (n_ss <= 64);
+    s.valid = ok ? 1 : 0;
+    s.n_ss = n_ss;
+    s.t_exp = t_exp;
+    if (!ok) return false;
+    projected_ellipse(k, f, theta, phi, s.A, s.B, s.C);
+    s.AC = s.A * s.C;
+    s.M2 = s.A * s.A + s.B * s.B + s.C * s.C;
+    s.K3 = 0.5 * (s.A * s.A + s.B * s.B - s.C * s.C);
+    s.K4 = s.B * s.C;
+    s.k = k;
+    // orbit (eq. coord-map): sin(beta) = b/d, x0 = d cos(alpha) sin(beta)
+    s.xb = d * (b / d);
+    s.d = d;
+    s.P = P;
+    s.t0 = t0;
+    s.w_orb = kTwoPi / P;
+    // overlap needs rho^2 = b^2 cos^2(alpha) + d^2 sin^2(alpha) < (1 + k)^2 with
+    // cos(alpha) > 0, i.e. sin^2(alpha) < ((1+k)^2 - b^2) / (d^2 - b^2)
+    const double num = (1.0 + k) * (1.0 + k) - b * b;
+    if (num > 0.0) {
+        const double sa = fmin(1.0, sqrt(num / ((d - b) * (d + b))));
+        s.half_win = (asin(sa) / s.w_orb) * (1.0 + 1e-9) + 1e-12 * P;
+    } else {
+        s.half_win = -1e300;  // never overlaps the disk
+    }
+    // Kipping (2013) q -> u, then I = c0 + c1 mu + c2 r^2
+    const double sq = sqrt(q1);
+    const double u1 = 2.0 * sq * q2, u2 = sq * (1.0 - 2.0 * q2);
+    s.c0 = 1.0 - u1 - 2.0 * u2;
+    s.c1 = u1 + 2.0 * u2;
+    s.c2 = u2;
+    s.inv_phi = 1.0 / (kPi * (1.0 - u1 / 3.0 - u2 / 6.0));
+    return true;
+}
+
+// Time offset from the nearest mid-transit, in (-P/2, P/2].
+GL_HD double phase_time(const SetConst& s, double t)
+{
+    const double dt = t - s.t0;
+    return dt - s.P * rint(dt / s.P);
+}
+
+// ---------------------------------------------------------------- work census
+// The census variant counts the work a sample really does (used to turn the
+// kernel time into an algorithmic FLOP rate); the default does nothing.
+struct NoCensus {
+    GL_HD void iter() {}
+    GL_HD void arc() {}
+    GL_HD void trap(int) {}
+    GL_HD void limb() {}
+};
+struct Census {
+    int iters = 0, arcs = 0, trap_nodes = 0, limbs = 0;
+    GL_HD void iter() { ++iters; }
+    GL_HD void arc() { ++arcs; }           // one 21-node Gauss-Kronrod piece
+    GL_HD void trap(int n) { trap_nodes += n; }
+    GL_HD void limb() { ++limbs; }
+};
+
+// ---------------------------------------------------------------- quartic
+struct Poly4 {
+    double a0, a1, a2, a3, a4;
+};
+
+GL_HD double p4(const Poly4& q, double t)
+{
+    return fma(fma(fma(fma(q.a4, t, q.a3), t, q.a2), t, q.a1), t, q.a0);
+}
+GL_HD double dp4(const Poly4& q, double t)
+{
+    return fma(fma(fma(4.0 * q.a4, t, 3.0 * q.a3), t, 2.0 * q.a2), t, q.a1);
+}
+GL_HD double ddp4(const Poly4& q, double t)
+{
+    return fma(fma(12.0 * q.a4, t, 6.0 * q.a3), t, 2.0 * q.a2);
+}
+
+// Root of a function that is monotone on [lo, hi] with values flo, fhi of
+// opposite sign at the ends: Newton from the regula-falsi point, with
+// bisection whenever a step leaves the bracket; stops when the step is at
+// rounding level or |f| is below the rounding noise of its own evaluation.
+template <int Deriv, class CT>
+GL_HD double bracket_root(const Poly4& q, double lo, double hi, double flo, double fhi, CT& ct)
+{
+    const double a0 = fabs(q.a0), a1 = fabs(q.a1), a2 = fabs(q.a2), a3 = fabs(q.a3),
+                 a4 = fabs(q.a4);
+    double x = lo - flo * (hi - lo) / (fhi - flo);
+    if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+    for (int it = 0; it < 100; ++it) {
+        ct.iter();
+        double f, df, noise;
+        const double ax = fabs(x);
+        if (Deriv == 0) {
+            f = p4(q, x);
+            df = dp4(q, x);
+            noise = fma(fma(fma(fma(a4, ax, a3), ax, a2), ax, a1), ax, a0);
+        } else {
+            f = dp4(q, x);
+            df = ddp4(q, x);
+            noise = fma(fma(fma(4.0 * a4, ax, 3.0 * a3), ax, 2.0 * a2), ax, a1);
+        }
+        if (fabs(f) <= 8e-16 * noise) return x;
+        if ((f < 0.0) == (flo < 0.0)) lo = x;
+        else hi = x;
+        double xn = x - f / df;
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        if (fabs(xn - x) <= 2e-16 * fmax(1.0, ax) || hi - lo <= 2e-16 * fmax(1.0, ax)) return xn;
+        x = xn;
+    }
+    return x;
+}
+
+// Real roots (ascending) and critical points (ascending) of the quartic.
+struct QuarticRoots {
+    int n_roots;
+    double r[4];
+    int n_crit;
+    double c[3];
+};
+
+template <class CT>
+GL_HD_CALL void solve_quartic(const Poly4& q, QuarticRoots& out, CT& ct)
+{
+    // Cauchy bound on all roots of q and of q'
+    const double inv = 1.0 / fabs(q.a4);
+    const double Bnd = 1.0 + fmax(fmax(fabs(q.a3), fabs(q.a2)), fmax(fabs(q.a1), fabs(q.a0))) * inv;
+    // inflection points: roots of q'' = 12 a4 t^2 + 6 a3 t + 2 a2
+    double infl[2];
+    int n_infl = 0;
+    {
+        const double qa = 12.0 * q.a4, qb = 6.0 * q.a3, qc = 2.0 * q.a2;
+        const double disc = qb * qb - 4.0 * qa * qc;
+        if (disc > 0.0) {
+            const double sd = sqrt(disc);
+            const double qq = -0.5 * (qb + copysign(sd, qb));
+            double x1 = qq / qa, x2 = (qq != 0.0) ? qc / qq : -x1;
+            if (x1 > x2) {
+                const double tmp = x1;
+                x1 = x2;
+                x2 = tmp;
+            }
+            infl[0] = x1;
+            infl[1] = x2;
+            n_infl = 2;
+        }
+    }
+    // critical points: roots of q' on the intervals where q' is monotone
+    double edges[4];
+    int ne = 0;
+    edges[ne++] = -Bnd;
+    for (int i = 0; i < n_infl; ++i)
+        if (infl[i] > -Bnd && infl[i] < Bnd) edges[ne++] = infl[i];
+    edges[ne++] = Bnd;
+    out.n_crit = 0;
+    for (int i = 0; i + 1 < ne; ++i) {
+        const double lo = edges[i], hi = edges[i + 1];
+        const double flo = dp4(q, lo), fhi = dp4(q, hi);
+        if ((flo < 0.0) != (fhi < 0.0) && flo != 0.0 && fhi != 0.0)
+            out.c[out.n_crit++] = bracket_root<1>(q, lo, hi, flo, fhi, ct);
+    }
+    // roots of q on the intervals between critical points
+    double e2[5];
+    int m = 0;
+    e2[m++] = -Bnd;
+    for (int i = 0; i < out.n_crit; ++i) e2[m++] = out.c[i];
+    e2[m++] = Bnd;
+    out.n_roots = 0;
+    for (int i = 0; i + 1 < m; ++i) {
+        const double lo = e2[i], hi = e2[i + 1];
+        const double flo = p4(q, lo), fhi = p4(q, hi);
+        if ((flo < 0.0) != (fhi < 0.0) && flo != 0.0 && fhi != 0.0 && out.n_roots < 4)
+            out.r[out.n_roots++] = bracket_root<0>(q, lo, hi, flo, fhi, ct);
+    }
+}
+
+// ---------------------------------------------------------------- geometry of one sample
+// Ellipse in the rotated angle psi = th - th0:
+//   x = x0 + Xc cos(psi) + Xs sin(psi),  y = y0 + Yc cos(psi) + Ys sin(psi)
+struct Frame {
+    double x0, y0;
+    double Xc, Xs, Yc, Ys;
+    double P0, P1, P2;     // x y' - y x' = P0 + P1 cos(psi) + P2 sin(psi)
+};
+
+GL_HD void make_frame(const SetConst& s, double x0, double y0, double c0a, double s0a, Frame& F)
+{
+    F.x0 = x0;
+    F.y0 = y0;
+    F.Xc = s.A * c0a;
+    F.Xs = -s.A * s0a;
+    F.Yc = s.B * c0a + s.C * s0a;
+    F.Ys = s.C * c0a - s.B * s0a;
+    F.P0 = s.AC;
+    F.P1 = x0 * F.Ys - y0 * F.Xs;
+    F.P2 = y0 * F.Xc - x0 * F.Yc;
+}
+
+// Sums of the three Green's integrands over E cap D: 1, mu and r^2.
+struct Sums {
+    double flat, lin, quad;
+};
+
+// Tolerances of the self-checking rules (absolute, on the integrals of 1 and
+// mu over the region; the flux error is at most about the same size).
+#ifndef GL_ARC_TOL
+#define GL_ARC_TOL 1e-7
+#endif
+#ifndef GL_TRAP_TOL
+#define GL_TRAP_TOL 1e-8
+#endif
+constexpr double kArcTol = GL_ARC_TOL;    // |K21 - G10| accepted on an arc
+constexpr double kTrapTol = GL_TRAP_TOL;  // |T_2n - T_n| accepted on a whole turn
+constexpr int kArcMaxLevel = 4;           // an arc is re-split at most into 16 pieces
+
+// One piece tau in [mid - half, mid + half] of the arc psi = psi_c + 2 atan(tau):
+// clustered Gauss-Kronrod 10/21 rule.  Adds the Kronrod sums to K and returns
+// the Gauss-Kronrod difference of the integrals of 1 and mu.
+GL_HD double gk_piece(const Frame& F, double cc, double sc, double mid, double half, Sums& K)
+{
+    double kf = 0.0, kl = 0.0, kq = 0.0, gf = 0.0, gl = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < 21; ++j) {
+        const double tau = mid + half * GK21_M[j];
+        const double t2 = tau * tau;
+        const double inv = rcp(1.0 + t2);
+        const double cu = (1.0 - t2) * inv, su = 2.0 * tau * inv;
+        const double c = cc * cu - sc * su, sn = sc * cu + cc * su;
+        const double x = F.x0 + F.Xc * c + F.Xs * sn;
+        const double y = F.y0 + F.Yc * c + F.Ys * sn;
+        const double dx = -F.Xc * sn + F.Xs * c;
+        const double dy = -F.Yc * sn + F.Ys * c;
+        const double x2 = x * x, y2 = y * y;
+        const double om = fmax(0.0, 1.0 - x2 - y2);
+        const double w = sqrt_nn(om);
+        const double G = 1.0 + om * rcp(1.0 + w);           // (1 + w + w^2)/(1 + w)
+        const double flat = F.P0 + F.P1 * c + F.P2 * sn;     // x y' - y x'
+        const double quad = x * (x2 * (1.0 / 3.0) + y2) * dy - y * (x2 + y2 * (1.0 / 3.0)) * dx;
+        const double fl = inv * flat, li = fl * G;           // dpsi = 2 dtau / (1 + tau^2)
+        kf += GK21_WK[j] * fl;
+        kl += GK21_WK[j] * li;
+        kq += GK21_WK[j] * (inv * quad);
+        gf += GK21_WG[j] * fl;
+        gl += GK21_WG[j] * li;
+    }
+    // dpsi factor 2, f_flat = flat/2, f_lin = (2/3) G flat/2, f_quad = quad/2
+    K.flat += half * kf;
+    K.lin += half * kl * (2.0 / 3.0);
+    K.quad += half * kq;
+    return half * (fabs(kf - gf) + (2.0 / 3.0) * fabs(kl - gl));
+}
+
+// Whole arc tau in [-h, h]: one Gauss-Kronrod piece, re-split uniformly into
+// 2, 4, ... pieces until the summed Gauss-Kronrod difference is below kArcTol.
+template <class CT>
+GL_HD_CALL void arc_gk(const Frame& F, double cc, double sc, double h, Sums& S, CT& ct)
+{
+    for (int L = 0;; ++L) {
+        const int np = 1 << L;
+        const double half = h / np;
+        Sums K = {0.0, 0.0, 0.0};
+        double err = 0.0;
+        for (int p = 0; p < np; ++p) {
+            err += gk_piece(F, cc, sc, -h + (2 * p + 1) * half, half, K);
+            ct.arc();
+        }
+        if (err <= kArcTol || L == kArcMaxLevel) {
+            S.flat += K.flat;
+            S.lin += K.lin;
+            S.quad += K.quad;
+            return;
+        }
+    }
+}
+
+// Orders of the periodic trapezoid rule for a whole ellipse on the star, and
+// cos/sin of their steps 2 pi / n.
+constexpr int kTrapOrders = 9;
+constexpr int kTrapN[kTrapOrders] = {8, 12, 16, 20, 24, 32, 40, 48, 64};
+
+GL_HD void trap_step(int i, double& c, double& s)
+{
+    switch (i) {
+    case 0: c = 0.70710678118654757; s = 0.70710678118654757; break;
+    case 1: c = 0.86602540378443860; s = 0.5; break;
+    case 2: c = 0.92387953251128674; s = 0.38268343236508978; break;
+    case 3: c = 0.95105651629515353; s = 0.30901699437494740; break;
+    case 4: c = 0.96592582628906831; s = 0.25881904510252074; break;
+    case 5: c = 0.98078528040323043; s = 0.19509032201612825; break;
+    case 6: c = 0.98768834059513777; s = 0.15643446504023087; break;
+    case 7: c = 0.99144486137381038; s = 0.13052619222005157; break;
+    default: c = 0.99518472667219693; s = 0.098017140329560604; break;
+    }
+}
+
+// Smallest trapezoid order n with n * d >= L, where d is the distance of the
+// nearest complex zero of 1 - r^2(th) from the real th axis (error ~ exp(-n d)).
+// The caller passes r = cosh(d) (or a lower bound of it), compared here with
+// cosh(L / n).  Returns -1 if even the largest order is not enough.
+constexpr double kTrapL = 30.0;
+constexpr double kTrapCosh[9] = {
+    // cosh(30 / n) for n = 8, 12, 16, 20, 24, 32, 40, 48, 64
+    21.2722705472043, 6.1322894796636, 3.3374035793208, 2.3524096152432, 1.8884239651648,
+    1.4725497384850, 1.2946832846768, 1.2017536151364, 1.1119268223779};
+
+GL_HD int trap_order_cosh(double r)
+{
+    for (int i = 0; i < kTrapOrders; ++i)
+        if (r >= kTrapCosh[i]) return i;
+    return -1;
+}
+
+GL_HD int trap_order(double d)
+{
+    for (int i = 0; i < kTrapOrders; ++i)
+        if (kTrapN[i] * d >= kTrapL) return i;
+    return -1;
+}
+
+// Whole ellipse, periodic trapezoid with n = kTrapN[oi] equally spaced nodes in
+// th (the integrand is periodic and analytic in a strip): mu integral.  Nodes
+// come in pairs +-th_j from a rotation recurrence.
+GL_HD_CALL double trap_lin(const SetConst& s, double x0, double y0, int oi)
+{
+    const double P1 = x0 * s.C, P2 = y0 * s.A - x0 * s.B;
+    const int n = kTrapN[oi];
+    double rc, rs;
+    trap_step(oi, rc, rs);
+    auto node = [&](double c, double sn) {
+        const double x = x0 + s.A * c;
+        const double y = y0 + s.B * c + s.C * sn;
+        const double om = fmax(0.0, 1.0 - x * x - y * y);
+        const double w = sqrt_nn(om);
+        return (1.0 + om * rcp(1.0 + w)) * (s.AC + P1 * c + P2 * sn);
+    };
+    double acc = node(1.0, 0.0) + node(-1.0, 0.0);
+    double c = rc, sn = rs;
+    for (int j = 1; j < n / 2; ++j) {
+        acc += node(c, sn) + node(c, -sn);
+        const double cn = c * rc - sn * rs;
+        sn = sn * rc + c * rs;
+        c = cn;
+    }
+    return acc * (kTwoPi / (3.0 * n));
+}
+
+// Whole ellipse, nested periodic trapezoid: 8, 16, 32, 64 nodes, each level
+// adding the midpoints of the previous one.  Returns true (and the mu
+// integral) once two successive levels agree to kTrapTol, judged from the
+// 16/32 pair on and only while the differences shrink (a coarse level can
+// agree with the next by accident before the convergence is exponential).
+GL_HD_CALL bool trap_lin_nested(const SetConst& s, double x0, double y0, double& out, int& levels)
+{
+    const double P1 = x0 * s.C, P2 = y0 * s.A - x0 * s.B;
+    auto node = [&](double c, double sn) {
+        const double x = x0 + s.A * c;
+        const double y = y0 + s.B * c + s.C * sn;
+        const double om = fmax(0.0, 1.0 - x * x - y * y);
+        const double w = sqrt_nn(om);
+        return (1.0 + om * rcp(1.0 + w)) * (s.AC + P1 * c + P2 * sn);
+    };
+    // level 8: nodes k pi/4
+    double sum = node(1.0, 0.0) + node(-1.0, 0.0) + node(0.0, 1.0) + node(0.0, -1.0);
+    {
+        const double r = TRAP_PI_C[0];  // cos(pi/4) = sin(pi/4)
+        sum += node(r, r) + node(r, -r) + node(-r, r) + node(-r, -r);
+    }
+    int n = 8;
+    double prev = sum * (kTwoPi / (3.0 * n));
+    double prev_diff = 1e300;
+    levels = 1;
+#pragma unroll 1
+    for (int L = 1; L <= 3; ++L) {
+        // midpoints (2j + 1) pi / n, j = 0 .. n/2 - 1, in +- pairs
+        const double c0 = TRAP_PI_C[L], s0 = TRAP_PI_S[L];          // pi / n
+        const double rc = TRAP_PI_C[L - 1], rs = TRAP_PI_S[L - 1];  // 2 pi / n
+        double c = c0, sn = s0, add = 0.0;
+#pragma unroll 2
+        for (int j = 0; j < n / 2; ++j) {
+            add += node(c, sn) + node(c, -sn);
+            const double cn = c * rc - sn * rs;
+            sn = sn * rc + c * rs;
+            c = cn;
+        }
+        sum += add;
+        n *= 2;
+        const double cur = sum * (kTwoPi / (3.0 * n));
+        const double diff = fabs(cur - prev);
+        ++levels;
+        if (n >= 32 && diff <= kTrapTol && diff <= prev_diff) {
+            out = cur;
+            return true;
+        }
+        prev = cur;
+        prev_diff = diff;
+    }
+    out = prev;
+    return false;
+}
+
+// Limb arc, counter-clockwise from unit vector direction (xa, ya) to (xb, yb).
+GL_HD void limb_sums(double xa, double ya, double xb, double yb, Sums& S)
+{
+    const double dl = atan2_d(xa * yb - ya * xb, xa * xb + ya * yb);
+    const double ra = rcp(xa * xa + ya * ya), rb = rcp(xb * xb + yb * yb);
+    // sin(4 lambda) = 4 x y (x^2 - y^2) / r^4
+    const double s4a = 4.0 * xa * ya * (xa * xa - ya * ya) * ra * ra;
+    const double s4b = 4.0 * xb * yb * (xb * xb - yb * yb) * rb * rb;
+    S.flat += 0.5 * dl;
+    S.lin += dl * (1.0 / 3.0);
+    S.quad += 0.25 * dl - (s4b - s4a) * (1.0 / 48.0);
+}
+
+// Arc between half-angle tangents ta -> tb (counter-clockwise in psi; passes
+// through psi = pi when tb < ta), described for the tau rule as a centre
+// direction (cc, sc) and h = tan(span/4); arcs longer than pi are split in two.
+struct TauArc {
+    double cc, sc, h;
+};
+
+GL_HD int arc_between(double ta, double tb, TauArc* out)
+{
+    const double Na = sqrt_nn(1.0 + ta * ta), Nb = sqrt_nn(1.0 + tb * tb);
+    const double sg = (tb > ta) ? 1.0 : -1.0;
+    // h = tan(span/4), centre psi_c = atan(ta) + atan(tb) (+ pi when wrapping)
+    const double h = sg * (tb - ta) / (Na * Nb + sg * (1.0 + ta * tb));
+    const double inv = sg / (Na * Nb);
+    const double cc = (1.0 - ta * tb) * inv, sc = (ta + tb) * inv;
+    if (h <= 1.0) {
+        out[0] = {cc, sc, h};
+        return 1;
+    }
+    const double q = sqrt_nn(1.0 + h * h);
+    const double r = rcp(q);
+    const double cq = r, sq = h * r;                  // quarter-span angle
+    const double h2 = h * rcp(1.0 + q);               // tan(span/8)
+    out[0] = {cc * cq + sc * sq, sc * cq - cc * sq, h2};
+    out[1] = {cc * cq - sc * sq, sc * cq + cc * sq, h2};
+    return 2;
+}
+
+GL_HD void point_at(const Frame& F, double t, double& x, double& y)
+{
+    const double t2 = t * t, inv = rcp(1.0 + t2);
+    const double cu = (1.0 - t2) * inv, su = 2.0 * t * inv;
+    x = F.x0 + F.Xc * cu + F.Xs * su;
+    y = F.y0 + F.Yc * cu + F.Ys * su;
+}
+
+// A local maximum of r^2 on the star whose nearby pair of complex zeros of
+// 1 - r^2 lies closer than this to the real th axis becomes a cluster point.
+constexpr double kSplitDist = 0.4;
+
+enum SampleClass : int { CLS_OUT = 0, CLS_FULL = 1, CLS_PARTIAL = 2 };
+
+// Lower bound on the distance from the real axis of any complex th with
+// |p(th)|^2 = 1 when the ellipse lies inside the disk: for th = a + i b,
+// p = u + i v with |u| <= rho + k cosh(b), so a zero needs cosh(b) >= (1 - rho)/k.
+GL_HD double zero_distance_bound(double rho, double k)
+{
+    const double r = (1.0 - rho) / k;
+    return r > 1.0 ? log(r + sqrt((r - 1.0) * (r + 1.0))) : 0.0;
+}
+
+// Occulted fraction delta for ellipse centre (x0, y0).
+template <class CT = NoCensus>
+GL_HD double occulted(const SetConst& s, double x0, double y0, int* cls_out, CT& ct)
+{
+    const double rho2 = x0 * x0 + y0 * y0;
+    const double kp = 1.0 + s.k;
+    if (rho2 >= kp * kp) {
+        if (cls_out) *cls_out = CLS_OUT;
+        return 0.0;
+    }
+    const double rho = sqrt_nn(rho2);
+    const double S_flat_whole = kPi * s.AC;
+    const double S_quad_whole = kPi * s.AC * (rho2 + 0.25 * s.M2);
+    // whole ellipse provably well inside: periodic trapezoid, order from the
+    // lower bound on the distance of the integrand's complex singularities
+    // cosh(d) >= (1 - rho)/k for every complex zero (zero_distance_bound)
+    const double cosh_bound = (1.0 - rho) * rcp(s.k);
+    const int oi_deep = trap_order_cosh(cosh_bound);
+    if (oi_deep >= 0) {
+        if (cls_out) *cls_out = CLS_FULL;
+        ct.trap(kTrapN[oi_deep]);
+        const double sl = trap_lin(s, x0, y0, oi_deep);
+        return (s.c0 * S_flat_whole + s.c1 * sl + s.c2 * S_quad_whole) * s.inv_phi;
+    }
+
+    // g(th) = |p(th)|^2 - 1 = K0 + K1 cos + K2 sin + K3 cos 2th + K4 sin 2th
+    const double K0 = rho2 - 1.0 + 0.5 * s.M2;
+    const double K1 = 2.0 * (x0 * s.A + y0 * s.B);
+    const double K2 = 2.0 * y0 * s.C;
+    const double nK2 = K1 * K1 + K2 * K2;
+    double cf = 1.0, sf = 0.0;  // direction of the far point th_far
+    if (nK2 > 1e-300) {
+        const double inv = rcp(sqrt_nn(nK2));
+        cf = K1 * inv;
+        sf = K2 * inv;
+    }
+    // anchor th0 so that t = +-inf (th = th0 + pi) is where |g| is largest
+    // among th_far + {0, pi/2, pi, 3pi/2}
+    double best_c = cf, best_s = sf, best_g = 0.0;
+    {
+        double cc = cf, ss = sf;
+        for (int i = 0; i < 4; ++i) {
+            const double c2 = cc * cc - ss * ss, s2 = 2.0 * cc * ss;
+            const double gv = K0 + K1 * cc + K2 * ss + s.K3 * c2 + s.K4 * s2;
+            if (fabs(gv) > fabs(best_g)) {
+                best_g = gv;
+                best_c = cc;
+                best_s = ss;
+            }
+            const double tmp = cc;
+            cc = -ss;
+            ss = tmp;
+        }
+    }
+    const double c0a = -best_c, s0a = -best_s;  // th0 = th_best + pi
+    // g(th0 + psi) = K0 + K1' cos psi + K2' sin psi + K3' cos 2psi + K4' sin 2psi
+    const double K1r = K1 * c0a + K2 * s0a;
+    const double K2r = -K1 * s0a + K2 * c0a;
+    const double c2a = c0a * c0a - s0a * s0a, s2a = 2.0 * c0a * s0a;
+    const double K3r = s.K3 * c2a + s.K4 * s2a;
+    const double K4r = -s.K3 * s2a + s.K4 * c2a;
+    // (1 + t^2)^2 g as a quartic in t = tan(psi/2)
+    Poly4 q;
+    q.a4 = K0 - K1r + K3r;
+    q.a3 = 2.0 * K2r - 4.0 * K4r;
+    q.a2 = 2.0 * K0 - 6.0 * K3r;
+    q.a1 = 2.0 * K2r + 4.0 * K4r;
+    q.a0 = K0 + K1r + K3r;
+    QuarticRoots R;
+    solve_quartic(q, R, ct);
+    const bool inf_inside = q.a4 < 0.0;
+
+    // local maxima of r^2 on the star: the nearby complex zeros of the quartic
+    // sit at t_c +- i sqrt(2|p|/|p''|), about 2 sqrt(2|p|/|p''|)/(1+t_c^2) in th
+    double tc[3];
+    int ntc = 0;
+    double t_near = 0.0, d_near = 1e300;
+    for (int i = 0; i < R.n_crit; ++i) {
+        const double t = R.c[i];
+        const double pv = p4(q, t), pp = ddp4(q, t);
+        if (pv < 0.0 && pp < 0.0) {
+            const double dth = 2.0 * sqrt_nn(2.0 * pv * rcp(pp)) * rcp(1.0 + t * t);
+            if (dth < d_near) {
+                d_near = dth;
+                t_near = t;
+            }
+            if (dth < kSplitDist) tc[ntc++] = t;
+        }
+    }
+
+    // break points of the boundary in t, ascending; kind 0 = root, 1 = cluster point
+    double bp[7];
+    int kind[7];
+    int nb = 0;
+    if (R.n_roots < 2) {
+        // no crossing: the whole ellipse is on the star or off it
+        if (!inf_inside) {
+            if (cls_out) *cls_out = CLS_OUT;
+            return 0.0;
+        }
+        if (cls_out) *cls_out = CLS_FULL;
+        if (ntc == 0) {
+            double sl;
+            int lev;
+            const bool ok = trap_lin_nested(s, x0, y0, sl, lev);
+            ct.trap(8 << (lev - 1));
+            if (ok) return (s.c0 * S_flat_whole + s.c1 * sl + s.c2 * S_quad_whole) * s.inv_phi;
+            tc[ntc++] = t_near;  // did not settle: cluster at the point nearest the limb
+        }
+        if (ntc == 1) {
+            // second break point diametrically opposite: psi + pi <-> -1/t
+            const double t = tc[0];
+            const double o = (t != 0.0) ? -1.0 / t : -1e16;
+            if (o < t) {
+                tc[1] = t;
+                tc[0] = o;
+            } else {
+                tc[1] = o;
+            }
+            ntc = 2;
+        }
+        for (int i = 0; i < ntc; ++i) {
+            bp[nb] = tc[i];
+            kind[nb++] = 1;
+        }
+    } else {
+        if (cls_out) *cls_out = CLS_PARTIAL;
+        int i = 0, j = 0;
+        while (i < R.n_roots || j < ntc) {
+            if (j >= ntc || (i < R.n_roots && R.r[i] <= tc[j])) {
+                bp[nb] = R.r[i++];
+                kind[nb++] = 0;
+            } else {
+                bp[nb] = tc[j++];
+                kind[nb++] = 1;
+            }
+        }
+    }
+
+    Frame F;
+    make_frame(s, x0, y0, c0a, s0a, F);
+    Sums S = {0.0, 0.0, 0.0};
+    for (int i = 0; i < nb; ++i) {
+        const int i1 = (i + 1 == nb) ? 0 : i + 1;
+        const double ta = bp[i], tb = bp[i1];
+        bool inside;
+        if (kind[i] == 1 || kind[i1] == 1) inside = true;  // cluster points lie on the star
+        else if (i1 != 0) inside = p4(q, 0.5 * (ta + tb)) < 0.0;
+        else inside = inf_inside;                         // the arc through t = inf
+        if (inside) {
+            TauArc arcs[2];
+            const int na = arc_between(ta, tb, arcs);
+            for (int k = 0; k < na; ++k) arc_gk(F, arcs[k].cc, arcs[k].sc, arcs[k].h, S, ct);
+        } else {
+            double xa, ya, xb, yb;
+            point_at(F, ta, xa, ya);
+            point_at(F, tb, xb, yb);
+            limb_sums(xa, ya, xb, yb, S);
+            ct.limb();
+        }
+    }
+    return (s.c0 * S.flat + s.c1 * S.lin + s.c2 * S.quad) * s.inv_phi;
+}
+
+// Planet centre at time t (eq. coord-map with a circular orbit); returns false
+// when the planet is behind the star or cannot touch the disk.
+GL_HD bool centre_at(const SetConst& s, double t, double& x0, double& y0)
+{
+    const double tau = phase_time(s, t);
+    const double alpha = s.w_orb * tau;
+    double sa, ca;
+    sincos_pi(alpha, sa, ca);
+    x0 = s.xb * ca;
+    y0 = s.d * sa;
+    return ca > 0.0;
+}
+
+// Relative flux of one instantaneous sub-sample.
+template <class CT = NoCensus>
+GL_HD double flux_instant(const SetConst& s, double t, int* cls_out, CT& ct)
+{
+    double x0, y0;
+    if (!centre_at(s, t, x0, y0)) {
+        if (cls_out) *cls_out = CLS_OUT;
+        return 1.0;
+    }
+    return 1.0 - occulted<CT>(s, x0, y0, cls_out, ct);
+}
+
+GL_HD double flux_instant(const SetConst& s, double t)
+{
+    NoCensus nc;
+    return flux_instant<NoCensus>(s, t, nullptr, nc);
+}
+
+// Algorithmic FP64 operation counts per unit of counted work (add, sub, mul,
+// divide, square root and library transcendental = 1, fused multiply-add = 2),
+// read off the source of this file; the census multiplies them by what a
+// launch really did.
+constexpr int kFlopSample = 40;     // in-window sub-sample: phase, orbit, classify
+constexpr int kFlopWhole = 30;      // whole-ellipse closed forms and singularity bound
+constexpr int kFlopPartial = 160;   // quartic set-up, frame, break points
+constexpr int kFlopIter = 18;       // one safeguarded-Newton step on the quartic or cubic
+constexpr int kFlopLimb = 30;       // one limb arc in closed form
+constexpr int kFlopTrapNode = 24;   // one trapezoid node (mu integrand + rotation)
+constexpr int kFlopGKPiece = 21 * 64 + 10;  // one 21-node Gauss-Kronrod piece
+
+}  // namespace gl

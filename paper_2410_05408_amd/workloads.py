@@ -173,3 +173,40 @@ def surrogate_samples(n: int, seed: int, window: float = 0.6):
 def by_name(name: str, **kw) -> Workload:
     return {"single_transit": single_transit, "walker_batch": walker_batch,
             "high_cadence": high_cadence, "uneven_batch": uneven_batch}[name](**kw)
+
+
+def adversarial_batch(n_dense: int = 3000) -> Workload:
+    """Hard shapes and grazing geometries, CSR layout.
+
+    Parameter sets: large and small k, extreme flattening with the spin axis
+    in the sky plane (flat ellipses whose flat side can run along the limb and
+    cross it four times), pole-on and f = 0 spheres, and impact parameters up
+    to grazing (b near 1 - k, 1, 1 + k/2).  Each set gets a uniform grid over
+    +-0.7 T14 plus a dense grid over the last 4% of the ingress side, so that
+    contacts and near-tangent configurations are sampled finely.  Exposures
+    and supersampling vary across sets.
+    """
+    rows = []
+    for k in (0.02, 0.12, 0.3, 0.5):
+        for f, theta in ((0.0, 1.0), (0.3, 0.0), (0.9, 0.5 * math.pi), (0.95, 1.3), (0.5, 2.2)):
+            for phi in (0.0, 0.25 * math.pi, 0.5 * math.pi, 2.0):
+                for b in (0.0, 1.0 - k, 1.0, 1.0 + 0.5 * k):
+                    rows.append((k, f, theta, phi, b))
+    n = len(rows)
+    p = np.empty((NPARAM, n))
+    rng = np.random.default_rng(99)
+    for s, (k, f, theta, phi, b) in enumerate(rows):
+        p[:, s] = (k, f, theta, phi, b, 20.0 + 30.0 * (s % 5), 50.0, 0.013 * (s % 3),
+                   rng.uniform(), rng.uniform())
+    t14 = full_duration(p[K], np.minimum(np.abs(p[B]), 1.0 + p[K] - 1e-9), p[ARS], p[P])
+    grids = []
+    for s in range(n):
+        t0, w = p[T0, s], t14[s]
+        g1 = np.linspace(t0 - 0.7 * w, t0 + 0.7 * w, n_dense)
+        g2 = np.linspace(t0 - 0.52 * w, t0 - 0.44 * w, n_dense // 3)
+        grids.append(np.sort(np.concatenate([g1, g2])))
+    offsets = np.zeros(n + 1, np.int64)
+    offsets[1:] = np.cumsum([len(g) for g in grids])
+    n_ss = np.array([(1, 5, 15, 3)[s % 4] for s in range(n)], np.int32)
+    t_exp = np.array([(0.0, 2e-3, 1e-2, 5e-4)[s % 4] for s in range(n)])
+    return Workload("adversarial", p, np.concatenate(grids), offsets, n_ss, t_exp, {})

@@ -1,0 +1,311 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+Bar: |gpu - oracle| <= 1e-9 on every compared point.  The oracle shares no
+code with the HIP library; both are fed from the seeded workload generator.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    c = gpu_lib.Context(0)
+    yield c
+    c.close()
+
+
+def run(gl, ctx, w, **kw):
+    import torch
+    d = gl.to_device(w, "cuda:0")
+    out = ctx.batch(d["params"], d["times"], offsets=d["offsets"], n_ss=d["n_ss"],
+                    t_exp=d["t_exp"], **kw)
+    torch.cuda.synchronize()
+    st = gl.gl_ctx_sync_status(ctx.handle)
+    res = out.cpu().numpy()
+    if w.offsets is None:
+        res = res.reshape(w.n_sets, -1)
+    return res, st
+
+
+def test_single_transit_all_points(gpu_lib, ctx):
+    from paper_2410_05408_amd import workloads as W
+    say("case: single transit, 1000 points")
+    w = W.single_transit()
+    got, st = run(gpu_lib, ctx, w)
+    assert st == gpu_lib.GL_OK
+    ref = np.loadtxt(os.path.join(HERE, "golden", "single_transit_oracle.txt"))[:, 1]
+    err = np.abs(got[0] - ref)
+    say(f"  max err {err.max():.3e}")
+    assert err.max() <= TOL
+    assert np.all(got[0][ref == 1.0] == 1.0)
+
+
+def test_walker_batch_small_all_points(gpu_lib, ctx, oracle):
+    from paper_2410_05408_amd import workloads as W
+    say("case: walker batch, 48 sets x 3000 times x 15 sub-samples, all points")
+    w = W.walker_batch(n_sets=48)
+    got, st = run(gpu_lib, ctx, w)
+    assert st == gpu_lib.GL_OK
+    ref = oracle.flux_batch(w.params, w.times, n_ss=w.n_ss, t_exp=w.t_exp)
+    err = np.abs(got - ref)
+    say(f"  max err {err.max():.3e}, in transit {np.sum(ref < 1)}")
+    assert err.max() <= TOL
+
+
+def test_walker_batch_full_size_sampled(gpu_lib, ctx, oracle):
+    from paper_2410_05408_amd import workloads as W
+    say("case: walker batch full size 4096 x 3000 x 15, stratified sample")
+    w = W.walker_batch()
+    got, st = run(gpu_lib, ctx, w)
+    assert st == gpu_lib.GL_OK
+    assert np.all((got >= 0.0) & (got <= 1.0))
+    rng = np.random.default_rng(0)
+    sets = rng.choice(w.n_sets, 24, replace=False)
+    ref = oracle.flux_batch(w.params[:, sets], w.times, n_ss=w.n_ss[sets], t_exp=w.t_exp[sets])
+    err = np.abs(got[sets] - ref)
+    say(f"  24 full sets: max err {err.max():.3e}")
+    assert err.max() <= TOL
+    # every output that changes, across all sets, in a random sample
+    changed = np.flatnonzero(got.ravel() < 1.0)
+    sel = rng.choice(changed, min(3000, changed.size), replace=False)
+    refs = oracle.flux_select(w.params, w.times, sel, n_ss=w.n_ss, t_exp=w.t_exp)
+    err2 = np.abs(got.ravel()[sel] - refs)
+    say(f"  3000 in-transit outputs: max err {err2.max():.3e}")
+    assert err2.max() <= TOL
+
+
+def test_high_cadence_all_points(gpu_lib, ctx, oracle):
+    from paper_2410_05408_amd import workloads as W
+    say("case: high cadence 512 x 65536, all 33.5M points")
+    w = W.high_cadence()
+    got, st = run(gpu_lib, ctx, w)
+    assert st == gpu_lib.GL_OK
+    ref = oracle.flux_batch(w.params, w.times, n_ss=w.n_ss, t_exp=w.t_exp)
+    err = np.abs(got - ref)
+    say(f"  max err {err.max():.3e}, points changed {np.sum(ref < 1)}")
+    assert err.max() <= TOL
+
+
+def test_uneven_batch_sampled(gpu_lib, ctx, oracle):
+    from paper_2410_05408_amd import workloads as W
+    say("case: uneven CSR batch 16384 walkers (71.4M outputs), sampled")
+    w = W.uneven_batch()
+    got, st = run(gpu_lib, ctx, w)
+    assert st == gpu_lib.GL_OK
+    assert np.all((got >= 0.0) & (got <= 1.0))
+    rng = np.random.default_rng(1)
+    sets = rng.choice(w.n_sets, 12, replace=False)
+    sel = np.concatenate([np.arange(w.offsets[s], w.offsets[s + 1]) for s in sets])
+    changed = np.flatnonzero(got < 1.0)
+    sel = np.concatenate([sel, rng.choice(changed, 3000, replace=False)])
+    ref = oracle.flux_select(w.params, w.times, sel, offsets=w.offsets, n_ss=w.n_ss, t_exp=w.t_exp)
+    err = np.abs(got[sel] - ref)
+    say(f"  {sel.size} outputs: max err {err.max():.3e}")
+    assert err.max() <= TOL
+
+
+def test_adversarial_all_points(gpu_lib, ctx, oracle):
+    from paper_2410_05408_amd import workloads as W
+    say("case: adversarial shapes and grazing geometries, all points")
+    w = W.adversarial_batch(600)
+    got, st = run(gpu_lib, ctx, w)
+    assert st == gpu_lib.GL_OK
+    ref = oracle.flux_batch(w.params, w.times, offsets=w.offsets, n_ss=w.n_ss, t_exp=w.t_exp)
+    err = np.abs(got - ref)
+    i = int(np.argmax(err))
+    s = int(np.searchsorted(w.offsets, i, side="right") - 1)
+    say(f"  max err {err.max():.3e} at set {s} params {w.params[:, s]} t {w.times[i]}")
+    assert err.max() <= TOL
+
+
+def _csr(params, grids, n_ss, t_exp):
+    from paper_2410_05408_amd import workloads as W
+    offsets = np.zeros(len(grids) + 1, np.int64)
+    offsets[1:] = np.cumsum([len(g) for g in grids])
+    times = np.concatenate(grids) if offsets[-1] else np.zeros(0)
+    return W.Workload("csr", np.ascontiguousarray(params), times, offsets,
+                      np.asarray(n_ss, np.int32), np.asarray(t_exp, float))
+
+
+def test_ragged_segments_and_extremes(gpu_lib, ctx, oracle):
+    from paper_2410_05408_amd import workloads as W
+    say("case: ragged CSR segments (0, 1, 63, 64, 65, 127, 200), n_ss up to 64")
+    base = W.walker_batch(n_sets=7).params
+    base[W.B] = 0.2
+    lens = [0, 1, 63, 64, 65, 127, 200]
+    grids = [np.linspace(-0.3, 0.3, n) for n in lens]
+    w = _csr(base, grids, [1, 64, 15, 5, 64, 2, 15], [0.0, 0.01, 0.02, 0.0, 0.03, 0.001, 0.0204])
+    got, st = run(gpu_lib, ctx, w)
+    assert st == gpu_lib.GL_OK
+    ref = oracle.flux_batch(w.params, w.times, offsets=w.offsets, n_ss=w.n_ss, t_exp=w.t_exp)
+    err = np.abs(got - ref)
+    say(f"  max err {err.max():.3e}")
+    assert err.max() <= TOL
+
+
+def test_several_transits_per_grid(gpu_lib, ctx, oracle):
+    from paper_2410_05408_amd import workloads as W
+    say("case: short period, grid spanning several transits and eclipses")
+    p = W.walker_batch(n_sets=16).params
+    p[W.P] = 3.0
+    p[W.ARS] = 8.0
+    p[W.T0] = 0.37
+    w = W.Workload("multi", p, np.linspace(-7.0, 7.0, 6000), None,
+                   np.full(16, 3, np.int32), np.full(16, 0.004), {})
+    got, st = run(gpu_lib, ctx, w)
+    assert st == gpu_lib.GL_OK
+    ref = oracle.flux_batch(w.params, w.times, n_ss=w.n_ss, t_exp=w.t_exp)
+    err = np.abs(got - ref)
+    say(f"  max err {err.max():.3e}, transits seen {np.sum(np.diff((ref[0] < 1).astype(int)) == 1)}")
+    assert err.max() <= TOL
+
+
+def test_shared_grid_of_one_time(gpu_lib, ctx, oracle):
+    from paper_2410_05408_amd import workloads as W
+    say("case: one time per set")
+    w = W.walker_batch(n_sets=300, n_times=1, n_ss=5)
+    w.times[:] = 0.01
+    got, st = run(gpu_lib, ctx, w)
+    ref = oracle.flux_batch(w.params, w.times, n_ss=w.n_ss, t_exp=w.t_exp)
+    assert st == gpu_lib.GL_OK and np.abs(got - ref).max() <= TOL
+
+
+def test_domain_errors_give_nan_and_status(gpu_lib, ctx, oracle):
+    from paper_2410_05408_amd import workloads as W
+    say("case: domain errors")
+    w = W.walker_batch(n_sets=8, n_times=200)
+    w.params[W.K, 1] = 0.0
+    w.params[W.F, 3] = 1.0
+    w.params[W.Q1, 5] = float("nan")
+    w.n_ss[6] = 0
+    got, st = run(gpu_lib, ctx, w)
+    assert st == gpu_lib.GL_ERR_DOMAIN
+    bad = [1, 3, 5, 6]
+    assert np.all(np.isnan(got[bad]))
+    good = [0, 2, 4, 7]
+    ref = oracle.flux_batch(w.params[:, good], w.times, n_ss=w.n_ss[good], t_exp=w.t_exp[good])
+    assert np.abs(got[good] - ref).max() <= TOL
+    # the flag is cleared by the read
+    w2 = W.walker_batch(n_sets=2, n_times=10)
+    _, st2 = run(gpu_lib, ctx, w2)
+    assert st2 == gpu_lib.GL_OK
+
+
+def test_bad_csr_offsets_are_reported(gpu_lib, ctx):
+    import torch
+    say("case: bad CSR offsets")
+    gl = gpu_lib
+    params = torch.tensor(np.tile([[0.1], [0.3], [1.0], [0.5], [0.2], [200.0], [500.0], [0.0],
+                                   [0.4], [0.3]], (1, 3)), device="cuda")
+    times = torch.linspace(-0.3, 0.3, 30, dtype=torch.float64, device="cuda")
+    out = torch.full((30,), -7.0, dtype=torch.float64, device="cuda")
+    offsets = torch.tensor([0, 20, 10, 30], dtype=torch.int64, device="cuda")
+    gl.gl_lightcurve_batch(ctx.handle, params, times, out, offsets=offsets)
+    torch.cuda.synchronize()
+    assert gl.gl_ctx_sync_status(ctx.handle) == gl.GL_ERR_DOMAIN
+    # the valid first and last segments are computed, nothing outside is written
+    o = out.cpu().numpy()
+    assert np.all(o[:20] <= 1.0) and np.all(o[20:30] <= 1.0)
+
+
+def test_host_checked_errors(gpu_lib, ctx):
+    import torch
+    gl = gpu_lib
+    L = gl.lib()
+    t = torch.zeros(4, dtype=torch.float64, device="cuda")
+    assert L.gl_lightcurve_batch(ctx.handle, None, 1, gl._ptr(t), None, 4, None, None,
+                                 gl._ptr(t), None) == gl.GL_ERR_NULL
+    assert L.gl_lightcurve_batch(ctx.handle, gl._ptr(t), 0, gl._ptr(t), None, 4, None, None,
+                                 gl._ptr(t), None) == gl.GL_ERR_SIZE
+    assert L.gl_lightcurve_batch(ctx.handle, gl._ptr(t), 1, gl._ptr(t), None, 0, None, None,
+                                 gl._ptr(t), None) == gl.GL_ERR_SIZE
+    assert "n_times" in gl.gl_ctx_last_error(ctx.handle)
+
+
+def test_deterministic_and_graph_equals_direct(gpu_lib, ctx):
+    import torch
+    from paper_2410_05408_amd import workloads as W
+    say("case: determinism, graph replay vs direct launch")
+    gl = gpu_lib
+    w = W.walker_batch(n_sets=256)
+    d = gl.to_device(w, "cuda:0")
+    outs = []
+    for graph in (True, True, True, False):
+        gl.gl_ctx_set_graph(ctx.handle, graph)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            o = ctx.batch(d["params"], d["times"], n_ss=d["n_ss"], t_exp=d["t_exp"])
+        s.synchronize()
+        outs.append(o.cpu().numpy())
+    gl.gl_ctx_set_graph(ctx.handle, True)
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_graph_replays_with_eager_work_between(gpu_lib, ctx):
+    import torch
+    from paper_2410_05408_amd import workloads as W
+    say("case: repeated graph replays on one stream with eager work between")
+    gl = gpu_lib
+    w = W.walker_batch(n_sets=128)
+    d = gl.to_device(w, "cuda:0")
+    s = torch.cuda.Stream()
+    out = torch.empty(w.n_out, dtype=torch.float64, device="cuda")
+    first = None
+    for r in range(5):
+        with torch.cuda.stream(s):
+            out.fill_(-1.0)
+            gl.gl_lightcurve_batch(ctx.handle, d["params"], d["times"], out, n_ss=d["n_ss"],
+                                   t_exp=d["t_exp"], stream=s)
+            junk = torch.randn(1000, device="cuda").sum()  # noqa: F841
+        s.synchronize()
+        cur = out.cpu().numpy()
+        if first is None:
+            first = cur
+        assert np.array_equal(cur, first), r
+
+
+def test_persistent_grid_sizes_agree(gpu_lib, ctx):
+    from paper_2410_05408_amd import workloads as W
+    say("case: persistent grid sizes give identical results")
+    gl = gpu_lib
+    w = W.walker_batch(n_sets=64)
+    res = []
+    for wpc in (1, 4, 32, 8):
+        gl.gl_ctx_set_plan(ctx.handle, wpc)
+        got, st = run(gl, ctx, w)
+        assert st == gl.GL_OK
+        res.append(got)
+    assert gl.gl_ctx_get_plan(ctx.handle) == 8
+    for r in res[1:]:
+        assert np.array_equal(r, res[0])
+
+
+def test_autotune_keeps_results(gpu_lib, ctx):
+    import torch
+    from paper_2410_05408_amd import workloads as W
+    say("case: autotune")
+    gl = gpu_lib
+    w = W.walker_batch(n_sets=512)
+    d = gl.to_device(w, "cuda:0")
+    before, _ = run(gl, ctx, w)
+    out = torch.empty(w.n_out, dtype=torch.float64, device="cuda")
+    gl.gl_autotune(ctx.handle, d["params"], d["times"], out, n_ss=d["n_ss"], t_exp=d["t_exp"])
+    wpc = gl.gl_ctx_get_plan(ctx.handle)
+    say(f"  tuned waves/CU {wpc}")
+    after, _ = run(gl, ctx, w)
+    assert np.array_equal(before, after)
