@@ -402,7 +402,7 @@ struct Sums {
 // Tolerances of the self-checking rules (absolute, on the integrals of 1 and
 // mu over the region; the flux error is at most about the same size).
 #ifndef GL_ARC_TOL
-#define GL_ARC_TOL 1e-7
+#define GL_ARC_TOL 1e-6
 #endif
 #ifndef GL_TRAP_TOL
 #define GL_TRAP_TOL 1e-8
@@ -651,40 +651,59 @@ constexpr double kSplitDist = 0.4;
 
 enum SampleClass : int { CLS_OUT = 0, CLS_FULL = 1, CLS_PARTIAL = 2 };
 
-// Lower bound on the distance from the real axis of any complex th with
-// |p(th)|^2 = 1 when the ellipse lies inside the disk: for th = a + i b,
-// p = u + i v with |u| <= rho + k cosh(b), so a zero needs cosh(b) >= (1 - rho)/k.
-GL_HD double zero_distance_bound(double rho, double k)
+// Lower bound on cosh(b) for any complex zero th = a + i b of |p(th)|^2 - 1
+// when the ellipse lies inside the disk.  With e(th) = cosh b e(a) + i sinh b e'(a),
+// p = u + i v where |u| <= rho + k cosh b and |v| >= kq sinh b (kq: minor
+// semi-axis); a zero needs |u|^2 - |v|^2 = 1, hence
+//   k^2 (1 - q^2) c^2 + 2 rho k c + rho^2 + (kq)^2 - 1 >= 0,  c = cosh b.
+// Returns the smallest such c (>= 1), or 1 when no bound applies.
+GL_HD double zero_cosh_bound(double rho2, double rho, double k, double kq)
 {
-    const double r = (1.0 - rho) / k;
-    return r > 1.0 ? log(r + sqrt((r - 1.0) * (r + 1.0))) : 0.0;
+    const double A = (k - kq) * (k + kq);
+    const double B = 2.0 * rho * k;
+    const double C = rho2 + kq * kq - 1.0;
+    if (C >= 0.0) return 1.0;
+    double c;
+    if (A > 1e-14 * k * k) c = (-B + sqrt_nn(B * B - 4.0 * A * C)) * rcp(2.0 * A);
+    else c = B > 0.0 ? -C * rcp(B) : 1e300;
+    return fmax(c, 1.0);
 }
 
-// Occulted fraction delta for ellipse centre (x0, y0).
+// Easy samples: the ellipse cannot touch the disk, or provably lies well
+// inside it (periodic trapezoid, order from the singularity bound).  Returns
+// true and the occulted fraction when the sample is easy.
 template <class CT = NoCensus>
-GL_HD double occulted(const SetConst& s, double x0, double y0, int* cls_out, CT& ct)
+GL_HD bool occulted_easy(const SetConst& s, double x0, double y0, double& delta, int* cls_out,
+                         CT& ct)
 {
     const double rho2 = x0 * x0 + y0 * y0;
     const double kp = 1.0 + s.k;
     if (rho2 >= kp * kp) {
         if (cls_out) *cls_out = CLS_OUT;
-        return 0.0;
+        delta = 0.0;
+        return true;
     }
     const double rho = sqrt_nn(rho2);
+    const double cosh_bound = zero_cosh_bound(rho2, rho, s.k, s.AC * rcp(s.k));
+    const int oi_deep = trap_order_cosh(cosh_bound);
+    if (oi_deep < 0) return false;
+    if (cls_out) *cls_out = CLS_FULL;
+    ct.trap(kTrapN[oi_deep]);
+    const double sl = trap_lin(s, x0, y0, oi_deep);
     const double S_flat_whole = kPi * s.AC;
     const double S_quad_whole = kPi * s.AC * (rho2 + 0.25 * s.M2);
-    // whole ellipse provably well inside: periodic trapezoid, order from the
-    // lower bound on the distance of the integrand's complex singularities
-    // cosh(d) >= (1 - rho)/k for every complex zero (zero_distance_bound)
-    const double cosh_bound = (1.0 - rho) * rcp(s.k);
-    const int oi_deep = trap_order_cosh(cosh_bound);
-    if (oi_deep >= 0) {
-        if (cls_out) *cls_out = CLS_FULL;
-        ct.trap(kTrapN[oi_deep]);
-        const double sl = trap_lin(s, x0, y0, oi_deep);
-        return (s.c0 * S_flat_whole + s.c1 * sl + s.c2 * S_quad_whole) * s.inv_phi;
-    }
+    delta = (s.c0 * S_flat_whole + s.c1 * sl + s.c2 * S_quad_whole) * s.inv_phi;
+    return true;
+}
 
+// Hard samples (everything occulted_easy declines): intersection quartic,
+// near-limb whole ellipses, limb and ellipse arcs.
+template <class CT = NoCensus>
+GL_HD double occulted_hard(const SetConst& s, double x0, double y0, int* cls_out, CT& ct)
+{
+    const double rho2 = x0 * x0 + y0 * y0;
+    const double S_flat_whole = kPi * s.AC;
+    const double S_quad_whole = kPi * s.AC * (rho2 + 0.25 * s.M2);
     // g(th) = |p(th)|^2 - 1 = K0 + K1 cos + K2 sin + K3 cos 2th + K4 sin 2th
     const double K0 = rho2 - 1.0 + 0.5 * s.M2;
     const double K1 = 2.0 * (x0 * s.A + y0 * s.B);
@@ -822,6 +841,15 @@ GL_HD double occulted(const SetConst& s, double x0, double y0, int* cls_out, CT&
         }
     }
     return (s.c0 * S.flat + s.c1 * S.lin + s.c2 * S.quad) * s.inv_phi;
+}
+
+// Occulted fraction delta for ellipse centre (x0, y0).
+template <class CT = NoCensus>
+GL_HD double occulted(const SetConst& s, double x0, double y0, int* cls_out, CT& ct)
+{
+    double d;
+    if (occulted_easy<CT>(s, x0, y0, d, cls_out, ct)) return d;
+    return occulted_hard<CT>(s, x0, y0, cls_out, ct);
 }
 
 // Planet centre at time t (eq. coord-map with a circular orbit); returns false

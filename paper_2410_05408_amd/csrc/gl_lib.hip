@@ -144,7 +144,7 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
 }
 
 __global__ void __launch_bounds__(256)
-k_fill(const double* __restrict__ times, int64_t n_sets, int shared_grid,
+k_fill(const double* __restrict__ times, int64_t n_sets, int shared_grid, int64_t cps,
        const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_begin,
        const int64_t* __restrict__ seg_len, const int64_t* __restrict__ chunk_off,
        Counters* __restrict__ ctr, unsigned long long* __restrict__ masks,
@@ -154,7 +154,7 @@ k_fill(const double* __restrict__ times, int64_t n_sets, int shared_grid,
     const int64_t c = uniform64((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     const int64_t total = (int64_t)ctr->total_chunks;
     if (c >= total) return;
-    const int64_t s = uniform64(set_of_chunk(chunk_off, n_sets, c));
+    const int64_t s = uniform64(shared_grid ? c / cps : set_of_chunk(chunk_off, n_sets, c));
     const int64_t lc = c - chunk_off[s];
     const int64_t pos = lc * kChunk + lane;  // position inside the set's segment
     const bool in_seg = pos < seg_len[s];
@@ -179,18 +179,92 @@ k_fill(const double* __restrict__ times, int64_t n_sets, int shared_grid,
     }
 }
 
+// Sub-samples of one chunk kept in LDS by the three-phase path (n_ss <= 16).
+constexpr int kMaxSubLds = kChunk * 16;
+
 template <bool CENSUS>
-__global__ void __launch_bounds__(64)
+struct Counter {
+    unsigned long long v[kCensus];
+    __device__ void add_sample(int cls, const gl::Census& ct)
+    {
+        if (!CENSUS) return;
+        v[0] += 1;
+        v[cls == gl::CLS_FULL ? 1 : (cls == gl::CLS_PARTIAL ? 2 : 3)] += 1;
+        v[4] += ct.trap_nodes;
+        v[5] += ct.arcs;
+        v[6] += ct.iters;
+        v[7] += ct.limbs;
+    }
+};
+
+// Instantaneous flux, easy part only: returns false (and leaves F) when the
+// sample needs the intersection machinery.
+template <bool CENSUS>
+__device__ __attribute__((noinline)) bool flux_easy(const gl::SetConst& S, double t, double& F,
+                                          Counter<CENSUS>& cnt)
+{
+    double x0, y0;
+    gl::Census ct;
+    int cls = gl::CLS_OUT;
+    if (!gl::centre_at(S, t, x0, y0)) {
+        F = 1.0;
+        cnt.add_sample(gl::CLS_OUT, ct);
+        return true;
+    }
+    double d;
+    bool easy;
+    if (CENSUS) easy = gl::occulted_easy<gl::Census>(S, x0, y0, d, &cls, ct);
+    else {
+        gl::NoCensus nc;
+        easy = gl::occulted_easy<gl::NoCensus>(S, x0, y0, d, nullptr, nc);
+    }
+    if (easy) {
+        F = 1.0 - d;
+        cnt.add_sample(cls, ct);
+    }
+    return easy;
+}
+
+template <bool CENSUS>
+__device__ __attribute__((noinline)) double flux_hard(const gl::SetConst& S, double t, Counter<CENSUS>& cnt)
+{
+    double x0, y0;
+    (void)gl::centre_at(S, t, x0, y0);
+    if (CENSUS) {
+        gl::Census ct;
+        int cls = gl::CLS_OUT;
+        const double d = gl::occulted_hard<gl::Census>(S, x0, y0, &cls, ct);
+        cnt.add_sample(cls, ct);
+        return 1.0 - d;
+    }
+    gl::NoCensus nc;
+    return 1.0 - gl::occulted_hard<gl::NoCensus>(S, x0, y0, nullptr, nc);
+}
+
+// Occupancy target of the compute kernel (waves per SIMD; 0 = compiler's choice).
+#ifndef GL_COMPUTE_WAVES_PER_EU
+#define GL_COMPUTE_WAVES_PER_EU 0
+#endif
+#if GL_COMPUTE_WAVES_PER_EU > 0
+#define GL_COMPUTE_ATTR __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GL_COMPUTE_WAVES_PER_EU)))
+#else
+#define GL_COMPUTE_ATTR __launch_bounds__(64)
+#endif
+
+template <bool CENSUS>
+__global__ void GL_COMPUTE_ATTR
 k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst* __restrict__ sc,
           const int64_t* __restrict__ seg_begin, const int64_t* __restrict__ chunk_off,
           Counters* __restrict__ ctr, const unsigned long long* __restrict__ masks,
           const int* __restrict__ chunk_set, double* __restrict__ out)
 {
-    __shared__ double lds_f[kChunk];
-    __shared__ int lds_idx[kChunk];
+    __shared__ double lds_f[kMaxSubLds];   // sub-sample fluxes of the chunk
+    __shared__ short lds_def[kMaxSubLds];  // deferred (hard) sub-samples
+    __shared__ int lds_idx[kChunk];        // chunk lanes with work, compacted
     const int lane = threadIdx.x;
     const int64_t total = (int64_t)ctr->total_chunks;
-    unsigned long long cnt[kCensus] = {0, 0, 0, 0, 0, 0, 0, 0};
+    Counter<CENSUS> cnt;
+    for (int i = 0; i < kCensus; ++i) cnt.v[i] = 0ull;
     for (;;) {
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(&ctr->head, (unsigned long long)kChunk);
@@ -214,45 +288,75 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
             __syncthreads();
             const int n_in = __popcll(M);
             const int nss = S.n_ss;
-            const int opw = kChunk / nss;
-            const int lo = lane / nss, j = lane - lo * nss;
-            const double frac = ((double)j + 0.5) / (double)nss - 0.5;
-            for (int g = 0; g < n_in; g += opw) {
-                const int o = g + lo;
-                const bool act = (lo < opw) && (o < n_in);
-                double F = 1.0;
-                int off = 0;
-                if (act) {
-                    off = lds_idx[o];
-                    const double t = times[tb + off] + frac * S.t_exp;
-                    if (CENSUS) {
-                        gl::Census ct;
-                        int cls = gl::CLS_OUT;
-                        F = gl::flux_instant<gl::Census>(S, t, &cls, ct);
-                        cnt[0] += 1;
-                        cnt[cls == gl::CLS_FULL ? 1 : (cls == gl::CLS_PARTIAL ? 2 : 3)] += 1;
-                        cnt[4] += ct.trap_nodes;
-                        cnt[5] += ct.arcs;
-                        cnt[6] += ct.iters;
-                        cnt[7] += ct.limbs;
-                    } else {
-                        F = gl::flux_instant(S, t);
+            const double inv_nss = 1.0 / (double)nss;
+            if (nss <= 16) {
+                // phase 1: easy sub-samples now, hard ones into the deferred list
+                const int N = n_in * nss;
+                int ndef = 0;
+                for (int f0 = 0; f0 < N; f0 += kChunk) {
+                    const int f = f0 + lane;
+                    bool hard = false;
+                    if (f < N) {
+                        const int o = f / nss, j = f - o * nss;
+                        const double t = times[tb + lds_idx[o]] + (((double)j + 0.5) * inv_nss - 0.5) * S.t_exp;
+                        double F = 1.0;
+                        hard = !flux_easy<CENSUS>(S, t, F, cnt);
+                        if (!hard) lds_f[f] = F;
+                    }
+                    const unsigned long long hm = __ballot(hard);
+                    if (hard) lds_def[ndef + __popcll(hm & ((1ull << lane) - 1ull))] = (short)f;
+                    ndef += __popcll(hm);
+                }
+                __syncthreads();
+                // phase 2: hard sub-samples, 64 at a time
+                for (int k0 = 0; k0 < ndef; k0 += kChunk) {
+                    const int k = k0 + lane;
+                    if (k < ndef) {
+                        const int f = lds_def[k];
+                        const int o = f / nss, j = f - o * nss;
+                        const double t = times[tb + lds_idx[o]] + (((double)j + 0.5) * inv_nss - 0.5) * S.t_exp;
+                        lds_f[f] = flux_hard<CENSUS>(S, t, cnt);
                     }
                 }
-                lds_f[lane] = F;
                 __syncthreads();
-                if (act && j == 0) {
+                // phase 3: box average per output, sub-samples in order
+                for (int o = lane; o < n_in; o += kChunk) {
                     double sum = 0.0;
-                    for (int jj = 0; jj < nss; ++jj) sum += lds_f[lane + jj];
-                    out[i0 + off] = sum / (double)nss;
+                    for (int jj = 0; jj < nss; ++jj) sum += lds_f[o * nss + jj];
+                    out[i0 + lds_idx[o]] = sum / (double)nss;
                 }
                 __syncthreads();
+            } else {
+                // long exposures (n_ss > 16): lanes take (output, sub-sample)
+                // pairs, averaged through LDS
+                const int opw = kChunk / nss;
+                const int lo = lane / nss, j = lane - lo * nss;
+                const double frac = ((double)j + 0.5) * inv_nss - 0.5;
+                for (int g = 0; g < n_in; g += opw) {
+                    const int o = g + lo;
+                    const bool act = (lo < opw) && (o < n_in);
+                    double F = 1.0;
+                    int off = 0;
+                    if (act) {
+                        off = lds_idx[o];
+                        const double t = times[tb + off] + frac * S.t_exp;
+                        if (!flux_easy<CENSUS>(S, t, F, cnt)) F = flux_hard<CENSUS>(S, t, cnt);
+                    }
+                    lds_f[lane] = F;
+                    __syncthreads();
+                    if (act && j == 0) {
+                        double sum = 0.0;
+                        for (int jj = 0; jj < nss; ++jj) sum += lds_f[lane + jj];
+                        out[i0 + off] = sum / (double)nss;
+                    }
+                    __syncthreads();
+                }
             }
         }
     }
     if (CENSUS) {
         for (int i = 0; i < kCensus; ++i) {
-            unsigned long long v = cnt[i];
+            unsigned long long v = cnt.v[i];
             for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
             if (lane == 0) atomicAdd(&ctr->census[i], v);
         }
@@ -439,8 +543,9 @@ gl_status enqueue(gl_ctx* ctx, const Batch& b, bool census = false)
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, b.stream, ctx->chunk_off, b.n_sets,
                        b.max_chunks, ctx->ctr);
     const int64_t fill_blocks = (b.max_chunks + 3) / 4;
+    const int64_t cps = shared ? (b.n_times + kChunk - 1) / kChunk : 0;
     hipLaunchKernelGGL(k_fill, dim3((unsigned)fill_blocks), dim3(256), 0, b.stream, b.times,
-                       b.n_sets, shared, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off,
+                       b.n_sets, shared, cps, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off,
                        ctx->ctr, ctx->masks, ctx->chunk_set, b.out);
     const int64_t want = (int64_t)ctx->n_cu * ctx->waves_per_cu;
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(want, (b.max_chunks + kChunk - 1) / kChunk * 4 + 1));

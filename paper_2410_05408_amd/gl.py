@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libgl_hip.so")
+LIB_PATH = os.environ.get("GL_LIB", os.path.join(_PKG, "libgl_hip.so"))
 
 GL_OK, GL_ERR_NULL, GL_ERR_SIZE, GL_ERR_DOMAIN = 0, -1, -2, -3
 GL_ERR_DEVICE, GL_ERR_STATE, GL_ERR_NOMEM = -4, -5, -6
