@@ -52,12 +52,63 @@ def cpu_baseline(w, gpu_out, target_s=10.0):
             "max_abs_err_gpu_vs_oracle": err}
 
 
+def surrogate_leg(ctx, d, exact_out, exact_ms, n_out, args):
+    """Config-5 style: train on samples from the exact kernels, calibrate,
+    evaluate the walker batch with exact fallback at 1 ppm."""
+    import torch
+
+    from paper_2410_05408_amd import surrogate as S
+    t0 = time.perf_counter()
+    train = S.Samples(ctx, args.sur_train, seed=5)
+    cal = S.Samples(ctx, args.sur_cal, seed=6)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    sur = S.Surrogate(ctx, max_batch=8192, seed=0)
+    t0 = time.perf_counter()
+    hist = sur.train(train, epochs=args.sur_epochs, log=log)
+    t_train = time.perf_counter() - t0
+    sur.calibrate(cal)
+    zero = S.Surrogate(ctx, max_batch=8192, zero=True)
+    zero.calibrate(cal)
+    del train, cal
+    out = torch.empty_like(exact_out)
+    sur.lightcurve(d, out)  # warm-up
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        n_sub, n_fb = sur.lightcurve(d, out)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    err = float((out - exact_out).abs().max().item())
+    out_z = torch.empty_like(exact_out)
+    n_sub_z, n_fb_z = zero.lightcurve(d, out_z)
+    torch.cuda.synchronize()
+    err_z = float((out_z - exact_out).abs().max().item())
+    res = {"value": n_out / (ms * 1e-3), "unit": "points/s", "ms_per_step": ms,
+           "speedup_vs_exact": exact_ms / ms, "tol": 1e-6, "max_abs_err_vs_exact": err,
+           "sub_samples_in_window": n_sub, "fallback_sub_samples": n_fb,
+           "fallback_fraction": n_fb / max(1, n_sub),
+           "zero_residual_predictor": {"fallback_fraction": n_fb_z / max(1, n_sub_z),
+                                       "max_abs_err_vs_exact": err_z},
+           "train_samples": args.sur_train, "calibration_samples": args.sur_cal,
+           "epochs": args.sur_epochs, "train_mse_first_last": [hist[0], hist[-1]],
+           "data_s": t_data, "train_s": t_train, "dtype": "bf16 mfma / f32 acc + f64"}
+    sur.close()
+    zero.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--sur-train", type=int, default=20_000_000)
+    ap.add_argument("--sur-cal", type=int, default=1_000_000)
+    ap.add_argument("--sur-epochs", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the exact path "
@@ -146,6 +197,9 @@ def main():
         "plan": {"waves_per_cu": wpc},
         "census": census,
     }
+    if not args.no_surrogate:
+        log("surrogate leg: data, training, calibration, gated evaluation")
+        res["surrogate"] = surrogate_leg(ctx, d, out, ms_per_step, w.n_out, args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on the host cores)")
         res["cpu_baseline"] = cpu_baseline(w, got)

@@ -147,6 +147,91 @@ gl_status gl_census(gl_ctx *ctx, const double *params, int64_t n_sets, const dou
  * per_item[8] (host memory) lines up with the census counts. */
 gl_status gl_flop_model(int64_t *per_item);
 
+/* ---------------------------------------------------------------------------
+ * Residual surrogate network: x[16] -> [Linear -> GELU] x 4 (width 256) -> Linear.
+ * BF16 matrix-core GEMMs with FP32 accumulation; FP32 master weights, biases,
+ * output layer, loss and Adam.  Packed FP32 parameter layout:
+ * W0[16][256] b0[256] W1[256][256] b1[256] W2 b2 W3 b3 w4[256] b4[1]
+ * (W_l[in][out]), gl_mlp_num_params() values.  GELU is the tanh form
+ * z/2 (1 + tanh(sqrt(2/pi)(z + 0.044715 z^3))); the loss is the mean squared
+ * error.  A network is used by one host thread at a time.
+ * ------------------------------------------------------------------------- */
+#define GL_MLP_DIN 16
+#define GL_MLP_WIDTH 256
+typedef struct gl_mlp gl_mlp;
+
+int gl_mlp_num_params(void);
+
+/* Allocates a network (zero weights) for batches of up to max_batch rows
+ * (a multiple of 64 in [64, 4194304]) on HIP device `device`. */
+gl_status gl_mlp_create(gl_mlp **mlp, int device, int max_batch);
+void gl_mlp_destroy(gl_mlp *mlp);
+const char *gl_mlp_last_error(const gl_mlp *mlp);
+
+/* Host FP32 packed parameters in/out (n must equal gl_mlp_num_params()).
+ * Setting weights resets the Adam state and step count.  Synchronous. */
+gl_status gl_mlp_set_weights(gl_mlp *mlp, const float *host_params, int64_t n);
+gl_status gl_mlp_get_weights(const gl_mlp *mlp, float *host_params, int64_t n);
+
+/* y[n] = network(x[n][16]); x, y device FP32; enqueued on stream. */
+gl_status gl_mlp_forward(gl_mlp *mlp, const float *x, int64_t n, float *y, void *stream);
+
+/* Gradients of the mean squared error against targets t[n] (device) for one
+ * batch (n <= max_batch) into host_grads (packed layout), and the loss into
+ * *host_loss (may be NULL).  Synchronises stream; weights unchanged. */
+gl_status gl_mlp_grads(gl_mlp *mlp, const float *x, const float *t, int64_t n, float *host_grads,
+                       float *host_loss, void *stream);
+
+/* One Adam step (b1 0.9, b2 0.999, eps 1e-8, learning rate lr) on a batch;
+ * loss_dev (device float, may be NULL) receives the batch's sum of squared
+ * residuals.  Enqueued on stream. */
+gl_status gl_mlp_train_step(gl_mlp *mlp, const float *x, const float *t, int64_t n, float lr,
+                            float *loss_dev, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned surrogate with exact fallback.  The network predicts the
+ * oblate-minus-equal-area-sphere residual r = F_oblate - F_sphere(k sqrt(q)),
+ * scaled by k^2 (1 - q); the sphere of the same projected area is the paper's
+ * comparison body for oblate transits (Section 2.1).  Inputs are the nine
+ * quantities (k, f, theta, phi, b, a/R*, u1, u2, phase), encoded through the
+ * symmetries of the occultation (it depends on them only through k, q, the
+ * centre distance, the angle between the projected spin axis and the radial
+ * direction mod pi, u1 and u2) into GL_MLP_DIN features.
+ * ------------------------------------------------------------------------- */
+
+/* Training / calibration samples, one per parameter set: params device SoA
+ * double[GL_NPARAM][n], times device double[n].  Writes (device) feat
+ * float[n][GL_MLP_DIN], target float[n] (scaled residual, 0 off the star),
+ * and, when non-NULL, f_obl / f_sph double[n] (exact fluxes from the same
+ * kernels as gl_lightcurve_batch), scale double[n] and bin int32[n] (-1 off
+ * the star). */
+gl_status gl_surrogate_samples(gl_ctx *ctx, const double *params, const double *times, int64_t n,
+                               float *feat, float *target, double *f_obl, double *f_sph,
+                               double *scale, int32_t *bin, void *stream);
+
+/* Number of calibration bins of the error-bound table. */
+int gl_surrogate_num_bins(void);
+
+/* Calibration: table[bin] = max(table[bin], |(pred - target) * scale|) over the
+ * n samples (device arrays; table float[gl_surrogate_num_bins()], start from
+ * zeros).  A bin never seen keeps 0 and must be marked unusable by the caller
+ * (negative entries always fall back). */
+gl_status gl_surrogate_bound(gl_ctx *ctx, const float *pred, const float *target, const double *scale,
+                             const int32_t *bin, int64_t n, float *table, void *stream);
+
+/* Light curves through the surrogate: same batch arguments and output as
+ * gl_lightcurve_batch.  Every in-window sub-sample on the star gets
+ * F = F_sphere + scale * network(features) when safety * table[bin] <= tol,
+ * and the exact kernel's value otherwise; outputs are box-averaged in order.
+ * Synchronous (it sizes its buffers from the device); *n_sub_out and
+ * *n_fallback_out (host, may be NULL) receive the number of in-window
+ * sub-samples and of those computed exactly. */
+gl_status gl_lightcurve_batch_surrogate(gl_ctx *ctx, gl_mlp *mlp, const float *table, double safety,
+                                        double tol, const double *params, int64_t n_sets,
+                                        const double *times, const int64_t *offsets, int64_t n_times,
+                                        const int32_t *n_ss, const double *t_exp, double *out,
+                                        void *stream, int64_t *n_sub_out, int64_t *n_fallback_out);
+
 /* Library version, e.g. "0.1.0". */
 const char *gl_version(void);
 

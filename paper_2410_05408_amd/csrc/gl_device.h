@@ -58,6 +58,7 @@ struct SetConst {
     double c0, c1, c2;     // I = c0 + c1 mu + c2 r^2
     double inv_phi;        // 1 / Phi
     double t_exp;          // exposure (days)
+    double sx, sy;         // unit vector of the projected spin axis (minor axis direction)
     int n_ss;              // midpoint sub-samples per output
     int valid;             // 0: domain error, outputs are NaN
 };
@@ -202,6 +203,8 @@ GL_HD bool make_set_const(const double* p, double t_exp, int n_ss, SetConst& s)
     s.t_exp = t_exp;
     if (!ok) return false;
     projected_ellipse(k, f, theta, phi, s.A, s.B, s.C);
+    s.sx = cos(phi);
+    s.sy = -sin(phi);
     s.AC = s.A * s.C;
     s.M2 = s.A * s.A + s.B * s.B + s.C * s.C;
     s.K3 = 0.5 * (s.A * s.A + s.B * s.B - s.C * s.C);
@@ -894,5 +897,57 @@ constexpr int kFlopIter = 18;       // one safeguarded-Newton step on the quarti
 constexpr int kFlopLimb = 30;       // one limb arc in closed form
 constexpr int kFlopTrapNode = 24;   // one trapezoid node (mu integrand + rotation)
 constexpr int kFlopGKPiece = 21 * 64 + 10;  // one 21-node Gauss-Kronrod piece
+
+// ---------------------------------------------------------------- surrogate helpers
+// The equal-projected-area sphere: a circle of radius k sqrt(q) at the same
+// centre (the oblate-minus-spherical residual of the surrogate is taken
+// against it).
+GL_HD SetConst sphere_of(const SetConst& s)
+{
+    SetConst c = s;
+    const double r = sqrt_nn(s.AC);  // k^2 q = dx dy2
+    c.A = r;
+    c.B = 0.0;
+    c.C = r;
+    c.AC = s.AC;
+    c.M2 = 2.0 * s.AC;
+    c.K3 = 0.0;
+    c.K4 = 0.0;
+    c.k = r;
+    return c;
+}
+
+constexpr int kSurFeat = 16;   // encoded features (zero-padded)
+constexpr int kSurBinsRho = 24;
+constexpr int kSurBinsQ = 8;
+constexpr int kSurBins = kSurBinsRho * kSurBinsQ;
+
+// Encodes one sample.  The instantaneous occultation depends on the nine
+// inputs (k, f, theta, phi, b, a/R*, u1, u2, phase) only through k, the
+// projected axis ratio q, the centre distance rho, the angle between the
+// projected spin axis and the radial direction (mod pi; the flux is even in
+// it) and u1, u2.  Writes the features, the residual scale k^2 (1 - q) and
+// the calibration bin; returns false when the ellipse cannot touch the disk.
+GL_HD bool sur_encode(const SetConst& s, double x0, double y0, float* feat, double& scale, int& bin)
+{
+    const double rho2 = x0 * x0 + y0 * y0, rho = sqrt_nn(rho2);
+    const double k = s.k, q = s.AC / (k * k);
+    if (rho >= 1.0 + k) return false;
+    const double cd = rho > 0.0 ? (s.sx * x0 + s.sy * y0) / rho : 1.0;
+    const double c2d = 2.0 * cd * cd - 1.0;
+    const double u2 = s.c2, u1 = s.c1 - 2.0 * s.c2;
+    const double z = fmin(fmax((rho - 1.0) / k, -6.0), 1.2);  // limb distance in planet radii
+    const double f[kSurFeat] = {(k - 0.085) / 0.035, 2.0 * q - 1.0, z / 3.0, rho, c2d,
+                                u1, u2, 1.0 - q, c2d * (1.0 - q), z * z / 9.0,
+                                0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < kSurFeat; ++i) feat[i] = (float)f[i];
+    scale = k * k * (1.0 - q) + 1e-30;
+    int br = (int)((z + 6.0) / 7.2 * kSurBinsRho);
+    br = br < 0 ? 0 : (br >= kSurBinsRho ? kSurBinsRho - 1 : br);
+    int bq = (int)((1.0 - q) * kSurBinsQ);
+    bq = bq < 0 ? 0 : (bq >= kSurBinsQ ? kSurBinsQ - 1 : bq);
+    bin = br * kSurBinsQ + bq;
+    return true;
+}
 
 }  // namespace gl

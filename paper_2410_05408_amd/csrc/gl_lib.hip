@@ -124,6 +124,8 @@ k_scan(int64_t* __restrict__ chunk_off, int64_t n, int64_t max_chunks, Counters*
     }
 }
 
+__global__ void k_reset_head(Counters* __restrict__ ctr) { ctr->head = 0ull; }
+
 __device__ __forceinline__ int64_t set_of_chunk(const int64_t* __restrict__ chunk_off,
                                                 int64_t n_sets, int64_t c)
 {
@@ -289,6 +291,8 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
             const int n_in = __popcll(M);
             const int nss = S.n_ss;
             const double inv_nss = 1.0 / (double)nss;
+            // f / nss for f < 1024, nss <= 16 from an exact float product
+            const float inv_nss_f = 1.0f / (float)nss;
             if (nss <= 16) {
                 // phase 1: easy sub-samples now, hard ones into the deferred list
                 const int N = n_in * nss;
@@ -297,7 +301,7 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
                     const int f = f0 + lane;
                     bool hard = false;
                     if (f < N) {
-                        const int o = f / nss, j = f - o * nss;
+                        const int o = (int)(((float)f + 0.5f) * inv_nss_f), j = f - o * nss;
                         const double t = times[tb + lds_idx[o]] + (((double)j + 0.5) * inv_nss - 0.5) * S.t_exp;
                         double F = 1.0;
                         hard = !flux_easy<CENSUS>(S, t, F, cnt);
@@ -313,7 +317,7 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
                     const int k = k0 + lane;
                     if (k < ndef) {
                         const int f = lds_def[k];
-                        const int o = f / nss, j = f - o * nss;
+                        const int o = (int)(((float)f + 0.5f) * inv_nss_f), j = f - o * nss;
                         const double t = times[tb + lds_idx[o]] + (((double)j + 0.5) * inv_nss - 0.5) * S.t_exp;
                         lds_f[f] = flux_hard<CENSUS>(S, t, cnt);
                     }
@@ -403,6 +407,19 @@ struct gl_ctx {
         void* ws;
     } key{};
     bool have_graph = false;
+    // surrogate path buffers (grown on demand)
+    int64_t* chunk_sub = nullptr;  // sub-sample offset per chunk (+1 total)
+    int64_t cap_sub_chunks = 0;
+    float* s_feat = nullptr;
+    float* s_pred = nullptr;
+    double* s_fsph = nullptr;
+    double* s_scale = nullptr;
+    double* s_t = nullptr;
+    double* s_F = nullptr;
+    int* s_bin = nullptr;
+    int* s_set = nullptr;
+    int64_t* s_fb = nullptr;
+    int64_t cap_sub = 0;
     // per-launch timing (events around the compute kernel and the pipeline)
     int t_slots = 0, t_used = 0;
     hipEvent_t* ev = nullptr;  // 3 events per slot: pipeline start, compute start, end
@@ -437,8 +454,22 @@ void drop_graph(gl_ctx* ctx)
     ctx->have_graph = false;
 }
 
+void free_sur(gl_ctx* ctx)
+{
+    void* b[] = {ctx->chunk_sub, ctx->s_feat, ctx->s_pred, ctx->s_fsph, ctx->s_scale, ctx->s_t,
+                 ctx->s_F,       ctx->s_bin,  ctx->s_set,  ctx->s_fb};
+    for (void* p : b) (void)hipFree(p);
+    ctx->chunk_sub = nullptr;
+    ctx->s_feat = ctx->s_pred = nullptr;
+    ctx->s_fsph = ctx->s_scale = ctx->s_t = ctx->s_F = nullptr;
+    ctx->s_bin = ctx->s_set = nullptr;
+    ctx->s_fb = nullptr;
+    ctx->cap_sub_chunks = ctx->cap_sub = 0;
+}
+
 void free_ws(gl_ctx* ctx)
 {
+    free_sur(ctx);
     (void)hipFree(ctx->sc);
     (void)hipFree(ctx->seg_begin);
     (void)hipFree(ctx->seg_len);
@@ -832,6 +863,344 @@ gl_status gl_flop_model(int64_t* per_item)
     per_item[5] = gl::kFlopGKPiece;
     per_item[6] = gl::kFlopIter;
     per_item[7] = gl::kFlopLimb;
+    return GL_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- surrogate path
+namespace {
+
+// One sample per parameter set: features, scaled residual target
+// (F_oblate - F_sphere) / scale, both fluxes, the scale and the bin.
+__global__ void k_sur_samples(const double* __restrict__ params, int64_t n, const double* __restrict__ times,
+                              float* __restrict__ feat, float* __restrict__ target, double* __restrict__ f_obl,
+                              double* __restrict__ f_sph, double* __restrict__ scale_out,
+                              int* __restrict__ bin_out, Counters* __restrict__ ctr)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double p[GL_NPARAM];
+    for (int r = 0; r < GL_NPARAM; ++r) p[r] = params[(int64_t)r * n + i];
+    gl::SetConst S;
+    float fe[gl::kSurFeat];
+    for (int r = 0; r < gl::kSurFeat; ++r) fe[r] = 0.f;
+    double Fo = 1.0, Fs = 1.0, sc = 0.0;
+    int bin = -1;
+    if (!gl::make_set_const(p, 0.0, 1, S) || !gl::finite_d(times[i])) {
+        atomicOr(&ctr->status, 1u);
+        Fo = Fs = __builtin_nan("");
+    } else {
+        double x0, y0;
+        if (gl::centre_at(S, times[i], x0, y0) && gl::sur_encode(S, x0, y0, fe, sc, bin)) {
+            gl::NoCensus nc;
+            Fo = 1.0 - gl::occulted<gl::NoCensus>(S, x0, y0, nullptr, nc);
+            const gl::SetConst C = gl::sphere_of(S);
+            Fs = 1.0 - gl::occulted<gl::NoCensus>(C, x0, y0, nullptr, nc);
+        }
+    }
+    for (int r = 0; r < gl::kSurFeat; ++r) feat[i * gl::kSurFeat + r] = fe[r];
+    target[i] = bin >= 0 ? (float)((Fo - Fs) / sc) : 0.f;
+    if (f_obl) f_obl[i] = Fo;
+    if (f_sph) f_sph[i] = Fs;
+    if (scale_out) scale_out[i] = sc;
+    if (bin_out) bin_out[i] = bin;
+}
+
+// table[bin] = max over samples of |(pred - target) * scale| (non-negative
+// floats order like their bit patterns, so an integer max is exact)
+__global__ void k_sur_bound(const float* __restrict__ pred, const float* __restrict__ target,
+                            const double* __restrict__ scale, const int* __restrict__ bin, int64_t n,
+                            float* __restrict__ table)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || bin[i] < 0) return;
+    const float e = (float)(fabs((double)pred[i] - (double)target[i]) * scale[i]);
+    atomicMax((unsigned int*)&table[bin[i]], __float_as_uint(e));
+}
+
+// sub-sample count per chunk: popcount(mask) * n_ss
+__global__ void k_sub_count(const unsigned long long* __restrict__ masks, const int* __restrict__ chunk_set,
+                            const gl::SetConst* __restrict__ sc, const Counters* __restrict__ ctr,
+                            int64_t* __restrict__ cnt)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (int64_t)ctr->total_chunks) return;
+    const unsigned long long m = masks[c];
+    cnt[c] = m ? (int64_t)__popcll(m) * sc[chunk_set[c]].n_ss : 0;
+}
+
+// exclusive scan of a[0..n) in place with a[n] = total, one workgroup
+__global__ void __launch_bounds__(kScanThreads) k_scan_n(int64_t* __restrict__ a, const Counters* __restrict__ ctr)
+{
+    __shared__ int64_t part[kScanThreads];
+    const int64_t n = (int64_t)ctr->total_chunks;
+    const int tid = threadIdx.x;
+    const int64_t per = (n + kScanThreads - 1) / kScanThreads;
+    const int64_t lo = std::min<int64_t>(n, per * tid), hi = std::min<int64_t>(n, lo + per);
+    int64_t sum = 0;
+    for (int64_t i = lo; i < hi; ++i) sum += a[i];
+    part[tid] = sum;
+    __syncthreads();
+    for (int d = 1; d < kScanThreads; d <<= 1) {
+        const int64_t v = (tid >= d) ? part[tid - d] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int64_t run = part[tid] - sum;
+    for (int64_t i = lo; i < hi; ++i) {
+        const int64_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    if (tid == kScanThreads - 1) a[n] = part[tid];
+}
+
+// one wavefront per chunk: sub-sample times, features, sphere flux
+__global__ void __launch_bounds__(64)
+k_sur_enum(const double* __restrict__ times, int shared_grid, const gl::SetConst* __restrict__ sc,
+           const int64_t* __restrict__ seg_begin, const int64_t* __restrict__ chunk_off,
+           const Counters* __restrict__ ctr, const unsigned long long* __restrict__ masks,
+           const int* __restrict__ chunk_set, const int64_t* __restrict__ chunk_sub,
+           float* __restrict__ feat, double* __restrict__ fsph, double* __restrict__ scale,
+           double* __restrict__ tsub, double* __restrict__ F, int* __restrict__ bin, int* __restrict__ setid)
+{
+    __shared__ int lds_idx[kChunk];
+    const int lane = threadIdx.x;
+    const int64_t c = uniform64((int64_t)blockIdx.x);
+    if (c >= (int64_t)ctr->total_chunks) return;
+    const unsigned long long M = (unsigned long long)uniform64((int64_t)masks[c]);
+    if (!M) return;
+    const int64_t s = uniform64(chunk_set[c]);
+    const gl::SetConst S = sc[s];
+    const int64_t lc = c - chunk_off[s];
+    const int64_t tb = shared_grid ? lc * kChunk : seg_begin[s] + lc * kChunk;
+    if ((M >> lane) & 1ull) lds_idx[__popcll(M & ((1ull << lane) - 1ull))] = lane;
+    __syncthreads();
+    const int nss = S.n_ss;
+    const int N = __popcll(M) * nss;
+    const int64_t g0 = chunk_sub[c];
+    for (int f = lane; f < N; f += kChunk) {
+        const int o = f / nss, j = f - o * nss;
+        const double t = times[tb + lds_idx[o]] + (((double)j + 0.5) / (double)nss - 0.5) * S.t_exp;
+        const int64_t g = g0 + f;
+        float fe[gl::kSurFeat];
+        for (int r = 0; r < gl::kSurFeat; ++r) fe[r] = 0.f;
+        double sc_ = 0.0, fs = 1.0, Fv = 1.0;
+        int b = -1;
+        double x0, y0;
+        if (gl::centre_at(S, t, x0, y0) && gl::sur_encode(S, x0, y0, fe, sc_, b)) {
+            gl::NoCensus nc;
+            const gl::SetConst C = gl::sphere_of(S);
+            fs = 1.0 - gl::occulted<gl::NoCensus>(C, x0, y0, nullptr, nc);
+            Fv = __builtin_nan("");  // decided by the gate
+        }
+        for (int r = 0; r < gl::kSurFeat; ++r) feat[g * gl::kSurFeat + r] = fe[r];
+        fsph[g] = fs;
+        scale[g] = sc_;
+        tsub[g] = t;
+        F[g] = Fv;
+        bin[g] = b;
+        setid[g] = (int)s;
+    }
+}
+
+// accept F = F_sphere + scale * pred where safety * table[bin] * ... <= tol,
+// otherwise queue the sub-sample for the exact kernel
+__global__ void k_sur_gate(const float* __restrict__ pred, const double* __restrict__ fsph,
+                           const double* __restrict__ scale, const int* __restrict__ bin,
+                           const float* __restrict__ table, double safety, double tol, int64_t n,
+                           double* __restrict__ F, int64_t* __restrict__ fb, Counters* __restrict__ ctr)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool queue = false;
+    if (g < n && bin[g] >= 0) {
+        const float tb = table[bin[g]];
+        const double bound = safety * (double)tb;
+        if (tb >= 0.f && bound <= tol && gl::finite_d(bound)) F[g] = fsph[g] + scale[g] * (double)pred[g];
+        else queue = true;
+    }
+    const unsigned long long qm = __ballot(queue);
+    unsigned long long base = 0;
+    const int lane = threadIdx.x & 63;
+    if (lane == 0 && qm) base = atomicAdd(&ctr->head, (unsigned long long)__popcll(qm));
+    base = (unsigned long long)uniform64((int64_t)base);
+    if (queue) fb[base + __popcll(qm & ((1ull << lane) - 1ull))] = g;
+}
+
+// exact flux for the queued sub-samples (count in ctr->head)
+__global__ void __launch_bounds__(64)
+k_sur_exact(const int64_t* __restrict__ fb, const Counters* __restrict__ ctr, const double* __restrict__ tsub,
+            const int* __restrict__ setid, const gl::SetConst* __restrict__ sc, double* __restrict__ F)
+{
+    const int64_t nq = (int64_t)ctr->head;
+    for (int64_t k = (int64_t)blockIdx.x * 64 + threadIdx.x; k < nq; k += (int64_t)gridDim.x * 64) {
+        const int64_t g = fb[k];
+        F[g] = gl::flux_instant(sc[setid[g]], tsub[g]);
+    }
+}
+
+// one wavefront per chunk: box average of each output's sub-samples in order
+__global__ void __launch_bounds__(64)
+k_sur_reduce(const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_begin,
+             const int64_t* __restrict__ chunk_off, const Counters* __restrict__ ctr,
+             const unsigned long long* __restrict__ masks, const int* __restrict__ chunk_set,
+             const int64_t* __restrict__ chunk_sub, const double* __restrict__ F, double* __restrict__ out)
+{
+    __shared__ int lds_idx[kChunk];
+    const int lane = threadIdx.x;
+    const int64_t c = uniform64((int64_t)blockIdx.x);
+    if (c >= (int64_t)ctr->total_chunks) return;
+    const unsigned long long M = (unsigned long long)uniform64((int64_t)masks[c]);
+    if (!M) return;
+    const int64_t s = uniform64(chunk_set[c]);
+    const int nss = sc[s].n_ss;
+    const int64_t i0 = seg_begin[s] + (c - chunk_off[s]) * kChunk;
+    if ((M >> lane) & 1ull) lds_idx[__popcll(M & ((1ull << lane) - 1ull))] = lane;
+    __syncthreads();
+    const int n_in = __popcll(M);
+    const int64_t g0 = chunk_sub[c];
+    for (int o = lane; o < n_in; o += kChunk) {
+        double sum = 0.0;
+        for (int j = 0; j < nss; ++j) sum += F[g0 + (int64_t)o * nss + j];
+        out[i0 + lds_idx[o]] = sum / (double)nss;
+    }
+}
+
+gl_status ensure_sur(gl_ctx* ctx, int64_t n_chunks, int64_t n_sub)
+{
+    if (n_chunks + 1 > ctx->cap_sub_chunks) {
+        (void)hipFree(ctx->chunk_sub);
+        ctx->chunk_sub = nullptr;
+        ctx->cap_sub_chunks = 0;
+        if (hipMalloc(&ctx->chunk_sub, sizeof(int64_t) * (n_chunks + 1)) != hipSuccess)
+            return fail(ctx, GL_ERR_NOMEM, "surrogate workspace (chunks)");
+        ctx->cap_sub_chunks = n_chunks + 1;
+    }
+    if (n_sub > ctx->cap_sub) {
+        void* b[] = {ctx->s_feat, ctx->s_pred, ctx->s_fsph, ctx->s_scale, ctx->s_t,
+                     ctx->s_F,    ctx->s_bin,  ctx->s_set,  ctx->s_fb};
+        for (void* p : b) (void)hipFree(p);
+        ctx->s_feat = ctx->s_pred = nullptr;
+        ctx->s_fsph = ctx->s_scale = ctx->s_t = ctx->s_F = nullptr;
+        ctx->s_bin = ctx->s_set = nullptr;
+        ctx->s_fb = nullptr;
+        ctx->cap_sub = 0;
+        const int64_t cap = std::max<int64_t>(n_sub, 1 << 16);
+        bool ok = hipMalloc(&ctx->s_feat, sizeof(float) * gl::kSurFeat * cap) == hipSuccess &&
+                  hipMalloc(&ctx->s_pred, sizeof(float) * cap) == hipSuccess &&
+                  hipMalloc(&ctx->s_fsph, sizeof(double) * cap) == hipSuccess &&
+                  hipMalloc(&ctx->s_scale, sizeof(double) * cap) == hipSuccess &&
+                  hipMalloc(&ctx->s_t, sizeof(double) * cap) == hipSuccess &&
+                  hipMalloc(&ctx->s_F, sizeof(double) * cap) == hipSuccess &&
+                  hipMalloc(&ctx->s_bin, sizeof(int) * cap) == hipSuccess &&
+                  hipMalloc(&ctx->s_set, sizeof(int) * cap) == hipSuccess &&
+                  hipMalloc(&ctx->s_fb, sizeof(int64_t) * cap) == hipSuccess;
+        if (!ok) {
+            free_sur(ctx);
+            return fail(ctx, GL_ERR_NOMEM, "surrogate workspace (sub-samples)");
+        }
+        ctx->cap_sub = cap;
+    }
+    return GL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gl_status gl_surrogate_samples(gl_ctx* ctx, const double* params, const double* times, int64_t n,
+                               float* feat, float* target, double* f_obl, double* f_sph,
+                               double* scale, int32_t* bin, void* stream)
+{
+    if (!ctx) return GL_ERR_NULL;
+    ctx->err.clear();
+    if (!params || !times || !feat || !target) return fail(ctx, GL_ERR_NULL, "params, times, feat, target");
+    if (n < 1) return fail(ctx, GL_ERR_SIZE, "n >= 1");
+    GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    hipLaunchKernelGGL(k_sur_samples, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, (hipStream_t)stream,
+                       params, n, times, feat, target, f_obl, f_sph, scale, bin, ctx->ctr);
+    GL_HIP(hipGetLastError(), "kernel launch");
+    return GL_OK;
+}
+
+gl_status gl_surrogate_bound(gl_ctx* ctx, const float* pred, const float* target, const double* scale,
+                             const int32_t* bin, int64_t n, float* table, void* stream)
+{
+    if (!ctx) return GL_ERR_NULL;
+    if (!pred || !target || !scale || !bin || !table) return fail(ctx, GL_ERR_NULL, "null argument");
+    if (n < 1) return fail(ctx, GL_ERR_SIZE, "n >= 1");
+    GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    hipLaunchKernelGGL(k_sur_bound, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       pred, target, scale, bin, n, table);
+    GL_HIP(hipGetLastError(), "kernel launch");
+    return GL_OK;
+}
+
+int gl_surrogate_num_bins(void) { return gl::kSurBins; }
+
+gl_status gl_lightcurve_batch_surrogate(gl_ctx* ctx, gl_mlp* mlp, const float* table, double safety,
+                                        double tol, const double* params, int64_t n_sets,
+                                        const double* times, const int64_t* offsets, int64_t n_times,
+                                        const int32_t* n_ss, const double* t_exp, double* out,
+                                        void* stream, int64_t* n_sub_out, int64_t* n_fallback_out)
+{
+    Batch b{params, n_sets, times, offsets, n_times, n_ss, t_exp, out, (hipStream_t)stream, 0};
+    gl_status st = check_args(ctx, b);
+    if (st != GL_OK) return st;
+    if (!mlp || !table) return fail(ctx, GL_ERR_NULL, "network and bound table are required");
+    GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    st = ensure_ws(ctx, n_sets, b.max_chunks);
+    if (st != GL_OK) return st;
+    st = ensure_sur(ctx, b.max_chunks, 0);
+    if (st != GL_OK) return st;
+    hipStream_t s = b.stream;
+    const int shared = b.offsets ? 0 : 1;
+    const int64_t cps = shared ? (b.n_times + kChunk - 1) / kChunk : 0;
+    hipLaunchKernelGGL(k_prep, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, s, params, n_sets,
+                       offsets, n_times, n_ss, t_exp, ctx->sc, ctx->seg_begin, ctx->seg_len,
+                       ctx->chunk_off, ctx->ctr);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, ctx->chunk_off, n_sets, b.max_chunks, ctx->ctr);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((b.max_chunks + 3) / 4)), dim3(256), 0, s, times, n_sets,
+                       shared, cps, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off, ctx->ctr,
+                       ctx->masks, ctx->chunk_set, out);
+    hipLaunchKernelGGL(k_sub_count, dim3((unsigned)((b.max_chunks + 255) / 256)), dim3(256), 0, s, ctx->masks,
+                       ctx->chunk_set, ctx->sc, ctx->ctr, ctx->chunk_sub);
+    hipLaunchKernelGGL(k_scan_n, dim3(1), dim3(kScanThreads), 0, s, ctx->chunk_sub, ctx->ctr);
+    GL_HIP(hipGetLastError(), "kernel launch");
+    // the sub-sample count sizes the buffers: one synchronisation
+    unsigned long long total_chunks = 0;
+    GL_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    GL_HIP(hipMemcpy(&total_chunks, &ctx->ctr->total_chunks, sizeof(total_chunks), hipMemcpyDeviceToHost), "hipMemcpy");
+    int64_t n_sub = 0;
+    GL_HIP(hipMemcpy(&n_sub, ctx->chunk_sub + total_chunks, sizeof(n_sub), hipMemcpyDeviceToHost), "hipMemcpy");
+    st = ensure_sur(ctx, b.max_chunks, n_sub);
+    if (st != GL_OK) return st;
+    if (n_sub > 0) {
+        hipLaunchKernelGGL(k_sur_enum, dim3((unsigned)total_chunks), dim3(64), 0, s, times, shared, ctx->sc,
+                           ctx->seg_begin, ctx->chunk_off, ctx->ctr, ctx->masks, ctx->chunk_set,
+                           ctx->chunk_sub, ctx->s_feat, ctx->s_fsph, ctx->s_scale, ctx->s_t, ctx->s_F,
+                           ctx->s_bin, ctx->s_set);
+        st = gl_mlp_forward(mlp, ctx->s_feat, n_sub, ctx->s_pred, s);
+        if (st != GL_OK) return fail(ctx, st, "surrogate network forward");
+        hipLaunchKernelGGL(k_reset_head, dim3(1), dim3(1), 0, s, ctx->ctr);
+        hipLaunchKernelGGL(k_sur_gate, dim3((unsigned)((n_sub + 255) / 256)), dim3(256), 0, s, ctx->s_pred,
+                           ctx->s_fsph, ctx->s_scale, ctx->s_bin, table, safety, tol, n_sub, ctx->s_F,
+                           ctx->s_fb, ctx->ctr);
+        const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)ctx->n_cu * ctx->waves_per_cu,
+                                                                    (n_sub + 63) / 64));
+        hipLaunchKernelGGL(k_sur_exact, dim3((unsigned)grid), dim3(64), 0, s, ctx->s_fb, ctx->ctr, ctx->s_t,
+                           ctx->s_set, ctx->sc, ctx->s_F);
+        hipLaunchKernelGGL(k_sur_reduce, dim3((unsigned)total_chunks), dim3(64), 0, s, ctx->sc, ctx->seg_begin,
+                           ctx->chunk_off, ctx->ctr, ctx->masks, ctx->chunk_set, ctx->chunk_sub, ctx->s_F, out);
+        GL_HIP(hipGetLastError(), "kernel launch");
+    }
+    GL_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    unsigned long long nfb = 0;
+    if (n_sub > 0) GL_HIP(hipMemcpy(&nfb, &ctx->ctr->head, sizeof(nfb), hipMemcpyDeviceToHost), "hipMemcpy");
+    if (n_sub_out) *n_sub_out = n_sub;
+    if (n_fallback_out) *n_fallback_out = (int64_t)nfb;
     return GL_OK;
 }
 

@@ -255,3 +255,173 @@ def to_device(workload, device="cuda"):
         t_exp=torch.from_numpy(np.ascontiguousarray(workload.t_exp)).to(device),
     )
     return d
+
+
+# ---------------------------------------------------------------- surrogate network
+GL_MLP_DIN, GL_MLP_WIDTH = 16, 256
+EXPORTED = EXPORTED + ("gl_mlp_num_params", "gl_mlp_create", "gl_mlp_destroy", "gl_mlp_last_error",
+                       "gl_mlp_set_weights", "gl_mlp_get_weights", "gl_mlp_forward", "gl_mlp_grads",
+                       "gl_mlp_train_step")
+
+
+def _mlp_lib():
+    L = lib()
+    if not getattr(L, "_mlp_typed", False):
+        vp, i, i64, f = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_float
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.gl_mlp_num_params.argtypes = []
+        L.gl_mlp_num_params.restype = i
+        L.gl_mlp_create.argtypes = [ctypes.POINTER(vp), i, i]
+        L.gl_mlp_create.restype = i
+        L.gl_mlp_destroy.argtypes = [vp]
+        L.gl_mlp_destroy.restype = None
+        L.gl_mlp_last_error.argtypes = [vp]
+        L.gl_mlp_last_error.restype = ctypes.c_char_p
+        L.gl_mlp_set_weights.argtypes = [vp, fp, i64]
+        L.gl_mlp_set_weights.restype = i
+        L.gl_mlp_get_weights.argtypes = [vp, fp, i64]
+        L.gl_mlp_get_weights.restype = i
+        L.gl_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.gl_mlp_forward.restype = i
+        L.gl_mlp_grads.argtypes = [vp, vp, vp, i64, fp, fp, vp]
+        L.gl_mlp_grads.restype = i
+        L.gl_mlp_train_step.argtypes = [vp, vp, vp, i64, f, vp, vp]
+        L.gl_mlp_train_step.restype = i
+        L._mlp_typed = True
+    return L
+
+
+def gl_mlp_num_params() -> int:
+    return _mlp_lib().gl_mlp_num_params()
+
+
+def _mcheck(h, st):
+    if st != GL_OK:
+        raise GLError(st, _mlp_lib().gl_mlp_last_error(h).decode() if h else "")
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class MLP:
+    """Owns a gl_mlp handle (the BF16-MFMA surrogate network)."""
+
+    def __init__(self, device: int = 0, max_batch: int = 8192):
+        L = _mlp_lib()
+        self.h = ctypes.c_void_p()
+        st = L.gl_mlp_create(ctypes.byref(self.h), int(device), int(max_batch))
+        if st != GL_OK:
+            raise GLError(st, "gl_mlp_create")
+        self.max_batch = max_batch
+
+    def close(self):
+        if self.h is not None:
+            _mlp_lib().gl_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, packed: np.ndarray):
+        packed = np.ascontiguousarray(packed, dtype=np.float32)
+        _mcheck(self.h, _mlp_lib().gl_mlp_set_weights(self.h, _fptr(packed), packed.size))
+
+    def get_weights(self) -> np.ndarray:
+        out = np.empty(gl_mlp_num_params(), np.float32)
+        _mcheck(self.h, _mlp_lib().gl_mlp_get_weights(self.h, _fptr(out), out.size))
+        return out
+
+    def forward(self, x, y=None, stream=None):
+        import torch
+        assert x.dtype == torch.float32 and x.is_cuda and x.is_contiguous() and x.shape[1] == GL_MLP_DIN
+        if y is None:
+            y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        _mcheck(self.h, _mlp_lib().gl_mlp_forward(self.h, _ptr(x), x.shape[0], _ptr(y),
+                                                  _stream_handle(stream)))
+        return y
+
+    def grads(self, x, t, stream=None):
+        out = np.empty(gl_mlp_num_params(), np.float32)
+        loss = ctypes.c_float()
+        _mcheck(self.h, _mlp_lib().gl_mlp_grads(self.h, _ptr(x), _ptr(t), x.shape[0], _fptr(out),
+                                                ctypes.byref(loss), _stream_handle(stream)))
+        return out, loss.value
+
+    def train_step(self, x, t, lr, loss_dev=None, stream=None):
+        _mcheck(self.h, _mlp_lib().gl_mlp_train_step(self.h, _ptr(x), _ptr(t), x.shape[0],
+                                                     float(lr), _ptr(loss_dev),
+                                                     _stream_handle(stream)))
+
+
+def pack_params(params) -> np.ndarray:
+    """[(W_l[in][out], b_l)] -> packed FP32 layout of the library."""
+    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in params]).astype(np.float32)
+
+
+def unpack_params(packed, d_in=GL_MLP_DIN, width=GL_MLP_WIDTH, depth=4):
+    dims = [d_in] + [width] * depth + [1]
+    out, o = [], 0
+    for a, b in zip(dims[:-1], dims[1:]):
+        W = packed[o:o + a * b].reshape(a, b)
+        o += a * b
+        bb = packed[o:o + b]
+        o += b
+        out.append((W, bb))
+    return out
+
+
+# ---------------------------------------------------------------- surrogate path
+EXPORTED = EXPORTED + ("gl_surrogate_samples", "gl_surrogate_num_bins", "gl_surrogate_bound",
+                       "gl_lightcurve_batch_surrogate")
+
+
+def _sur_lib():
+    L = _mlp_lib()
+    if not getattr(L, "_sur_typed", False):
+        vp, i, i64, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        L.gl_surrogate_samples.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
+        L.gl_surrogate_samples.restype = i
+        L.gl_surrogate_num_bins.argtypes = []
+        L.gl_surrogate_num_bins.restype = i
+        L.gl_surrogate_bound.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
+        L.gl_surrogate_bound.restype = i
+        L.gl_lightcurve_batch_surrogate.argtypes = [vp, vp, vp, d, d, vp, i64, vp, vp, i64, vp, vp, vp,
+                                                    vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.gl_lightcurve_batch_surrogate.restype = i
+        L._sur_typed = True
+    return L
+
+
+def gl_surrogate_num_bins() -> int:
+    return _sur_lib().gl_surrogate_num_bins()
+
+
+def gl_surrogate_samples(ctx, params, times, feat, target, f_obl=None, f_sph=None, scale=None,
+                         bin=None, stream=None):
+    n = params.shape[1]
+    assert times.numel() == n and feat.shape == (n, GL_MLP_DIN) and target.numel() == n
+    _check(ctx, _sur_lib().gl_surrogate_samples(ctx, _ptr(params), _ptr(times), n, _ptr(feat),
+                                                _ptr(target), _ptr(f_obl), _ptr(f_sph), _ptr(scale),
+                                                _ptr(bin), _stream_handle(stream)))
+
+
+def gl_surrogate_bound(ctx, pred, target, scale, bin, table, stream=None):
+    _check(ctx, _sur_lib().gl_surrogate_bound(ctx, _ptr(pred), _ptr(target), _ptr(scale), _ptr(bin),
+                                              pred.numel(), _ptr(table), _stream_handle(stream)))
+
+
+def gl_lightcurve_batch_surrogate(ctx, mlp, table, safety, tol, params, times, out, offsets=None,
+                                  n_ss=None, t_exp=None, stream=None):
+    """Returns (n_sub, n_fallback)."""
+    _validate(params, times, offsets, n_ss, t_exp, out)
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    st = _sur_lib().gl_lightcurve_batch_surrogate(
+        ctx, mlp.h, _ptr(table), float(safety), float(tol), _ptr(params), params.shape[1],
+        _ptr(times), _ptr(offsets), times.numel(), _ptr(n_ss), _ptr(t_exp), _ptr(out),
+        _stream_handle(stream), ctypes.byref(a), ctypes.byref(b))
+    _check(ctx, st)
+    return a.value, b.value

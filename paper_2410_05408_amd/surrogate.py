@@ -1,0 +1,121 @@
+"""Learned residual surrogate with exact fallback (training and evaluation).
+
+The network (library kernels, BF16 matrix cores) predicts the scaled residual
+(F_oblate - F_sphere) / (k^2 (1 - q)) of the exact oblate flux against the
+equal-projected-area sphere; the library's gate accepts F_sphere + prediction
+only where the calibrated error bound of the sample's bin, times a safety
+factor, is within the tolerance, and computes every other sub-sample with the
+exact kernel.  This module only orchestrates: every number is produced by the
+library (gl_surrogate_samples, gl_mlp_*, gl_surrogate_bound,
+gl_lightcurve_batch_surrogate); PyTorch provides buffers, index permutations
+and streams.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import gl, workloads
+
+
+def init_weights(seed: int, d_in: int = gl.GL_MLP_DIN, width: int = gl.GL_MLP_WIDTH,
+                 depth: int = 4) -> np.ndarray:
+    """He-uniform initial weights, zero biases, packed in the library layout."""
+    rng = np.random.default_rng(seed)
+    dims = [d_in] + [width] * depth + [1]
+    parts = []
+    for a, b in zip(dims[:-1], dims[1:]):
+        lim = math.sqrt(6.0 / a) if b != 1 else math.sqrt(3.0 / a)
+        parts += [rng.uniform(-lim, lim, a * b), np.zeros(b)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+class Samples:
+    """Device-resident samples from the exact kernels."""
+
+    def __init__(self, ctx, n: int, seed: int, window: float = 0.6, device="cuda"):
+        import torch
+        p, t = workloads.surrogate_samples(n, seed, window)
+        self.params = torch.from_numpy(np.ascontiguousarray(p)).to(device)
+        self.times = torch.from_numpy(np.ascontiguousarray(t)).to(device)
+        self.feat = torch.empty((n, gl.GL_MLP_DIN), dtype=torch.float32, device=device)
+        self.target = torch.empty(n, dtype=torch.float32, device=device)
+        self.scale = torch.empty(n, dtype=torch.float64, device=device)
+        self.bin = torch.empty(n, dtype=torch.int32, device=device)
+        self.f_obl = torch.empty(n, dtype=torch.float64, device=device)
+        self.f_sph = torch.empty(n, dtype=torch.float64, device=device)
+        gl.gl_surrogate_samples(ctx.handle, self.params, self.times, self.feat, self.target,
+                                self.f_obl, self.f_sph, self.scale, self.bin)
+        self.n = n
+
+
+class Surrogate:
+    def __init__(self, ctx, device: int = 0, max_batch: int = 8192, seed: int = 0, zero: bool = False):
+        import torch
+        self.ctx = ctx
+        self.net = gl.MLP(device, max_batch)
+        w = init_weights(seed)
+        if zero:
+            w[:] = 0.0  # the zero-residual predictor (ablation baseline)
+        self.net.set_weights(w)
+        self.bins = gl.gl_surrogate_num_bins()
+        self.table = torch.full((self.bins,), -1.0, dtype=torch.float32, device="cuda")
+        self.max_batch = max_batch
+        self.history = []
+
+    def close(self):
+        self.net.close()
+
+    def train(self, data: Samples, epochs: int, batch: int = 8192, lr: float = 2e-3,
+              lr_final: float = 1e-4, seed: int = 0, log=None):
+        import torch
+        batch = min(batch, self.max_batch)
+        keep = torch.nonzero(data.bin >= 0).squeeze(1)  # samples on the star
+        n = keep.numel()
+        steps = max(1, epochs * (n // batch))
+        g = torch.Generator(device="cuda")
+        g.manual_seed(seed)
+        loss_dev = torch.zeros(1, dtype=torch.float32, device="cuda")
+        step = 0
+        t0 = time.perf_counter()
+        for ep in range(epochs):
+            perm = keep[torch.randperm(n, device="cuda", generator=g)]
+            ep_loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+            for b0 in range(0, n - batch + 1, batch):
+                idx = perm[b0:b0 + batch]
+                x = data.feat.index_select(0, idx).contiguous()
+                t = data.target.index_select(0, idx).contiguous()
+                lr_s = lr * (lr_final / lr) ** (step / max(1, steps - 1))
+                self.net.train_step(x, t, lr_s, loss_dev)
+                ep_loss += loss_dev.double()
+                step += 1
+            torch.cuda.synchronize()
+            mse = float(ep_loss.item()) / max(1, (n // batch) * batch)
+            self.history.append(mse)
+            if log:
+                log(f"epoch {ep}: train mse {mse:.3e} ({time.perf_counter() - t0:.1f} s)")
+        return self.history
+
+    def predict(self, feat):
+        return self.net.forward(feat)
+
+    def calibrate(self, data: Samples):
+        """Per-bin maximum flux error of the network on calibration samples;
+        bins without samples stay negative (always computed exactly)."""
+        import torch
+        pred = self.predict(data.feat)
+        self.table.zero_()
+        gl.gl_surrogate_bound(self.ctx.handle, pred, data.target, data.scale, data.bin, self.table)
+        counts = torch.bincount(data.bin[data.bin >= 0].long(), minlength=self.bins)
+        self.table[counts == 0] = -1.0
+        torch.cuda.synchronize()
+        return self.table
+
+    def lightcurve(self, d, out, tol=1e-6, safety=4.0, stream=None):
+        """Gated light curves for a device workload dict (``gl.to_device``);
+        returns (n_sub, n_fallback)."""
+        return gl.gl_lightcurve_batch_surrogate(self.ctx.handle, self.net, self.table, safety, tol,
+                                                d["params"], d["times"], out, offsets=d["offsets"],
+                                                n_ss=d["n_ss"], t_exp=d["t_exp"], stream=stream)

@@ -1,0 +1,85 @@
+"""GPU: the learned surrogate with exact fallback.
+
+- its training targets come from the exact kernels and agree with the oracle
+  (oblate ellipse and the equal-area sphere);
+- the gated light curves stay within 1 ppm of the exact kernel on every point;
+- the trained network lets the gate accept more sub-samples than the same
+  gate around a zero-residual predictor (what the network gains).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    c = gpu_lib.Context(0)
+    yield c
+    c.close()
+
+
+def test_targets_match_oracle(gpu_lib, ctx, oracle):
+    import torch
+    from paper_2410_05408_amd import surrogate as S
+    say("case: surrogate training targets vs oracle")
+    data = S.Samples(ctx, 3000, seed=11)
+    torch.cuda.synchronize()
+    p = data.params.cpu().numpy()
+    t = data.times.cpu().numpy()
+    fo = data.f_obl.cpu().numpy()
+    fs = data.f_sph.cpu().numpy()
+    b = data.bin.cpu().numpy()
+    errs_o, errs_s = [], []
+    for i in range(0, 3000, 7):
+        ro = oracle.flux(p[:, i], t[i])
+        errs_o.append(abs(fo[i] - ro))
+        front, c, z, uh, sh, k, kq = oracle.geometry(p[:, i], t[i])
+        u1, u2 = oracle.kipping(p[8, i], p[9, i])
+        rs = 1.0 - oracle.occulted(c[0], c[1], 1.0, 0.0, math.sqrt(k * kq), 1.0, u1, u2) if front else 1.0
+        errs_s.append(abs(fs[i] - rs))
+    say(f"  oblate max err {max(errs_o):.2e}, sphere max err {max(errs_s):.2e}, on star {np.mean(b >= 0):.2f}")
+    assert max(errs_o) <= 1e-9 and max(errs_s) <= 1e-9
+
+
+def test_gated_light_curves_within_1ppm_and_network_gains(gpu_lib, ctx):
+    import torch
+    from paper_2410_05408_amd import surrogate as S
+    from paper_2410_05408_amd import workloads as W
+    gl = gpu_lib
+    say("case: train, calibrate, gated walker batch vs exact")
+    train = S.Samples(ctx, 400_000, seed=5)
+    cal = S.Samples(ctx, 200_000, seed=6)
+    sur = S.Surrogate(ctx, max_batch=8192, seed=0)
+    hist = sur.train(train, epochs=6, log=say)
+    assert hist[-1] < 0.5 * hist[0]
+    sur.calibrate(cal)
+    zero = S.Surrogate(ctx, max_batch=8192, zero=True)
+    zero.calibrate(cal)
+
+    w = W.walker_batch(n_sets=256)
+    d = gl.to_device(w, "cuda:0")
+    exact = ctx.batch(d["params"], d["times"], n_ss=d["n_ss"], t_exp=d["t_exp"])
+    out = torch.empty_like(exact)
+    n_sub, n_fb = sur.lightcurve(d, out, tol=1e-6)
+    out_z = torch.empty_like(exact)
+    n_sub_z, n_fb_z = zero.lightcurve(d, out_z, tol=1e-6)
+    torch.cuda.synchronize()
+    err = (out - exact).abs().max().item()
+    err_z = (out_z - exact).abs().max().item()
+    say(f"  trained: {n_sub} sub-samples, {n_fb} exact fallback ({n_fb / n_sub:.3f}), max err {err:.2e}")
+    say(f"  zero   : {n_sub_z} sub-samples, {n_fb_z} exact fallback ({n_fb_z / n_sub_z:.3f}), max err {err_z:.2e}")
+    assert err <= 1e-6 and err_z <= 1e-6
+    assert n_sub == n_sub_z
+    assert n_fb < n_sub
+    assert n_fb < n_fb_z  # what the trained network gains over the method without it
+    sur.close()
+    zero.close()
