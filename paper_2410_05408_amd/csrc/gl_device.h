@@ -89,16 +89,20 @@ GL_HD double rcp(double x)
 GL_HD double sqrt_nn(double x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    if (!(x > 1e-300)) return 0.0;
-    const double y = __builtin_amdgcn_rsq(x);
-    double g = x * y, h = 0.5 * y;
+    // branch-free: the refinement runs on a clamped argument and the result
+    // is selected afterwards (zero for x <= 1e-300 and for NaN)
+    const bool pos = x > 1e-300;
+    const double xc = pos ? x : 1.0;
+    const double y = __builtin_amdgcn_rsq(xc);
+    double g = xc * y, h = 0.5 * y;
     const double e = fma(-g, h, 0.5);
     g = fma(g, e, g);
     h = fma(h, e, h);
-    const double d = fma(-g, g, x);
+    const double d = fma(-g, g, xc);
     g = fma(d, h, g);
-    const double d2 = fma(-g, g, x);
-    return fma(d2, h, g);
+    const double d2 = fma(-g, g, xc);
+    const double r = fma(d2, h, g);
+    return pos ? r : 0.0;
 #else
     return x > 0.0 ? sqrt(x) : 0.0;
 #endif
@@ -479,6 +483,11 @@ GL_HD_CALL void arc_gk(const Frame& F, double cc, double sc, double h, Sums& S, 
 constexpr int kTrapOrders = 9;
 constexpr int kTrapN[kTrapOrders] = {8, 12, 16, 20, 24, 32, 40, 48, 64};
 
+// Weights 2 pi / (3 n) of the trapezoid sums of the mu integral.
+constexpr double kTrapW[kTrapOrders] = {
+    kTwoPi / (3.0 * 8), kTwoPi / (3.0 * 12), kTwoPi / (3.0 * 16), kTwoPi / (3.0 * 20), kTwoPi / (3.0 * 24),
+    kTwoPi / (3.0 * 32), kTwoPi / (3.0 * 40), kTwoPi / (3.0 * 48), kTwoPi / (3.0 * 64)};
+
 GL_HD void trap_step(int i, double& c, double& s)
 {
     switch (i) {
@@ -498,11 +507,11 @@ GL_HD void trap_step(int i, double& c, double& s)
 // nearest complex zero of 1 - r^2(th) from the real th axis (error ~ exp(-n d)).
 // The caller passes r = cosh(d) (or a lower bound of it), compared here with
 // cosh(L / n).  Returns -1 if even the largest order is not enough.
-constexpr double kTrapL = 30.0;
+constexpr double kTrapL = 24.0;
 constexpr double kTrapCosh[9] = {
-    // cosh(30 / n) for n = 8, 12, 16, 20, 24, 32, 40, 48, 64
-    21.2722705472043, 6.1322894796636, 3.3374035793208, 2.3524096152432, 1.8884239651648,
-    1.4725497384850, 1.2946832846768, 1.2017536151364, 1.1119268223779};
+    // cosh(24 / n) for n = 8, 12, 16, 20, 24, 32, 40, 48, 64
+    10.0676619957778, 3.7621956910836, 2.3524096152432, 1.8106555673244, 1.5430806348152,
+    1.2946832846768, 1.1854652182423, 1.1276259652064, 1.0711403467046};
 
 GL_HD int trap_order_cosh(double r)
 {
@@ -542,7 +551,7 @@ GL_HD_CALL double trap_lin(const SetConst& s, double x0, double y0, int oi)
         sn = sn * rc + c * rs;
         c = cn;
     }
-    return acc * (kTwoPi / (3.0 * n));
+    return acc * kTrapW[oi];
 }
 
 // Whole ellipse, nested periodic trapezoid: 8, 16, 32, 64 nodes, each level
@@ -567,7 +576,8 @@ GL_HD_CALL bool trap_lin_nested(const SetConst& s, double x0, double y0, double&
         sum += node(r, r) + node(r, -r) + node(-r, r) + node(-r, -r);
     }
     int n = 8;
-    double prev = sum * (kTwoPi / (3.0 * n));
+    double wn = kTwoPi / (3.0 * 8);  // 2 pi / (3 n), halved exactly with each level
+    double prev = sum * wn;
     double prev_diff = 1e300;
     levels = 1;
 #pragma unroll 1
@@ -585,7 +595,8 @@ GL_HD_CALL bool trap_lin_nested(const SetConst& s, double x0, double y0, double&
         }
         sum += add;
         n *= 2;
-        const double cur = sum * (kTwoPi / (3.0 * n));
+        wn *= 0.5;
+        const double cur = sum * wn;
         const double diff = fabs(cur - prev);
         ++levels;
         if (n >= 32 && diff <= kTrapTol && diff <= prev_diff) {
