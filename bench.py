@@ -99,6 +99,19 @@ def surrogate_leg(ctx, d, exact_out, exact_ms, n_out, args):
     return res
 
 
+def copy_calibration(n_bytes=1 << 30, reps=3):
+    """A plain device-to-device copy of known size: the HBM byte counters read
+    for it (per dispatch) give the scale applied to the compute kernel's."""
+    import torch
+    a = torch.ones(n_bytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": n_bytes, "bytes_written": n_bytes,
+                                           "dispatches": reps}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +122,8 @@ def main():
     ap.add_argument("--sur-train", type=int, default=20_000_000)
     ap.add_argument("--sur-cal", type=int, default=1_000_000)
     ap.add_argument("--sur-epochs", type=int, default=4)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the exact path "
@@ -116,6 +131,10 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     from paper_2410_05408_amd import gl, workloads
 
