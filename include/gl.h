@@ -103,7 +103,7 @@ gl_status gl_ctx_sync_status(gl_ctx *ctx);
 const char *gl_ctx_last_error(const gl_ctx *ctx);
 
 /* Launch-plan autotuner: times the candidate persistent-grid sizes of the
- * exact kernel on a representative batch (same arguments as
+ * work-list kernels on a representative batch (same arguments as
  * gl_lightcurve_batch; `out` is overwritten) and keeps the fastest in the
  * context's plan.  Synchronises `stream`.  Quadrature orders are not a plan
  * setting: every sample picks its own (self-checking rules). */
@@ -112,39 +112,66 @@ gl_status gl_autotune(gl_ctx *ctx, const double *params, int64_t n_sets,
                       const int32_t *n_ss, const double *t_exp, double *out,
                       void *stream);
 
-/* Current plan: persistent wavefronts per compute unit of the compute kernel. */
+/* Current plan: persistent wavefronts per compute unit of the work-list
+ * kernels (trapezoid, hard-sample and arc stages). */
 gl_status gl_ctx_get_plan(const gl_ctx *ctx, int *waves_per_cu);
 
-/* Sets the plan; waves_per_cu in [1, 32] (default 8). */
+/* Sets the plan; waves_per_cu in [1, 32] (default 16). */
 gl_status gl_ctx_set_plan(gl_ctx *ctx, int waves_per_cu);
+
+/* Work-list capacities of the exact path, in entries: sub-sample flux slots
+ * (and trapezoid entries) <= 2^27 - 1, hard samples and ellipse arcs
+ * <= 2^30 - 1; 0 selects the default (16 Mi slots, a quarter of that of hard
+ * samples, twice that of arcs, about 1.5 GB of device memory, less for small
+ * batches).  A chunk of 64 outputs whose samples do not fit is evaluated by
+ * the fused per-lane kernel instead, with the same results up to rounding;
+ * an ellipse arc that does not fit is integrated where it is found.  Waits
+ * for the device and frees the current lists (reallocated by the next batch). */
+gl_status gl_ctx_set_capacity(gl_ctx *ctx, int64_t sub_samples, int64_t hard_samples,
+                              int64_t arcs);
 
 /* When on != 0, later batches replay a captured HIP graph of the whole
  * pipeline if their arguments equal the previous batch's (default on). */
 gl_status gl_ctx_set_graph(gl_ctx *ctx, int on);
 
+/* Stages of one batch, in launch order (timed separately):
+ *  0 set-up (parameter preparation, chunk scan), 1 window test and
+ *  classification, 2 whole-ellipse trapezoid, 3 hard samples (intersection
+ *  quartic, break points, limb arcs), 4 nested trapezoid for whole ellipses
+ *  near the limb, 5 ellipse arcs (Gauss-Kronrod levels 0..4, with the final
+ *  combination of each hard sample), 6 supersample average, 7 fused kernel
+ *  for chunks beyond the work-list capacities. */
+#define GL_NSTAGES 8
+
 /* Instrumentation: with n_slots > 0, the next n_slots batches are launched
- * directly (no graph) with HIP events recorded on their stream around the
- * whole pipeline and around the compute kernel.  n_slots = 0 turns it off. */
+ * directly (no graph) with a HIP event recorded on their stream before the
+ * first stage and after every stage.  n_slots = 0 turns it off. */
 gl_status gl_ctx_set_timing(gl_ctx *ctx, int n_slots);
 
-/* Waits for the recorded batches and returns the summed compute-kernel and
- * pipeline times (ms) and how many batches were timed; frees the slots for
- * reuse.  Any output pointer may be NULL. */
+/* Waits for the recorded batches and returns the summed times (ms) of stages
+ * 1..7 (compute) and 0..7 (pipeline) and how many batches were timed; frees
+ * the slots for reuse.  Any output pointer may be NULL. */
 gl_status gl_ctx_get_timing(gl_ctx *ctx, double *compute_ms, double *pipeline_ms, int *n);
 
+/* Like gl_ctx_get_timing, per stage: stage_ms[GL_NSTAGES] (host memory)
+ * receives the summed time of each stage over the timed batches. */
+gl_status gl_ctx_get_stage_timing(gl_ctx *ctx, double *stage_ms, int *n);
+
 /* Work census: runs the batch once (same arguments and results as
- * gl_lightcurve_batch) with a counting variant of the compute kernel, waits,
- * and writes counts[8] (host memory): in-window sub-samples, samples with the
+ * gl_lightcurve_batch) with counting variants of the kernels, waits, and
+ * writes counts[10] (host memory): in-window sub-samples, samples with the
  * whole ellipse on the star, intersecting samples, in-window samples off the
- * star, periodic-trapezoid nodes, 21-node Gauss-Kronrod pieces, Newton steps
- * of the intersection solver, limb arcs. */
+ * star, nodes of the rigorous-order periodic trapezoid, 21-node
+ * Gauss-Kronrod pieces, Newton steps of the intersection solver, limb arcs,
+ * nodes of the nested periodic trapezoid, ellipse arcs listed for the
+ * Gauss-Kronrod stage. */
 gl_status gl_census(gl_ctx *ctx, const double *params, int64_t n_sets, const double *times,
                     const int64_t *offsets, int64_t n_times, const int32_t *n_ss,
                     const double *t_exp, double *out, void *stream, int64_t *counts);
 
 /* Algorithmic FP64 operations per census item (add/sub/mul/div/sqrt/
  * transcendental = 1, fused multiply-add = 2), counted from the kernel source:
- * per_item[8] (host memory) lines up with the census counts. */
+ * per_item[10] (host memory) lines up with the census counts. */
 gl_status gl_flop_model(int64_t *per_item);
 
 /* ---------------------------------------------------------------------------
@@ -212,17 +239,21 @@ gl_status gl_surrogate_samples(gl_ctx *ctx, const double *params, const double *
 /* Number of calibration bins of the error-bound table. */
 int gl_surrogate_num_bins(void);
 
-/* Calibration: table[bin] = max(table[bin], |(pred - target) * scale|) over the
- * n samples (device arrays; table float[gl_surrogate_num_bins()], start from
- * zeros).  A bin never seen keeps 0 and must be marked unusable by the caller
+/* Calibration: table[bin] = max(table[bin], |pred - target|) over the n
+ * samples, the network's largest error in scaled-residual units (rounded up
+ * to float; device arrays; table float[gl_surrogate_num_bins()], start from
+ * zeros; `scale` is accepted for symmetry with the samples and not used).
+ * A bin never seen keeps 0 and must be marked unusable by the caller
  * (negative entries always fall back). */
 gl_status gl_surrogate_bound(gl_ctx *ctx, const float *pred, const float *target, const double *scale,
                              const int32_t *bin, int64_t n, float *table, void *stream);
 
 /* Light curves through the surrogate: same batch arguments and output as
  * gl_lightcurve_batch.  Every in-window sub-sample on the star gets
- * F = F_sphere + scale * network(features) when safety * table[bin] <= tol,
- * and the exact kernel's value otherwise; outputs are box-averaged in order.
+ * F = F_sphere + scale * network(features) when
+ * safety * table[bin] * scale <= tol (its bin's calibrated error in flux
+ * units, with a safety factor), and the exact kernel's value otherwise;
+ * outputs are box-averaged in order.
  * Synchronous (it sizes its buffers from the device); *n_sub_out and
  * *n_fallback_out (host, may be NULL) receive the number of in-window
  * sub-samples and of those computed exactly. */

@@ -325,7 +325,7 @@ struct QuarticRoots {
 };
 
 template <class CT>
-GL_HD_CALL void solve_quartic(const Poly4& q, QuarticRoots& out, CT& ct)
+GL_HD void solve_quartic_inl(const Poly4& q, QuarticRoots& out, CT& ct)
 {
     // Cauchy bound on all roots of q and of q'
     const double inv = 1.0 / fabs(q.a4);
@@ -379,6 +379,13 @@ GL_HD_CALL void solve_quartic(const Poly4& q, QuarticRoots& out, CT& ct)
     }
 }
 
+// Out-of-line form (keeps the register budget of callers that rarely need it).
+template <class CT>
+GL_HD_CALL void solve_quartic(const Poly4& q, QuarticRoots& out, CT& ct)
+{
+    solve_quartic_inl(q, out, ct);
+}
+
 // ---------------------------------------------------------------- geometry of one sample
 // Ellipse in the rotated angle psi = th - th0:
 //   x = x0 + Xc cos(psi) + Xs sin(psi),  y = y0 + Yc cos(psi) + Ys sin(psi)
@@ -421,11 +428,11 @@ constexpr int kArcMaxLevel = 4;           // an arc is re-split at most into 16 
 // One piece tau in [mid - half, mid + half] of the arc psi = psi_c + 2 atan(tau):
 // clustered Gauss-Kronrod 10/21 rule.  Adds the Kronrod sums to K and returns
 // the Gauss-Kronrod difference of the integrals of 1 and mu.
+template <bool UNROLL = false>
 GL_HD double gk_piece(const Frame& F, double cc, double sc, double mid, double half, Sums& K)
 {
     double kf = 0.0, kl = 0.0, kq = 0.0, gf = 0.0, gl = 0.0;
-#pragma unroll 1
-    for (int j = 0; j < 21; ++j) {
+    auto node = [&](int j) {
         const double tau = mid + half * GK21_M[j];
         const double t2 = tau * tau;
         const double inv = rcp(1.0 + t2);
@@ -447,6 +454,15 @@ GL_HD double gk_piece(const Frame& F, double cc, double sc, double mid, double h
         kq += GK21_WK[j] * (inv * quad);
         gf += GK21_WG[j] * fl;
         gl += GK21_WG[j] * li;
+    };
+    // same nodes in the same order either way; unrolled, the rule's constants
+    // become immediates (no table loads inside the loop)
+    if (UNROLL) {
+#pragma unroll
+        for (int j = 0; j < 21; ++j) node(j);
+    } else {
+#pragma unroll 1
+        for (int j = 0; j < 21; ++j) node(j);
     }
     // dpsi factor 2, f_flat = flat/2, f_lin = (2/3) G flat/2, f_quad = quad/2
     K.flat += half * kf;
@@ -456,11 +472,12 @@ GL_HD double gk_piece(const Frame& F, double cc, double sc, double mid, double h
 }
 
 // Whole arc tau in [-h, h]: one Gauss-Kronrod piece, re-split uniformly into
-// 2, 4, ... pieces until the summed Gauss-Kronrod difference is below kArcTol.
+// 2, 4, ... pieces until the summed Gauss-Kronrod difference is below kArcTol
+// (starting at 2^L0 pieces when the coarser levels are already known to fail).
 template <class CT>
-GL_HD_CALL void arc_gk(const Frame& F, double cc, double sc, double h, Sums& S, CT& ct)
+GL_HD_CALL void arc_gk(const Frame& F, double cc, double sc, double h, Sums& S, CT& ct, int L0 = 0)
 {
-    for (int L = 0;; ++L) {
+    for (int L = L0;; ++L) {
         const int np = 1 << L;
         const double half = h / np;
         Sums K = {0.0, 0.0, 0.0};
@@ -529,8 +546,9 @@ GL_HD int trap_order(double d)
 
 // Whole ellipse, periodic trapezoid with n = kTrapN[oi] equally spaced nodes in
 // th (the integrand is periodic and analytic in a strip): mu integral.  Nodes
-// come in pairs +-th_j from a rotation recurrence.
-GL_HD_CALL double trap_lin(const SetConst& s, double x0, double y0, int oi)
+// come in pairs +-th_j from a rotation recurrence.  (Inlined form; trap_lin
+// below is the same rule as an out-of-line call.)
+GL_HD double trap_lin_inl(const SetConst& s, double x0, double y0, int oi)
 {
     const double P1 = x0 * s.C, P2 = y0 * s.A - x0 * s.B;
     const int n = kTrapN[oi];
@@ -554,12 +572,17 @@ GL_HD_CALL double trap_lin(const SetConst& s, double x0, double y0, int oi)
     return acc * kTrapW[oi];
 }
 
+GL_HD_CALL double trap_lin(const SetConst& s, double x0, double y0, int oi)
+{
+    return trap_lin_inl(s, x0, y0, oi);
+}
+
 // Whole ellipse, nested periodic trapezoid: 8, 16, 32, 64 nodes, each level
 // adding the midpoints of the previous one.  Returns true (and the mu
 // integral) once two successive levels agree to kTrapTol, judged from the
 // 16/32 pair on and only while the differences shrink (a coarse level can
 // agree with the next by accident before the convergence is exponential).
-GL_HD_CALL bool trap_lin_nested(const SetConst& s, double x0, double y0, double& out, int& levels)
+GL_HD bool trap_lin_nested_inl(const SetConst& s, double x0, double y0, double& out, int& levels)
 {
     const double P1 = x0 * s.C, P2 = y0 * s.A - x0 * s.B;
     auto node = [&](double c, double sn) {
@@ -608,6 +631,11 @@ GL_HD_CALL bool trap_lin_nested(const SetConst& s, double x0, double y0, double&
     }
     out = prev;
     return false;
+}
+
+GL_HD_CALL bool trap_lin_nested(const SetConst& s, double x0, double y0, double& out, int& levels)
+{
+    return trap_lin_nested_inl(s, x0, y0, out, levels);
 }
 
 // Limb arc, counter-clockwise from unit vector direction (xa, ya) to (xb, yb).
@@ -683,6 +711,34 @@ GL_HD double zero_cosh_bound(double rho2, double rho, double k, double kq)
     return fmax(c, 1.0);
 }
 
+// Classification of a sample by its ellipse centre: kOffDisk when the ellipse
+// cannot touch the disk, the trapezoid order index (>= 0) when the rigorous
+// singularity bound proves the whole ellipse lies well inside the disk, kHard
+// otherwise.
+constexpr int kOffDisk = -2;
+constexpr int kHard = -1;
+
+GL_HD int easy_class(const SetConst& s, double x0, double y0)
+{
+    const double rho2 = x0 * x0 + y0 * y0;
+    const double kp = 1.0 + s.k;
+    if (rho2 >= kp * kp) return kOffDisk;
+    const double rho = sqrt_nn(rho2);
+    const double cosh_bound = zero_cosh_bound(rho2, rho, s.k, s.AC * rcp(s.k));
+    const int oi = trap_order_cosh(cosh_bound);
+    return oi < 0 ? kHard : oi;
+}
+
+// Occulted fraction of a whole ellipse on the disk from its mu integral sl:
+// the area and the r^2 moment of the ellipse are closed forms.
+GL_HD double whole_delta(const SetConst& s, double x0, double y0, double sl)
+{
+    const double rho2 = x0 * x0 + y0 * y0;
+    const double S_flat_whole = kPi * s.AC;
+    const double S_quad_whole = kPi * s.AC * (rho2 + 0.25 * s.M2);
+    return (s.c0 * S_flat_whole + s.c1 * sl + s.c2 * S_quad_whole) * s.inv_phi;
+}
+
 // Easy samples: the ellipse cannot touch the disk, or provably lies well
 // inside it (periodic trapezoid, order from the singularity bound).  Returns
 // true and the occulted fraction when the sample is easy.
@@ -690,34 +746,37 @@ template <class CT = NoCensus>
 GL_HD bool occulted_easy(const SetConst& s, double x0, double y0, double& delta, int* cls_out,
                          CT& ct)
 {
-    const double rho2 = x0 * x0 + y0 * y0;
-    const double kp = 1.0 + s.k;
-    if (rho2 >= kp * kp) {
+    const int oi = easy_class(s, x0, y0);
+    if (oi == kOffDisk) {
         if (cls_out) *cls_out = CLS_OUT;
         delta = 0.0;
         return true;
     }
-    const double rho = sqrt_nn(rho2);
-    const double cosh_bound = zero_cosh_bound(rho2, rho, s.k, s.AC * rcp(s.k));
-    const int oi_deep = trap_order_cosh(cosh_bound);
-    if (oi_deep < 0) return false;
+    if (oi == kHard) return false;
     if (cls_out) *cls_out = CLS_FULL;
-    ct.trap(kTrapN[oi_deep]);
-    const double sl = trap_lin(s, x0, y0, oi_deep);
-    const double S_flat_whole = kPi * s.AC;
-    const double S_quad_whole = kPi * s.AC * (rho2 + 0.25 * s.M2);
-    delta = (s.c0 * S_flat_whole + s.c1 * sl + s.c2 * S_quad_whole) * s.inv_phi;
+    ct.trap(kTrapN[oi]);
+    delta = whole_delta(s, x0, y0, trap_lin(s, x0, y0, oi));
     return true;
 }
 
-// Hard samples (everything occulted_easy declines): intersection quartic,
-// near-limb whole ellipses, limb and ellipse arcs.
-template <class CT = NoCensus>
-GL_HD double occulted_hard(const SetConst& s, double x0, double y0, int* cls_out, CT& ct)
+// What a hard sample needs before its boundary is walked: the intersection
+// quartic in t = tan(psi/2) about the anchor th0, its real roots and critical
+// points, and the cluster points (local maxima of r^2 on the star whose
+// nearby complex zeros come close to the real axis).
+struct HardPrep {
+    Poly4 q;
+    QuarticRoots R;
+    double c0a, s0a;  // cos, sin of the anchor th0
+    double tc[3];
+    int ntc;
+    double t_near;    // the local maximum nearest the limb
+    bool inf_inside;  // t = +-inf (th = th0 + pi) lies on the star
+};
+
+template <class CT, bool INLINE_SOLVE = false>
+GL_HD void hard_prepare(const SetConst& s, double x0, double y0, HardPrep& H, CT& ct)
 {
     const double rho2 = x0 * x0 + y0 * y0;
-    const double S_flat_whole = kPi * s.AC;
-    const double S_quad_whole = kPi * s.AC * (rho2 + 0.25 * s.M2);
     // g(th) = |p(th)|^2 - 1 = K0 + K1 cos + K2 sin + K3 cos 2th + K4 sin 2th
     const double K0 = rho2 - 1.0 + 0.5 * s.M2;
     const double K1 = 2.0 * (x0 * s.A + y0 * s.B);
@@ -748,6 +807,8 @@ GL_HD double occulted_hard(const SetConst& s, double x0, double y0, int* cls_out
         }
     }
     const double c0a = -best_c, s0a = -best_s;  // th0 = th_best + pi
+    H.c0a = c0a;
+    H.s0a = s0a;
     // g(th0 + psi) = K0 + K1' cos psi + K2' sin psi + K3' cos 2psi + K4' sin 2psi
     const double K1r = K1 * c0a + K2 * s0a;
     const double K2r = -K1 * s0a + K2 * c0a;
@@ -755,98 +816,100 @@ GL_HD double occulted_hard(const SetConst& s, double x0, double y0, int* cls_out
     const double K3r = s.K3 * c2a + s.K4 * s2a;
     const double K4r = -s.K3 * s2a + s.K4 * c2a;
     // (1 + t^2)^2 g as a quartic in t = tan(psi/2)
-    Poly4 q;
+    Poly4& q = H.q;
     q.a4 = K0 - K1r + K3r;
     q.a3 = 2.0 * K2r - 4.0 * K4r;
     q.a2 = 2.0 * K0 - 6.0 * K3r;
     q.a1 = 2.0 * K2r + 4.0 * K4r;
     q.a0 = K0 + K1r + K3r;
-    QuarticRoots R;
-    solve_quartic(q, R, ct);
-    const bool inf_inside = q.a4 < 0.0;
+    if (INLINE_SOLVE) solve_quartic_inl(q, H.R, ct);
+    else solve_quartic(q, H.R, ct);
+    H.inf_inside = q.a4 < 0.0;
 
     // local maxima of r^2 on the star: the nearby complex zeros of the quartic
     // sit at t_c +- i sqrt(2|p|/|p''|), about 2 sqrt(2|p|/|p''|)/(1+t_c^2) in th
-    double tc[3];
-    int ntc = 0;
-    double t_near = 0.0, d_near = 1e300;
-    for (int i = 0; i < R.n_crit; ++i) {
-        const double t = R.c[i];
+    H.ntc = 0;
+    H.t_near = 0.0;
+    double d_near = 1e300;
+    for (int i = 0; i < H.R.n_crit; ++i) {
+        const double t = H.R.c[i];
         const double pv = p4(q, t), pp = ddp4(q, t);
         if (pv < 0.0 && pp < 0.0) {
             const double dth = 2.0 * sqrt_nn(2.0 * pv * rcp(pp)) * rcp(1.0 + t * t);
             if (dth < d_near) {
                 d_near = dth;
-                t_near = t;
+                H.t_near = t;
             }
-            if (dth < kSplitDist) tc[ntc++] = t;
+            if (dth < kSplitDist) H.tc[H.ntc++] = t;
         }
     }
+}
 
-    // break points of the boundary in t, ascending; kind 0 = root, 1 = cluster point
-    double bp[7];
-    int kind[7];
+// Class of a prepared hard sample: no crossing with t = inf off the star means
+// the ellipse lies off the disk; no crossing otherwise means whole on the disk.
+GL_HD int hard_class(const HardPrep& H)
+{
+    if (H.R.n_roots < 2) return H.inf_inside ? CLS_FULL : CLS_OUT;
+    return CLS_PARTIAL;
+}
+
+// Break points of the boundary of E cap D in t, ascending (kind 0 = root,
+// 1 = cluster point).  A whole ellipse needs at least one cluster point
+// (a single one gets the diametrically opposite point as its partner).
+GL_HD int hard_breaks(HardPrep& H, double* bp, int* kind)
+{
     int nb = 0;
-    if (R.n_roots < 2) {
-        // no crossing: the whole ellipse is on the star or off it
-        if (!inf_inside) {
-            if (cls_out) *cls_out = CLS_OUT;
-            return 0.0;
-        }
-        if (cls_out) *cls_out = CLS_FULL;
-        if (ntc == 0) {
-            double sl;
-            int lev;
-            const bool ok = trap_lin_nested(s, x0, y0, sl, lev);
-            ct.trap(8 << (lev - 1));
-            if (ok) return (s.c0 * S_flat_whole + s.c1 * sl + s.c2 * S_quad_whole) * s.inv_phi;
-            tc[ntc++] = t_near;  // did not settle: cluster at the point nearest the limb
-        }
-        if (ntc == 1) {
+    if (H.R.n_roots < 2) {
+        if (H.ntc == 1) {
             // second break point diametrically opposite: psi + pi <-> -1/t
-            const double t = tc[0];
+            const double t = H.tc[0];
             const double o = (t != 0.0) ? -1.0 / t : -1e16;
             if (o < t) {
-                tc[1] = t;
-                tc[0] = o;
+                H.tc[1] = t;
+                H.tc[0] = o;
             } else {
-                tc[1] = o;
+                H.tc[1] = o;
             }
-            ntc = 2;
+            H.ntc = 2;
         }
-        for (int i = 0; i < ntc; ++i) {
-            bp[nb] = tc[i];
+        for (int i = 0; i < H.ntc; ++i) {
+            bp[nb] = H.tc[i];
             kind[nb++] = 1;
         }
     } else {
-        if (cls_out) *cls_out = CLS_PARTIAL;
         int i = 0, j = 0;
-        while (i < R.n_roots || j < ntc) {
-            if (j >= ntc || (i < R.n_roots && R.r[i] <= tc[j])) {
-                bp[nb] = R.r[i++];
+        while (i < H.R.n_roots || j < H.ntc) {
+            if (j >= H.ntc || (i < H.R.n_roots && H.R.r[i] <= H.tc[j])) {
+                bp[nb] = H.R.r[i++];
                 kind[nb++] = 0;
             } else {
-                bp[nb] = tc[j++];
+                bp[nb] = H.tc[j++];
                 kind[nb++] = 1;
             }
         }
     }
+    return nb;
+}
 
-    Frame F;
-    make_frame(s, x0, y0, c0a, s0a, F);
-    Sums S = {0.0, 0.0, 0.0};
+// Walks the boundary between consecutive break points: ellipse arcs on the
+// star go to arc(cc, sc, h) (as tau-rule arcs, split when longer than pi);
+// limb arcs are added to S in closed form when `limbs` is set.
+template <class ArcFn, class CT>
+GL_HD void boundary_walk(const HardPrep& H, const Frame& F, const double* bp, const int* kind,
+                         int nb, Sums& S, bool limbs, ArcFn&& arc, CT& ct)
+{
     for (int i = 0; i < nb; ++i) {
         const int i1 = (i + 1 == nb) ? 0 : i + 1;
         const double ta = bp[i], tb = bp[i1];
         bool inside;
         if (kind[i] == 1 || kind[i1] == 1) inside = true;  // cluster points lie on the star
-        else if (i1 != 0) inside = p4(q, 0.5 * (ta + tb)) < 0.0;
-        else inside = inf_inside;                         // the arc through t = inf
+        else if (i1 != 0) inside = p4(H.q, 0.5 * (ta + tb)) < 0.0;
+        else inside = H.inf_inside;                         // the arc through t = inf
         if (inside) {
             TauArc arcs[2];
             const int na = arc_between(ta, tb, arcs);
-            for (int k = 0; k < na; ++k) arc_gk(F, arcs[k].cc, arcs[k].sc, arcs[k].h, S, ct);
-        } else {
+            for (int k = 0; k < na; ++k) arc(arcs[k].cc, arcs[k].sc, arcs[k].h);
+        } else if (limbs) {
             double xa, ya, xb, yb;
             point_at(F, ta, xa, ya);
             point_at(F, tb, xb, yb);
@@ -854,7 +917,42 @@ GL_HD double occulted_hard(const SetConst& s, double x0, double y0, int* cls_out
             ct.limb();
         }
     }
+}
+
+// Occulted fraction from the three boundary sums.
+GL_HD double sums_delta(const SetConst& s, const Sums& S)
+{
     return (s.c0 * S.flat + s.c1 * S.lin + s.c2 * S.quad) * s.inv_phi;
+}
+
+// Hard samples (everything occulted_easy declines): intersection quartic,
+// near-limb whole ellipses, limb and ellipse arcs.
+template <class CT = NoCensus>
+GL_HD double occulted_hard(const SetConst& s, double x0, double y0, int* cls_out, CT& ct)
+{
+    HardPrep H;
+    hard_prepare(s, x0, y0, H, ct);
+    const int cls = hard_class(H);
+    if (cls_out) *cls_out = cls;
+    if (cls == CLS_OUT) return 0.0;
+    if (cls == CLS_FULL && H.ntc == 0) {
+        double sl;
+        int lev;
+        const bool ok = trap_lin_nested(s, x0, y0, sl, lev);
+        ct.trap(8 << (lev - 1));
+        if (ok) return whole_delta(s, x0, y0, sl);
+        H.tc[0] = H.t_near;  // did not settle: cluster at the point nearest the limb
+        H.ntc = 1;
+    }
+    double bp[7];
+    int kind[7];
+    const int nb = hard_breaks(H, bp, kind);
+    Frame F;
+    make_frame(s, x0, y0, H.c0a, H.s0a, F);
+    Sums S = {0.0, 0.0, 0.0};
+    boundary_walk(H, F, bp, kind, nb, S, true,
+                  [&](double cc, double sc, double h) { arc_gk(F, cc, sc, h, S, ct); }, ct);
+    return sums_delta(s, S);
 }
 
 // Occulted fraction delta for ellipse centre (x0, y0).
@@ -906,6 +1004,7 @@ constexpr int kFlopWhole = 30;      // whole-ellipse closed forms and singularit
 constexpr int kFlopPartial = 160;   // quartic set-up, frame, break points
 constexpr int kFlopIter = 18;       // one safeguarded-Newton step on the quartic or cubic
 constexpr int kFlopLimb = 30;       // one limb arc in closed form
+constexpr int kFlopArc = 20;        // one ellipse arc set up for the tau rule
 constexpr int kFlopTrapNode = 24;   // one trapezoid node (mu integrand + rotation)
 constexpr int kFlopGKPiece = 21 * 64 + 10;  // one 21-node Gauss-Kronrod piece
 

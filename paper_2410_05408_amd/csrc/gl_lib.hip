@@ -1,18 +1,33 @@
 // gl_lib.hip -- kernels and C ABI of the oblate transit light-curve library.
 //
 // Pipeline of one gl_lightcurve_batch call (all on the caller's stream):
-//   k_prep     one thread per parameter set: domain checks, derived constants
-//              (projected ellipse from eqs. dx, dy1, dy2, orbit, limb darkening),
-//              CSR segment checks, number of 64-output chunks per set.
-//   k_scan     one workgroup: exclusive scan of the chunk counts.
-//   k_fill     one wavefront per chunk of 64 consecutive outputs of one set:
-//              outputs whose exposure cannot overlap the star are written as
-//              1 (NaN for an invalid set); a 64-bit mask of the others is kept.
-//   k_compute  persistent wavefronts pull chunks from an atomic head; for each
-//              chunk with work, lanes take (output, sub-sample) pairs, evaluate
-//              the instantaneous flux in FP64 and the sub-samples of an output
-//              are averaged in a fixed order through LDS (deterministic).
-// The four launches are captured once into a HIP graph and replayed while the
+//   k_prep      one thread per parameter set: domain checks, derived constants
+//               (projected ellipse from eqs. dx, dy1, dy2, orbit, limb darkening),
+//               CSR segment checks, number of 64-output chunks per set.
+//   k_scan      one workgroup: exclusive scan of the chunk counts.
+//   k_window    one wavefront per 4 chunks of 64 consecutive outputs of one set:
+//               outputs whose exposure cannot overlap the star are written as
+//               1 (NaN for an invalid set); chunks with in-window outputs get
+//               flux slots for their sub-samples, a work-chunk entry and one
+//               group entry per 64 sub-samples.
+//   k_classify  one wavefront per group: each sub-sample is classified by its
+//               ellipse centre: off the disk (flux 1 now), whole ellipse well
+//               inside (trapezoid list, sorted by rule order), hard (hard list).
+//   k_trap      one thread per trapezoid entry: mu integral of the whole ellipse.
+//   k_hard      one thread per hard entry: intersection quartic, break points,
+//               limb arcs in closed form, ellipse arcs appended to an arc list;
+//               whole ellipses near the limb go to the nested-trapezoid list.
+//   k_nested    one thread per nested entry: nested periodic trapezoid.
+//   k_gk<L>     level L = 0..4 of the self-checking arc rule: one thread per
+//               Gauss-Kronrod piece (2^L pieces per arc, summed across lanes);
+//               arcs whose error estimate is too large go on to level L + 1;
+//               the arc that completes a hard sample writes its flux.
+//   k_average   one wavefront per listed chunk: box average of each output's
+//               sub-samples in a fixed order (deterministic).
+//   k_compute   the fused per-lane evaluation, for chunks whose sub-samples
+//               did not fit the work-list capacities.
+// Every list is appended through per-shard counters (see kShards).  The
+// launches are captured once into a HIP graph and replayed while the
 // arguments stay the same.
 #include <hip/hip_runtime.h>
 
@@ -29,17 +44,99 @@ namespace {
 constexpr int kChunk = 64;
 constexpr int kScanThreads = 1024;
 
-constexpr int kCensus = 8;
+constexpr int kCensus = 10;
+constexpr int kLevels = gl::kArcMaxLevel + 1;
+
+// Appended work lists are split into kShards shards, each with its own
+// counter on its own 128-byte line and its own region of the list: a
+// wavefront appends to shard (its workgroup index mod kShards), so the
+// atomics spread over many L2 lines instead of serialising on one.
+constexpr int kShards = 32;
+enum : int {
+    L_SUB = 0,   // sub-sample flux slots (reserved per chunk)
+    L_WC,        // chunks evaluated through the lists
+    L_GRP,       // groups of up to 64 sub-samples of one chunk
+    L_TRAP,      // whole ellipses for the trapezoid stage
+    L_HARD,      // hard samples
+    L_NEST,      // whole ellipses near the limb for the nested trapezoid
+    L_ARC,       // ellipse arcs
+    L_LVL1,      // arcs entering level 1 .. kArcMaxLevel of the arc rule
+    kLists = L_LVL1 + gl::kArcMaxLevel
+};
+
+struct alignas(128) LineCount {
+    unsigned long long v;
+    unsigned long long pad[15];
+};
 
 struct Counters {
     unsigned long long total_chunks;  // written by k_scan
-    unsigned long long head;          // work head of k_compute (reset by k_prep)
+    unsigned long long head;          // work head of the surrogate path
     unsigned int status;              // bit 0: invalid set, bit 1: bad CSR segment, bit 2: non-finite time
     unsigned int pad;
+    unsigned long long n_fb;          // chunks queued for the fused kernel
+    unsigned long long fb_head;       // work head of the fused kernel
     // work census (census launches only): in-window sub-samples, whole-on-star,
-    // intersecting, in-window but off the star, full-turn rules, arc rules,
-    // Newton steps, limb arcs
+    // intersecting, in-window but off the star, trapezoid nodes of the rigorous
+    // rule, Gauss-Kronrod pieces, Newton steps, limb arcs, nested-trapezoid
+    // nodes, ellipse arcs
     unsigned long long census[kCensus];
+    LineCount lc[kLists][kShards];    // shard counters (reset by k_prep)
+};
+
+// One sub-sample handed to the trapezoid or the hard stage.
+struct Entry {
+    double x0, y0;  // ellipse centre
+    int set;        // -1: empty slot (its chunk overflowed a list)
+    int sub;        // flux slot; trapezoid entries carry the rule order in bits 27..30
+};
+constexpr int kSubBits = 27;
+constexpr int kSubMask = (1 << kSubBits) - 1;
+
+// A chunk on the work lists and its first flux slot.
+struct WorkChunk {
+    int64_t c, base;  // base -1: empty slot
+};
+
+// Up to 64 consecutive sub-samples [f0, min(f0 + 64, cnt)) of chunk c.
+struct Group {
+    int64_t c, base;  // c -1: empty slot
+    int f0, cnt;
+};
+
+// A hard sample after its boundary walk: the frame anchor, the closed-form
+// limb sums and its range in the arc list.  `left` counts the arcs still
+// open; the arc that closes the last one combines the sums.
+struct HardRec {
+    double x0, y0, c0a, s0a;
+    gl::Sums limb;
+    int set, sub;
+    int arc_begin, n_arcs;
+    int left, pad;
+};
+
+// One ellipse arc on the star (tau-rule description) of the hard sample in
+// slot `hard`.
+struct ArcRec {
+    double cc, sc, h;
+    int hard;  // -1: empty slot
+    int pad;
+};
+
+// Device pointers and per-shard capacities of the work lists.
+struct Pipe {
+    double* fsub;          // sub-sample fluxes
+    WorkChunk* wc;
+    Group* grp;
+    int64_t* fb_chunk;     // chunks for the fused kernel
+    Entry* trap;
+    Entry* hard;
+    Entry* nest;
+    HardRec* hrec;         // indexed like `hard`
+    ArcRec* arcs;
+    gl::Sums* arc_res;     // indexed like `arcs`
+    int* lvl[kLevels];     // arcs re-split at level L (index 0 unused)
+    int64_t scap[kLists];  // entries per shard
 };
 
 // ---------------------------------------------------------------- kernels
@@ -53,8 +150,11 @@ __global__ void k_prep(const double* __restrict__ params, int64_t n_sets,
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s == 0) {
         ctr->head = 0ull;
+        ctr->n_fb = ctr->fb_head = 0ull;
         for (int i = 0; i < kCensus; ++i) ctr->census[i] = 0ull;
     }
+    for (int64_t i = s; i < (int64_t)kLists * kShards; i += (int64_t)gridDim.x * blockDim.x)
+        ctr->lc[i / kShards][i % kShards].v = 0ull;
     if (s >= n_sets) return;
     double p[GL_NPARAM];
 #pragma unroll
@@ -145,39 +245,570 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-__global__ void __launch_bounds__(256)
-k_fill(const double* __restrict__ times, int64_t n_sets, int shared_grid, int64_t cps,
-       const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_begin,
-       const int64_t* __restrict__ seg_len, const int64_t* __restrict__ chunk_off,
-       Counters* __restrict__ ctr, unsigned long long* __restrict__ masks,
-       int* __restrict__ chunk_set, double* __restrict__ out)
+// ---------------------------------------------------------------- work-list helpers
+__device__ __forceinline__ unsigned long long lanemask_lt(int lane)
+{
+    return (1ull << lane) - 1ull;
+}
+
+// Adds a wave's census counts (one atomic per counter).
+__device__ __forceinline__ void census_add(Counters* ctr, int idx, unsigned long long v)
+{
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(&ctr->census[idx], v);
+}
+
+// Reserves m slots of list l in shard j for the calling wavefront (called by
+// every lane; lane 0 does the atomic): returns the position in the shard.
+__device__ __forceinline__ int64_t reserve(Counters* ctr, int l, int j, unsigned long long m)
+{
+    unsigned long long p = 0;
+    if ((threadIdx.x & 63) == 0 && m) p = atomicAdd(&ctr->lc[l][j].v, m);
+    return uniform64((int64_t)p);
+}
+
+// Wavefront view of a sharded list: lanes 0..kShards-1 hold the shard counts
+// (clamped to the capacity) and their inclusive prefix sums.
+struct ShardMap {
+    int64_t cnt, incl, total;
+};
+
+__device__ __forceinline__ ShardMap shard_map(const Counters* ctr, int l, int64_t scap)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t c = uniform64((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    ShardMap m;
+    m.cnt = lane < kShards ? std::min<int64_t>((int64_t)ctr->lc[l][lane].v, scap) : 0;
+    m.incl = m.cnt;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t v = __shfl_up(m.incl, d);
+        if (lane >= d) m.incl += v;
+    }
+    m.total = __shfl(m.incl, kShards - 1);
+    return m;
+}
+
+// List slot of the g-th entry (0 <= g < total) in shard order; every lane of
+// the wavefront must call it.
+__device__ __forceinline__ int64_t shard_slot(const ShardMap& m, int64_t g, int64_t scap)
+{
+    int j = 0;
+#pragma unroll
+    for (int step = kShards / 2; step >= 1; step >>= 1) {
+        const int64_t v = __shfl(m.incl, j + step - 1);
+        if (v <= g) j += step;
+    }
+    const int64_t excl = __shfl(m.incl, j) - __shfl(m.cnt, j);
+    return (int64_t)j * scap + (g - excl);
+}
+
+// Queues chunk c for the fused kernel once (the first caller wins).
+__device__ __forceinline__ void to_fused(Counters* ctr, const Pipe& P, int* chunk_fb, int64_t c)
+{
+    if (atomicExch(&chunk_fb[c], 1) == 0) P.fb_chunk[atomicAdd(&ctr->n_fb, 1ull)] = c;
+}
+
+// Window test: one wavefront per group of kWinChunks consecutive chunks (their
+// memory operations overlap): outputs whose exposure cannot overlap the star
+// are written as 1 (NaN for an invalid set or a non-finite time); a 64-bit
+// mask of the others and the chunk's set are kept.  With `lists`, every chunk
+// with in-window outputs gets its flux slots, a work-chunk entry and one group
+// entry per 64 sub-samples (one reservation per list for the wavefront); a
+// chunk that does not fit is queued for the fused kernel.
+constexpr int kWinChunks = 4;
+
+__global__ void __launch_bounds__(256)
+k_window(const double* __restrict__ times, int64_t n_sets, int shared_grid, int64_t cps,
+         const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_begin,
+         const int64_t* __restrict__ seg_len, const int64_t* __restrict__ chunk_off,
+         Counters* __restrict__ ctr, unsigned long long* __restrict__ masks,
+         int* __restrict__ chunk_set, double* __restrict__ out, int lists, Pipe P,
+         int* __restrict__ chunk_fb)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t g = uniform64((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     const int64_t total = (int64_t)ctr->total_chunks;
-    if (c >= total) return;
-    const int64_t s = uniform64(shared_grid ? c / cps : set_of_chunk(chunk_off, n_sets, c));
-    const int64_t lc = c - chunk_off[s];
-    const int64_t pos = lc * kChunk + lane;  // position inside the set's segment
-    const bool in_seg = pos < seg_len[s];
-    const int64_t i = seg_begin[s] + pos;
-    const gl::SetConst& S = sc[s];
-    bool work = false;
-    if (in_seg) {
-        const double t = shared_grid ? times[pos] : times[i];
-        if (!S.valid || !gl::finite_d(t)) {
-            out[i] = __builtin_nan("");
-            if (S.valid) atomicOr(&ctr->status, 4u);
-        } else {
-            const double tau = gl::phase_time(S, t);
-            work = fabs(tau) < S.half_win + 0.5 * S.t_exp;
-            if (!work) out[i] = 1.0;
+    int cnt[kWinChunks];
+#pragma unroll
+    for (int k = 0; k < kWinChunks; ++k) {
+        cnt[k] = 0;
+        const int64_t c = g * kWinChunks + k;
+        if (c >= total) continue;
+        const int64_t s = uniform64(shared_grid ? c / cps : set_of_chunk(chunk_off, n_sets, c));
+        const int64_t pos = (c - chunk_off[s]) * kChunk + lane;  // position inside the set's segment
+        const bool in_seg = pos < seg_len[s];
+        const int64_t i = seg_begin[s] + pos;
+        const gl::SetConst& S = sc[s];
+        bool work = false;
+        if (in_seg) {
+            const double t = shared_grid ? times[pos] : times[i];
+            if (!S.valid || !gl::finite_d(t)) {
+                out[i] = __builtin_nan("");
+                if (S.valid) atomicOr(&ctr->status, 4u);
+            } else {
+                const double tau = gl::phase_time(S, t);
+                work = fabs(tau) < S.half_win + 0.5 * S.t_exp;
+                if (!work) out[i] = 1.0;
+            }
+        }
+        const unsigned long long m = __ballot(work);
+        if (lane == 0) {
+            masks[c] = m;
+            chunk_set[c] = (int)s;
+        }
+        if (m) cnt[k] = __popcll(m) * S.n_ss;
+    }
+    if (!lists) return;
+    int tot_sub = 0, tot_wc = 0, tot_grp = 0;
+#pragma unroll
+    for (int k = 0; k < kWinChunks; ++k) {
+        tot_sub += cnt[k];
+        tot_wc += cnt[k] > 0;
+        tot_grp += (cnt[k] + kChunk - 1) / kChunk;
+    }
+    if (tot_wc == 0) return;
+    const int shard = (int)(g % kShards);
+    int64_t os = reserve(ctr, L_SUB, shard, (unsigned long long)tot_sub);
+    int64_t ow = reserve(ctr, L_WC, shard, (unsigned long long)tot_wc);
+    int64_t og = reserve(ctr, L_GRP, shard, (unsigned long long)tot_grp);
+    const int64_t scs = P.scap[L_SUB], scw = P.scap[L_WC], scg = P.scap[L_GRP];
+#pragma unroll
+    for (int k = 0; k < kWinChunks; ++k) {
+        if (cnt[k] == 0) continue;
+        const int64_t c = g * kWinChunks + k;
+        const int ng = (cnt[k] + kChunk - 1) / kChunk;
+        const bool ok = os + cnt[k] <= scs && ow < scw && og + ng <= scg;
+        const int64_t base = ok ? (int64_t)shard * scs + os : -1;
+        if (lane == 0) {
+            chunk_fb[c] = 0;
+            if (ow < scw) P.wc[(int64_t)shard * scw + ow] = WorkChunk{c, base};
+        }
+        if (lane < ng && og + lane < scg)
+            P.grp[(int64_t)shard * scg + og + lane] = Group{ok ? c : -1, base, lane * kChunk, cnt[k]};
+        if (!ok && lane == 0) to_fused(ctr, P, chunk_fb, c);
+        os += cnt[k];
+        ow += 1;
+        og += ng;
+    }
+}
+
+// Classification: one wavefront per group of up to 64 sub-samples of one
+// chunk, classified by the ellipse centre: off the disk (flux 1 now), whole
+// ellipse provably well inside (trapezoid list, written sorted by rule order
+// within the group so that neighbouring lanes of k_trap run the same number
+// of nodes), everything else (hard list).  A group that does not fit the
+// lists sends its chunk to the fused kernel.
+template <bool CENSUS>
+__global__ void __launch_bounds__(64)
+k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst* __restrict__ sc,
+           const int64_t* __restrict__ seg_begin, const int64_t* __restrict__ chunk_off,
+           Counters* __restrict__ ctr, Pipe P, const unsigned long long* __restrict__ masks,
+           const int* __restrict__ chunk_set, int* __restrict__ chunk_fb)
+{
+    __shared__ double lds_t[kChunk];  // times of the chunk's in-window outputs, compacted
+    const int lane = threadIdx.x;
+    const unsigned long long lt = lanemask_lt(lane);
+    const int shard = (int)(blockIdx.x % kShards);
+    const int64_t gcap = P.scap[L_GRP];
+    const ShardMap m = shard_map(ctr, L_GRP, gcap);
+    unsigned long long c_in = 0, c_whole = 0, c_off = 0;
+    for (int64_t gi = blockIdx.x; gi < m.total; gi += gridDim.x) {
+        const Group G = P.grp[shard_slot(m, gi, gcap)];
+        const int64_t c = uniform64(G.c);
+        if (c < 0) continue;
+        const int64_t base = uniform64(G.base);
+        const int f0 = __builtin_amdgcn_readfirstlane(G.f0), cnt = __builtin_amdgcn_readfirstlane(G.cnt);
+        const unsigned long long M = (unsigned long long)uniform64((int64_t)masks[c]);
+        const int64_t s = uniform64(chunk_set[c]);
+        const gl::SetConst& S = sc[s];
+        const int64_t lc = c - chunk_off[s];
+        const int64_t tb = shared_grid ? lc * kChunk : seg_begin[s] + lc * kChunk;
+        if ((M >> lane) & 1ull) lds_t[__popcll(M & lt)] = times[tb + lane];
+        __syncthreads();
+        const int nss = S.n_ss;
+        const double inv_nss = 1.0 / (double)nss;
+        const float inv_nss_f = 1.0f / (float)nss;
+        const int f = f0 + lane;
+        int cls = gl::kOffDisk - 1;  // no sample on this lane
+        double x0 = 0.0, y0 = 0.0;
+        if (f < cnt) {
+            // f / nss for f < 4096, nss <= 64 from a float product (exact floor)
+            const int o = (int)(((float)f + 0.5f) * inv_nss_f), j = f - o * nss;
+            const double t = lds_t[o] + (((double)j + 0.5) * inv_nss - 0.5) * S.t_exp;
+            cls = gl::centre_at(S, t, x0, y0) ? gl::easy_class(S, x0, y0) : gl::kOffDisk;
+            if (cls == gl::kOffDisk) P.fsub[base + f] = 1.0;
+            if (CENSUS) {
+                c_in += 1;
+                c_whole += cls >= 0;
+                c_off += cls == gl::kOffDisk;
+            }
+        }
+        const int sub = (int)(base + f);
+        bool fb = false;
+        const unsigned long long mt = __ballot(cls >= 0);
+        if (mt) {
+            const int64_t tp = reserve(ctr, L_TRAP, shard, (unsigned long long)__popcll(mt));
+            const int64_t tcap = P.scap[L_TRAP];
+            Entry* tl = P.trap + (int64_t)shard * tcap;
+            if (tp + __popcll(mt) > tcap) {
+                // slots reserved below the capacity are marked empty
+                const int64_t slot = tp + __popcll(mt & lt);
+                if (cls >= 0 && slot < tcap) tl[slot].set = -1;
+                fb = true;
+            } else {
+                int rank = 0;
+#pragma unroll
+                for (int k = 0; k < gl::kTrapOrders; ++k) {
+                    const unsigned long long mk = __ballot(cls == k);
+                    rank += (k < cls) ? __popcll(mk) : (k == cls ? __popcll(mk & lt) : 0);
+                }
+                if (cls >= 0) tl[tp + rank] = Entry{x0, y0, (int)s, sub | (cls << kSubBits)};
+            }
+        }
+        const unsigned long long mh = __ballot(cls == gl::kHard);
+        if (mh) {
+            const int64_t hp = reserve(ctr, L_HARD, shard, (unsigned long long)__popcll(mh));
+            const int64_t hcap = P.scap[L_HARD];
+            Entry* hl = P.hard + (int64_t)shard * hcap;
+            const int64_t slot = hp + __popcll(mh & lt);
+            if (hp + __popcll(mh) > hcap) {
+                if (cls == gl::kHard && slot < hcap) hl[slot].set = -1;
+                fb = true;
+            } else if (cls == gl::kHard) {
+                hl[slot] = Entry{x0, y0, (int)s, sub};
+            }
+        }
+        if (fb && lane == 0) to_fused(ctr, P, chunk_fb, c);
+        __syncthreads();
+    }
+    if (CENSUS) {
+        census_add(ctr, 0, c_in);
+        census_add(ctr, 1, c_whole);
+        census_add(ctr, 3, c_off);
+    }
+}
+
+// Whole ellipses well inside the disk: one entry per thread, the trapezoid
+// order was chosen by k_classify from the singularity bound.
+template <bool CENSUS>
+__global__ void __launch_bounds__(256)
+k_trap(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t scap = P.scap[L_TRAP];
+    const ShardMap m = shard_map(ctr, L_TRAP, scap);
+    unsigned long long nodes = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); g0 < m.total; g0 += stride) {
+        const int64_t g = g0 + lane;
+        const int64_t slot = shard_slot(m, g < m.total ? g : 0, scap);
+        if (g >= m.total) continue;
+        const Entry e = P.trap[slot];
+        if (e.set < 0) continue;  // slot of an overflowing chunk
+        const int oi = e.sub >> kSubBits, sub = e.sub & kSubMask;
+        const gl::SetConst& S = sc[e.set];
+        const double sl = gl::trap_lin_inl(S, e.x0, e.y0, oi);
+        P.fsub[sub] = 1.0 - gl::whole_delta(S, e.x0, e.y0, sl);
+        if (CENSUS) nodes += gl::kTrapN[oi];
+    }
+    if (CENSUS) census_add(ctr, 4, nodes);
+}
+
+// Hard entries: intersection quartic and break points per thread; the limb
+// arcs are summed in closed form, the ellipse arcs are appended to the arc
+// list (one reservation per wavefront, positions from a wavefront scan).
+// Samples off the disk get their flux here; whole ellipses near the limb with
+// no cluster point go to the nested-trapezoid list.  If the arc list is full,
+// the arcs are integrated in place.
+template <bool CENSUS>
+__global__ void __launch_bounds__(64)
+k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
+{
+    const int lane = threadIdx.x;
+    const unsigned long long lt = lanemask_lt(lane);
+    const int shard = (int)(blockIdx.x % kShards);
+    const int64_t scap = P.scap[L_HARD], acap = P.scap[L_ARC], ncap = P.scap[L_NEST];
+    const ShardMap m = shard_map(ctr, L_HARD, scap);
+    unsigned long long c_whole = 0, c_part = 0, c_off = 0, c_arcs = 0;
+    gl::Census ct;
+    gl::NoCensus nc;
+    ArcRec* al = P.arcs + (int64_t)shard * acap;
+    for (int64_t g0 = (int64_t)blockIdx.x * 64; g0 < m.total; g0 += (int64_t)gridDim.x * 64) {
+        const int64_t g = g0 + lane;
+        const int64_t slot = shard_slot(m, g < m.total ? g : 0, scap);
+        Entry e{0.0, 0.0, -1, 0};
+        if (g < m.total) e = P.hard[slot];
+        const bool valid = g < m.total && e.set >= 0;
+        if (g < m.total && !valid) P.hrec[slot].n_arcs = 0;  // slot of an overflowing chunk
+        gl::HardPrep H;
+        double bp[7];
+        int kind[7];
+        int nb = 0, na = 0;
+        bool open = false, nested = false;
+        if (valid) {
+            const gl::SetConst& S = sc[e.set];
+            if (CENSUS) gl::hard_prepare<gl::Census, true>(S, e.x0, e.y0, H, ct);
+            else gl::hard_prepare<gl::NoCensus, true>(S, e.x0, e.y0, H, nc);
+            const int cls = gl::hard_class(H);
+            if (cls == gl::CLS_FULL && H.ntc == 0) nested = true;
+            else if (cls != gl::CLS_OUT) open = true;
+            if (CENSUS) {
+                c_off += cls == gl::CLS_OUT;
+                c_whole += cls == gl::CLS_FULL;
+                c_part += cls == gl::CLS_PARTIAL;
+            }
+            if (open) {
+                nb = gl::hard_breaks(H, bp, kind);
+                gl::Frame F0{};
+                gl::Sums none{0.0, 0.0, 0.0};
+                gl::boundary_walk(H, F0, bp, kind, nb, none, false,
+                                  [&](double, double, double) { ++na; }, nc);
+            } else {
+                if (!nested) P.fsub[e.sub] = 1.0;
+                P.hrec[slot].n_arcs = 0;
+            }
+        }
+        // nested-trapezoid list
+        const unsigned long long mn = __ballot(nested);
+        if (mn) {
+            const int64_t np = reserve(ctr, L_NEST, shard, (unsigned long long)__popcll(mn));
+            const int64_t ns = np + __popcll(mn & lt);
+            if (nested) {
+                if (ns < ncap) {
+                    P.nest[(int64_t)shard * ncap + ns] = e;
+                } else {
+                    // list shard full: the nested rule here (rare)
+                    double sl;
+                    int lev;
+                    if (gl::trap_lin_nested(sc[e.set], e.x0, e.y0, sl, lev)) {
+                        P.fsub[e.sub] = 1.0 - gl::whole_delta(sc[e.set], e.x0, e.y0, sl);
+                    } else {
+                        H.tc[0] = H.t_near;
+                        H.ntc = 1;
+                        open = true;
+                        nb = gl::hard_breaks(H, bp, kind);
+                        na = 0;  // integrated in place below
+                    }
+                }
+            }
+        }
+        // positions in the arc list: inclusive wavefront scan of na
+        int incl = na;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(incl, d);
+            if (lane >= d) incl += v;
+        }
+        const int wtotal = __shfl(incl, 63);
+        const int64_t ap = reserve(ctr, L_ARC, shard, (unsigned long long)wtotal);
+        const bool over = ap + wtotal > acap;
+        if (open) {
+            const gl::SetConst& S = sc[e.set];
+            gl::Frame F;
+            gl::make_frame(S, e.x0, e.y0, H.c0a, H.s0a, F);
+            gl::Sums Sm{0.0, 0.0, 0.0};
+            const int64_t first = ap + incl - na;
+            if (over || na == 0) {
+                if (CENSUS)
+                    gl::boundary_walk(H, F, bp, kind, nb, Sm, true,
+                                      [&](double cc, double scv, double h) { gl::arc_gk(F, cc, scv, h, Sm, ct); }, ct);
+                else
+                    gl::boundary_walk(H, F, bp, kind, nb, Sm, true,
+                                      [&](double cc, double scv, double h) { gl::arc_gk(F, cc, scv, h, Sm, nc); }, nc);
+                P.fsub[e.sub] = 1.0 - gl::sums_delta(S, Sm);
+                P.hrec[slot].n_arcs = 0;
+                // this lane's reserved arc slots below the capacity are marked empty
+                for (int64_t k = first; k < first + na && k < acap; ++k) al[k].hard = -1;
+            } else {
+                int64_t k = first;
+                if (CENSUS)
+                    gl::boundary_walk(H, F, bp, kind, nb, Sm, true,
+                                      [&](double cc, double scv, double h) { al[k++] = ArcRec{cc, scv, h, (int)slot, 0}; }, ct);
+                else
+                    gl::boundary_walk(H, F, bp, kind, nb, Sm, true,
+                                      [&](double cc, double scv, double h) { al[k++] = ArcRec{cc, scv, h, (int)slot, 0}; }, nc);
+                P.hrec[slot] = HardRec{e.x0, e.y0, H.c0a, H.s0a, Sm, e.set, e.sub,
+                                       (int)((int64_t)shard * acap + first), na, na, 0};
+                if (CENSUS) c_arcs += na;
+            }
         }
     }
-    const unsigned long long m = __ballot(work);
-    if (lane == 0) {
-        masks[c] = m;
-        chunk_set[c] = (int)s;
+    if (CENSUS) {
+        census_add(ctr, 1, c_whole);
+        census_add(ctr, 2, c_part);
+        census_add(ctr, 3, c_off);
+        census_add(ctr, 6, (unsigned long long)ct.iters);
+        census_add(ctr, 7, (unsigned long long)ct.limbs);
+        census_add(ctr, 8, (unsigned long long)ct.trap_nodes);
+        census_add(ctr, 9, c_arcs);
+        census_add(ctr, 5, (unsigned long long)ct.arcs);  // pieces integrated in place
+    }
+}
+
+// Whole ellipses near the limb with no cluster point: nested periodic
+// trapezoid 8 -> 64 per thread; a sample whose rule does not settle takes the
+// cluster-arc route in place (rare).
+template <bool CENSUS>
+__global__ void __launch_bounds__(64)
+k_nested(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
+{
+    const int lane = threadIdx.x;
+    const int64_t scap = P.scap[L_NEST];
+    const ShardMap m = shard_map(ctr, L_NEST, scap);
+    unsigned long long nodes = 0;
+    gl::Census ct;
+    gl::NoCensus nc;
+    for (int64_t g0 = (int64_t)blockIdx.x * 64; g0 < m.total; g0 += (int64_t)gridDim.x * 64) {
+        const int64_t g = g0 + lane;
+        const int64_t slot = shard_slot(m, g < m.total ? g : 0, scap);
+        if (g >= m.total) continue;
+        const Entry e = P.nest[slot];
+        const gl::SetConst& S = sc[e.set];
+        double sl;
+        int lev;
+        const bool ok = gl::trap_lin_nested_inl(S, e.x0, e.y0, sl, lev);
+        if (CENSUS) nodes += 8 << (lev - 1);
+        if (ok) {
+            P.fsub[e.sub] = 1.0 - gl::whole_delta(S, e.x0, e.y0, sl);
+            continue;
+        }
+        gl::HardPrep H;
+        if (CENSUS) gl::hard_prepare(S, e.x0, e.y0, H, ct);
+        else gl::hard_prepare(S, e.x0, e.y0, H, nc);
+        H.tc[0] = H.t_near;  // did not settle: cluster at the point nearest the limb
+        H.ntc = 1;
+        double bp[7];
+        int kind[7];
+        const int nb = gl::hard_breaks(H, bp, kind);
+        gl::Frame F;
+        gl::make_frame(S, e.x0, e.y0, H.c0a, H.s0a, F);
+        gl::Sums Sm{0.0, 0.0, 0.0};
+        if (CENSUS)
+            gl::boundary_walk(H, F, bp, kind, nb, Sm, true,
+                              [&](double cc, double scv, double h) { gl::arc_gk(F, cc, scv, h, Sm, ct); }, ct);
+        else
+            gl::boundary_walk(H, F, bp, kind, nb, Sm, true,
+                              [&](double cc, double scv, double h) { gl::arc_gk(F, cc, scv, h, Sm, nc); }, nc);
+        P.fsub[e.sub] = 1.0 - gl::sums_delta(S, Sm);
+    }
+    if (CENSUS) {
+        census_add(ctr, 8, nodes);
+        census_add(ctr, 6, (unsigned long long)ct.iters);
+        census_add(ctr, 5, (unsigned long long)ct.arcs);
+    }
+}
+
+// Level L of the self-checking arc rule: arc tau in [-h, h] split into 2^L
+// equal pieces, one clustered Gauss-Kronrod 10/21 piece per thread; the 2^L
+// lanes of an arc sum their Kronrod sums and differences by a butterfly (same
+// order on every lane).  Accepted when the summed difference is within the
+// tolerance (or at the last level); otherwise the arc enters level L + 1.
+// The arc that closes the last open arc of its hard sample adds the limb sums
+// and every arc of the sample in list order and writes the sample's flux.
+template <int L, bool CENSUS>
+__global__ void __launch_bounds__(64)
+k_gk(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
+{
+    constexpr int np = 1 << L;
+    constexpr int lin = (L == 0) ? L_ARC : L_LVL1 + L - 1;                  // input list
+    constexpr int lout = (L < gl::kArcMaxLevel) ? L_LVL1 + L : L_LVL1;      // output list
+    const int lane = threadIdx.x;
+    const unsigned long long lt = lanemask_lt(lane);
+    const int64_t scap = P.scap[lin];
+    const ShardMap m = shard_map(ctr, lin, scap);
+    const int64_t n = m.total << L;
+    unsigned long long pieces = 0;
+    for (int64_t p0 = (int64_t)blockIdx.x * 64; p0 < n; p0 += (int64_t)gridDim.x * 64) {
+        const int64_t p = p0 + lane;
+        const bool valid = p < n;
+        const int q = (int)(p & (np - 1));
+        const int64_t slot = shard_slot(m, valid ? (p >> L) : 0, scap);
+        int a = -1;
+        ArcRec A{0.0, 0.0, 0.0, -1, 0};
+        gl::Sums K{0.0, 0.0, 0.0};
+        double err = 0.0;
+        if (valid) {
+            a = (L == 0) ? (int)slot : P.lvl[L][slot];
+            A = P.arcs[a];
+            if (A.hard >= 0) {  // (negative: slot of an overflowing wavefront, skipped)
+                const HardRec& R = P.hrec[A.hard];
+                const gl::SetConst& S = sc[R.set];
+                gl::Frame F;
+                gl::make_frame(S, R.x0, R.y0, R.c0a, R.s0a, F);
+                const double half = A.h / np;
+                err = gl::gk_piece<true>(F, A.cc, A.sc, -A.h + (2 * q + 1) * half, half, K);
+                if (CENSUS) pieces += 1;
+            }
+        }
+#pragma unroll
+        for (int d = 1; d < np; d <<= 1) {
+            K.flat += __shfl_xor(K.flat, d);
+            K.lin += __shfl_xor(K.lin, d);
+            K.quad += __shfl_xor(K.quad, d);
+            err += __shfl_xor(err, d);
+        }
+        const bool lead = valid && q == 0 && A.hard >= 0;
+        const bool accept = err <= gl::kArcTol || L == gl::kArcMaxLevel;
+        if (lead && accept) {
+            P.arc_res[a] = K;
+            HardRec& R = P.hrec[A.hard];
+            const int before = __hip_atomic_fetch_add(&R.left, -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (before == 1) {
+                gl::Sums S = R.limb;
+                for (int k = 0; k < R.n_arcs; ++k) {
+                    const gl::Sums& B = P.arc_res[R.arc_begin + k];
+                    S.flat += B.flat;
+                    S.lin += B.lin;
+                    S.quad += B.quad;
+                }
+                P.fsub[R.sub] = 1.0 - gl::sums_delta(sc[R.set], S);
+            }
+        }
+        if (L < gl::kArcMaxLevel) {
+            // an arc re-enters the shard of its home slot in the arc list, so a
+            // level-list shard never holds more arcs than an arc-list shard
+            const bool want = lead && !accept;
+            const int64_t acap = P.scap[L_ARC];
+            const int hs = want ? (int)(a / acap) : -1;
+            unsigned long long pending = __ballot(want);
+            while (pending) {
+                const int j = __shfl(hs, __builtin_ctzll(pending));
+                const unsigned long long mj = __ballot(want && hs == j);
+                const int64_t op = reserve(ctr, lout, j, (unsigned long long)__popcll(mj));
+                if (want && hs == j)
+                    P.lvl[L + 1 < kLevels ? L + 1 : L][(int64_t)j * P.scap[lout] + op + __popcll(mj & lt)] = a;
+                pending &= ~mj;
+            }
+        }
+    }
+    if (CENSUS) census_add(ctr, 5, pieces);
+}
+
+// One wavefront per listed chunk: each in-window output averages its
+// sub-sample fluxes in order.
+__global__ void __launch_bounds__(64)
+k_average(const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_begin,
+          const int64_t* __restrict__ chunk_off, const Counters* __restrict__ ctr, Pipe P,
+          const unsigned long long* __restrict__ masks, const int* __restrict__ chunk_set,
+          const int* __restrict__ chunk_fb, double* __restrict__ out)
+{
+    const int lane = threadIdx.x;
+    const int64_t wcap = P.scap[L_WC];
+    const ShardMap m = shard_map(ctr, L_WC, wcap);
+    for (int64_t w = blockIdx.x; w < m.total; w += gridDim.x) {
+        const WorkChunk W = P.wc[shard_slot(m, w, wcap)];
+        const int64_t base = uniform64(W.base), c = uniform64(W.c);
+        if (base < 0) continue;
+        if (__builtin_amdgcn_readfirstlane(chunk_fb[c])) continue;  // evaluated by the fused kernel
+        const unsigned long long M = (unsigned long long)uniform64((int64_t)masks[c]);
+        const int64_t s = uniform64(chunk_set[c]);
+        const int nss = sc[s].n_ss;
+        const int64_t i0 = seg_begin[s] + (c - chunk_off[s]) * kChunk;
+        if ((M >> lane) & 1ull) {
+            const int64_t o = __popcll(M & lanemask_lt(lane));
+            const double* f = P.fsub + base + o * nss;
+            double sum = 0.0;
+            for (int j = 0; j < nss; ++j) sum += f[j];
+            out[i0 + lane] = sum / (double)nss;
+        }
     }
 }
 
@@ -258,27 +889,23 @@ __global__ void GL_COMPUTE_ATTR
 k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst* __restrict__ sc,
           const int64_t* __restrict__ seg_begin, const int64_t* __restrict__ chunk_off,
           Counters* __restrict__ ctr, const unsigned long long* __restrict__ masks,
-          const int* __restrict__ chunk_set, double* __restrict__ out)
+          const int* __restrict__ chunk_set, const int64_t* __restrict__ fb_chunk,
+          double* __restrict__ out)
 {
     __shared__ double lds_f[kMaxSubLds];   // sub-sample fluxes of the chunk
     __shared__ short lds_def[kMaxSubLds];  // deferred (hard) sub-samples
     __shared__ int lds_idx[kChunk];        // chunk lanes with work, compacted
     const int lane = threadIdx.x;
-    const int64_t total = (int64_t)ctr->total_chunks;
+    const int64_t n_fb = (int64_t)ctr->n_fb;
     Counter<CENSUS> cnt;
     for (int i = 0; i < kCensus; ++i) cnt.v[i] = 0ull;
     for (;;) {
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(&ctr->head, (unsigned long long)kChunk);
-        base = (unsigned long long)uniform64((int64_t)base);  // lane 0's value
-        if ((int64_t)base >= total) break;
-        const int64_t my = (int64_t)base + lane;
-        const unsigned long long mym = (my < total) ? masks[my] : 0ull;
-        unsigned long long todo = __ballot(mym != 0ull);
-        while (todo) {
-            const int b = __builtin_ctzll(todo);
-            todo &= todo - 1ull;
-            const int64_t c = (int64_t)base + b;
+        unsigned long long k = 0;
+        if (lane == 0) k = atomicAdd(&ctr->fb_head, 1ull);
+        k = (unsigned long long)uniform64((int64_t)k);  // lane 0's value
+        if ((int64_t)k >= n_fb) break;
+        {
+            const int64_t c = uniform64(fb_chunk[k]);
             const unsigned long long M = (unsigned long long)uniform64((int64_t)masks[c]);
             const int64_t s = uniform64(chunk_set[c]);
             const gl::SetConst S = sc[s];
@@ -367,17 +994,13 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
     }
 }
 
-using ComputeFn = void (*)(const double*, int, const gl::SetConst*, const int64_t*,
-                           const int64_t*, Counters*, const unsigned long long*, const int*,
-                           double*);
-
 }  // namespace
 
 // ---------------------------------------------------------------- context
 struct gl_ctx {
     int device = 0;
     int n_cu = 256;
-    int waves_per_cu = 8;
+    int waves_per_cu = 16;  // persistent waves per CU of the list kernels
     bool use_graph = true;
     std::string err;
     // workspace
@@ -420,9 +1043,15 @@ struct gl_ctx {
     int* s_set = nullptr;
     int64_t* s_fb = nullptr;
     int64_t cap_sub = 0;
-    // per-launch timing (events around the compute kernel and the pipeline)
+    // work lists of the exact path (capacities in entries; 0 = default)
+    Pipe pipe{};
+    bool have_pipe = false;
+    int* chunk_fb = nullptr;  // per chunk: 1 = evaluated by the fused kernel
+    int64_t pipe_chunks = 0;  // length of the per-chunk arrays
+    int64_t want_sub = 0, want_hard = 0, want_arc = 0;
+    // per-launch timing: an event before the first and after every stage
     int t_slots = 0, t_used = 0;
-    hipEvent_t* ev = nullptr;  // 3 events per slot: pipeline start, compute start, end
+    hipEvent_t* ev = nullptr;  // (GL_NSTAGES + 1) events per slot
 };
 
 namespace {
@@ -467,8 +1096,22 @@ void free_sur(gl_ctx* ctx)
     ctx->cap_sub_chunks = ctx->cap_sub = 0;
 }
 
+void free_pipe(gl_ctx* ctx)
+{
+    Pipe& P = ctx->pipe;
+    void* b[] = {P.fsub, P.wc, P.grp, P.fb_chunk, P.trap, P.hard, P.nest, P.hrec, P.arcs, P.arc_res,
+                 ctx->chunk_fb};
+    for (void* q : b) (void)hipFree(q);
+    ctx->chunk_fb = nullptr;
+    for (int L = 0; L < kLevels; ++L) (void)hipFree(P.lvl[L]);
+    P = Pipe{};
+    ctx->have_pipe = false;
+    ctx->pipe_chunks = 0;
+}
+
 void free_ws(gl_ctx* ctx)
 {
+    free_pipe(ctx);
     free_sur(ctx);
     (void)hipFree(ctx->sc);
     (void)hipFree(ctx->seg_begin);
@@ -524,6 +1167,62 @@ gl_status ensure_ws(gl_ctx* ctx, int64_t n_sets, int64_t n_chunks)
     return GL_OK;
 }
 
+// Default work-list capacities: 16 Mi sub-samples (a chunk holds at most
+// 64 outputs x 64 sub-samples), a quarter of that of hard samples, two arcs
+// per hard sample, each split evenly over the shards.  About 1.5 GB of device
+// memory at the defaults, less for small batches.
+constexpr int64_t kDefSub = (int64_t)1 << 24;
+
+gl_status ensure_pipe(gl_ctx* ctx, int64_t n_chunks)
+{
+    const int64_t per_chunk = (int64_t)kChunk * 64;
+    int64_t cs = ctx->want_sub > 0 ? ctx->want_sub : std::min<int64_t>(kDefSub, n_chunks * per_chunk);
+    cs = std::max<int64_t>(std::min<int64_t>(cs, kSubMask - kShards), kShards);
+    int64_t ch = ctx->want_hard > 0 ? ctx->want_hard : std::max<int64_t>(cs / 4, kShards);
+    int64_t ca = ctx->want_arc > 0 ? ctx->want_arc : 2 * ch;
+    ch = std::max<int64_t>(std::min<int64_t>(ch, INT32_MAX / 2), kShards);
+    ca = std::max<int64_t>(std::min<int64_t>(ca, INT32_MAX / 2), kShards);
+    const int64_t nc = std::max<int64_t>(ctx->cap_chunks, n_chunks);
+    int64_t sc_[kLists];
+    sc_[L_SUB] = (cs + kShards - 1) / kShards;
+    sc_[L_TRAP] = sc_[L_SUB];
+    sc_[L_WC] = std::max<int64_t>(64, 2 * ((nc + kShards - 1) / kShards));
+    sc_[L_GRP] = std::max<int64_t>(64, sc_[L_SUB] / kChunk + sc_[L_WC]);
+    sc_[L_HARD] = (ch + kShards - 1) / kShards;
+    sc_[L_NEST] = sc_[L_HARD];
+    sc_[L_ARC] = (ca + kShards - 1) / kShards;
+    for (int L = 1; L < kLevels; ++L) sc_[L_LVL1 + L - 1] = sc_[L_ARC];
+    Pipe& P = ctx->pipe;
+    bool same = ctx->have_pipe && ctx->pipe_chunks >= n_chunks;
+    for (int l = 0; l < kLists && same; ++l) same = P.scap[l] == sc_[l];
+    if (same) return GL_OK;
+    drop_graph(ctx);
+    GL_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    free_pipe(ctx);
+    const int64_t K = kShards;
+    bool ok = hipMalloc(&P.fsub, sizeof(double) * K * sc_[L_SUB]) == hipSuccess &&
+              hipMalloc(&P.wc, sizeof(WorkChunk) * K * sc_[L_WC]) == hipSuccess &&
+              hipMalloc(&P.grp, sizeof(Group) * K * sc_[L_GRP]) == hipSuccess &&
+              hipMalloc(&P.fb_chunk, sizeof(int64_t) * nc) == hipSuccess &&
+              hipMalloc(&ctx->chunk_fb, sizeof(int) * nc) == hipSuccess &&
+              hipMalloc(&P.trap, sizeof(Entry) * K * sc_[L_TRAP]) == hipSuccess &&
+              hipMalloc(&P.hard, sizeof(Entry) * K * sc_[L_HARD]) == hipSuccess &&
+              hipMalloc(&P.nest, sizeof(Entry) * K * sc_[L_NEST]) == hipSuccess &&
+              hipMalloc(&P.hrec, sizeof(HardRec) * K * sc_[L_HARD]) == hipSuccess &&
+              hipMalloc(&P.arcs, sizeof(ArcRec) * K * sc_[L_ARC]) == hipSuccess &&
+              hipMalloc(&P.arc_res, sizeof(gl::Sums) * K * sc_[L_ARC]) == hipSuccess;
+    for (int L = 1; L < kLevels && ok; ++L)
+        ok = hipMalloc(&P.lvl[L], sizeof(int) * K * sc_[L_ARC]) == hipSuccess;
+    if (!ok) {
+        free_pipe(ctx);
+        return fail(ctx, GL_ERR_NOMEM, "work-list allocation");
+    }
+    for (int l = 0; l < kLists; ++l) P.scap[l] = sc_[l];
+    ctx->pipe_chunks = nc;
+    ctx->have_pipe = true;
+    return GL_OK;
+}
+
 struct Batch {
     const double* params;
     int64_t n_sets;
@@ -558,35 +1257,84 @@ gl_status check_args(gl_ctx* ctx, Batch& b)
     return GL_OK;
 }
 
-gl_status enqueue(gl_ctx* ctx, const Batch& b, bool census = false)
+// Window test over all chunks (fills the out-of-window outputs, chunk masks).
+void launch_window(gl_ctx* ctx, const Batch& b, hipStream_t st, int lists)
 {
     const int shared = b.offsets ? 0 : 1;
+    const int64_t cps = shared ? (b.n_times + kChunk - 1) / kChunk : 0;
+    const int64_t groups = (b.max_chunks + kWinChunks - 1) / kWinChunks;
+    hipLaunchKernelGGL(k_window, dim3((unsigned)((groups + 3) / 4)), dim3(256), 0, st, b.times,
+                       b.n_sets, shared, cps, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off,
+                       ctx->ctr, ctx->masks, ctx->chunk_set, b.out, lists, ctx->pipe, ctx->chunk_fb);
+}
+
+template <bool CENSUS>
+void launch_arcs(gl_ctx* ctx, hipStream_t st, unsigned grid)
+{
+    const Pipe& P = ctx->pipe;
+    hipLaunchKernelGGL((k_gk<0, CENSUS>), dim3(grid), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
+    hipLaunchKernelGGL((k_gk<1, CENSUS>), dim3(grid), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
+    // few arcs reach the deeper levels: smaller persistent grids there
+    const unsigned small = std::max(1u, grid / 8);
+    hipLaunchKernelGGL((k_gk<2, CENSUS>), dim3(small), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
+    hipLaunchKernelGGL((k_gk<3, CENSUS>), dim3(small), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
+    hipLaunchKernelGGL((k_gk<4, CENSUS>), dim3(small), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
+}
+static_assert(kLevels == 5, "launch_arcs launches levels 0..4");
+
+template <bool CENSUS>
+gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
+{
+    const int shared = b.offsets ? 0 : 1;
+    hipStream_t st = b.stream;
     hipEvent_t* ev = nullptr;
-    if (ctx->t_slots > 0 && ctx->t_used < ctx->t_slots && !census) {
-        ev = ctx->ev + 3 * ctx->t_used;
+    int e = 0;
+    if (!CENSUS && ctx->t_slots > 0 && ctx->t_used < ctx->t_slots) {
+        ev = ctx->ev + (GL_NSTAGES + 1) * ctx->t_used;
         ctx->t_used++;
-        GL_HIP(hipEventRecord(ev[0], b.stream), "hipEventRecord");
+        GL_HIP(hipEventRecord(ev[e++], st), "hipEventRecord");
     }
+#define GL_STAGE_DONE() \
+    do { if (ev) GL_HIP(hipEventRecord(ev[e++], st), "hipEventRecord"); } while (0)
+    const Pipe& P = ctx->pipe;
     const unsigned prep_blocks = (unsigned)((b.n_sets + 255) / 256);
-    hipLaunchKernelGGL(k_prep, dim3(prep_blocks), dim3(256), 0, b.stream, b.params, b.n_sets,
+    hipLaunchKernelGGL(k_prep, dim3(prep_blocks), dim3(256), 0, st, b.params, b.n_sets,
                        b.offsets, b.n_times, b.n_ss, b.t_exp, ctx->sc, ctx->seg_begin,
                        ctx->seg_len, ctx->chunk_off, ctx->ctr);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, b.stream, ctx->chunk_off, b.n_sets,
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, ctx->chunk_off, b.n_sets,
                        b.max_chunks, ctx->ctr);
-    const int64_t fill_blocks = (b.max_chunks + 3) / 4;
-    const int64_t cps = shared ? (b.n_times + kChunk - 1) / kChunk : 0;
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)fill_blocks), dim3(256), 0, b.stream, b.times,
-                       b.n_sets, shared, cps, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off,
-                       ctx->ctr, ctx->masks, ctx->chunk_set, b.out);
-    const int64_t want = (int64_t)ctx->n_cu * ctx->waves_per_cu;
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(want, (b.max_chunks + kChunk - 1) / kChunk * 4 + 1));
-    if (ev) GL_HIP(hipEventRecord(ev[1], b.stream), "hipEventRecord");
-    ComputeFn fn = census ? k_compute<true> : k_compute<false>;
-    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64), 0, b.stream, b.times, shared, ctx->sc,
-                       ctx->seg_begin, ctx->chunk_off, ctx->ctr, ctx->masks, ctx->chunk_set, b.out);
-    if (ev) GL_HIP(hipEventRecord(ev[2], b.stream), "hipEventRecord");
+    GL_STAGE_DONE();
+    const int64_t n_cu = ctx->n_cu;
+    launch_window(ctx, b, st, 1);
+    const unsigned waves = (unsigned)std::max<int64_t>(4, n_cu * ctx->waves_per_cu);
+    hipLaunchKernelGGL(k_classify<CENSUS>, dim3(waves), dim3(64), 0, st, b.times, shared, ctx->sc,
+                       ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks, ctx->chunk_set,
+                       ctx->chunk_fb);
+    GL_STAGE_DONE();
+    hipLaunchKernelGGL(k_trap<CENSUS>, dim3((waves + 3) / 4), dim3(256), 0, st, ctx->sc, ctx->ctr, P);
+    GL_STAGE_DONE();
+    hipLaunchKernelGGL(k_hard<CENSUS>, dim3(waves), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
+    GL_STAGE_DONE();
+    hipLaunchKernelGGL(k_nested<CENSUS>, dim3((unsigned)(n_cu * 4)), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
+    GL_STAGE_DONE();
+    launch_arcs<CENSUS>(ctx, st, waves);
+    GL_STAGE_DONE();
+    hipLaunchKernelGGL(k_average, dim3((unsigned)(n_cu * 8)), dim3(64), 0, st, ctx->sc,
+                       ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks, ctx->chunk_set,
+                       ctx->chunk_fb, b.out);
+    GL_STAGE_DONE();
+    hipLaunchKernelGGL(k_compute<CENSUS>, dim3((unsigned)n_cu), dim3(64), 0, st, b.times, shared,
+                       ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, ctx->masks, ctx->chunk_set,
+                       P.fb_chunk, b.out);
+    GL_STAGE_DONE();
+#undef GL_STAGE_DONE
     GL_HIP(hipGetLastError(), "kernel launch");
     return GL_OK;
+}
+
+gl_status enqueue(gl_ctx* ctx, const Batch& b, bool census = false)
+{
+    return census ? enqueue_t<true>(ctx, b) : enqueue_t<false>(ctx, b);
 }
 
 bool same_key(const gl_ctx::Key& a, const gl_ctx::Key& b)
@@ -627,7 +1375,7 @@ gl_status gl_ctx_create(gl_ctx** out, int device)
 
 void free_timing(gl_ctx* ctx)
 {
-    for (int i = 0; i < 3 * ctx->t_slots; ++i) (void)hipEventDestroy(ctx->ev[i]);
+    for (int i = 0; i < (GL_NSTAGES + 1) * ctx->t_slots; ++i) (void)hipEventDestroy(ctx->ev[i]);
     delete[] ctx->ev;
     ctx->ev = nullptr;
     ctx->t_slots = ctx->t_used = 0;
@@ -655,6 +1403,8 @@ gl_status gl_lightcurve_batch(gl_ctx* ctx, const double* params, int64_t n_sets,
     if (st != GL_OK) return st;
     GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     st = ensure_ws(ctx, n_sets, b.max_chunks);
+    if (st != GL_OK) return st;
+    st = ensure_pipe(ctx, b.max_chunks);
     if (st != GL_OK) return st;
     // the legacy default stream cannot be captured, and timed launches record
     // events per launch: launch directly there
@@ -754,12 +1504,14 @@ gl_status gl_autotune(gl_ctx* ctx, const double* params, int64_t n_sets, const d
     GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     st = ensure_ws(ctx, n_sets, b.max_chunks);
     if (st != GL_OK) return st;
+    st = ensure_pipe(ctx, b.max_chunks);
+    if (st != GL_OK) return st;
     const bool graph = ctx->use_graph;
     drop_graph(ctx);
     hipEvent_t e0, e1;
     GL_HIP(hipEventCreate(&e0), "hipEventCreate");
     GL_HIP(hipEventCreate(&e1), "hipEventCreate");
-    const int cands[] = {2, 4, 8, 12, 16, 24, 32};
+    const int cands[] = {4, 8, 16, 24, 32};
     int best = ctx->waves_per_cu;
     float best_ms = 1e30f;
     for (int w : cands) {
@@ -797,9 +1549,9 @@ gl_status gl_ctx_set_timing(gl_ctx* ctx, int n_slots)
     free_timing(ctx);
     if (n_slots == 0) return GL_OK;
     drop_graph(ctx);
-    ctx->ev = new (std::nothrow) hipEvent_t[3 * n_slots];
+    ctx->ev = new (std::nothrow) hipEvent_t[(GL_NSTAGES + 1) * n_slots];
     if (!ctx->ev) return fail(ctx, GL_ERR_NOMEM, "timing slots");
-    for (int i = 0; i < 3 * n_slots; ++i) {
+    for (int i = 0; i < (GL_NSTAGES + 1) * n_slots; ++i) {
         if (hipEventCreate(&ctx->ev[i]) != hipSuccess) {
             for (int j = 0; j < i; ++j) (void)hipEventDestroy(ctx->ev[j]);
             delete[] ctx->ev;
@@ -812,23 +1564,54 @@ gl_status gl_ctx_set_timing(gl_ctx* ctx, int n_slots)
     return GL_OK;
 }
 
-gl_status gl_ctx_get_timing(gl_ctx* ctx, double* compute_ms, double* pipeline_ms, int* n)
+gl_status gl_ctx_get_stage_timing(gl_ctx* ctx, double* stage_ms, int* n)
 {
     if (!ctx) return GL_ERR_NULL;
-    double c = 0.0, p = 0.0;
+    double acc[GL_NSTAGES] = {};
     for (int i = 0; i < ctx->t_used; ++i) {
-        hipEvent_t* ev = ctx->ev + 3 * i;
-        GL_HIP(hipEventSynchronize(ev[2]), "hipEventSynchronize");
-        float a = 0.0f, b = 0.0f;
-        GL_HIP(hipEventElapsedTime(&a, ev[1], ev[2]), "hipEventElapsedTime");
-        GL_HIP(hipEventElapsedTime(&b, ev[0], ev[2]), "hipEventElapsedTime");
-        c += a;
-        p += b;
+        hipEvent_t* ev = ctx->ev + (GL_NSTAGES + 1) * i;
+        GL_HIP(hipEventSynchronize(ev[GL_NSTAGES]), "hipEventSynchronize");
+        for (int k = 0; k < GL_NSTAGES; ++k) {
+            float ms = 0.0f;
+            GL_HIP(hipEventElapsedTime(&ms, ev[k], ev[k + 1]), "hipEventElapsedTime");
+            acc[k] += ms;
+        }
+    }
+    if (stage_ms)
+        for (int k = 0; k < GL_NSTAGES; ++k) stage_ms[k] = acc[k];
+    if (n) *n = ctx->t_used;
+    ctx->t_used = 0;
+    return GL_OK;
+}
+
+gl_status gl_ctx_get_timing(gl_ctx* ctx, double* compute_ms, double* pipeline_ms, int* n)
+{
+    double st[GL_NSTAGES];
+    const gl_status r = gl_ctx_get_stage_timing(ctx, st, n);
+    if (r != GL_OK) return r;
+    double c = 0.0, p = 0.0;
+    for (int k = 0; k < GL_NSTAGES; ++k) {
+        p += st[k];
+        if (k > 0) c += st[k];
     }
     if (compute_ms) *compute_ms = c;
     if (pipeline_ms) *pipeline_ms = p;
-    if (n) *n = ctx->t_used;
-    ctx->t_used = 0;
+    return GL_OK;
+}
+
+gl_status gl_ctx_set_capacity(gl_ctx* ctx, int64_t sub_samples, int64_t hard_samples, int64_t arcs)
+{
+    if (!ctx) return GL_ERR_NULL;
+    if (sub_samples < 0 || hard_samples < 0 || arcs < 0 || sub_samples > kSubMask ||
+        hard_samples > INT32_MAX / 2 || arcs > INT32_MAX / 2)
+        return fail(ctx, GL_ERR_SIZE, "capacities: 0 (default) or sub <= 2^27 - 1, hard and arcs <= 2^30 - 1");
+    GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    GL_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    ctx->want_sub = sub_samples;
+    ctx->want_hard = hard_samples;
+    ctx->want_arc = arcs;
+    drop_graph(ctx);
+    free_pipe(ctx);
     return GL_OK;
 }
 
@@ -842,6 +1625,8 @@ gl_status gl_census(gl_ctx* ctx, const double* params, int64_t n_sets, const dou
     if (st != GL_OK) return st;
     GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     st = ensure_ws(ctx, n_sets, b.max_chunks);
+    if (st != GL_OK) return st;
+    st = ensure_pipe(ctx, b.max_chunks);
     if (st != GL_OK) return st;
     st = enqueue(ctx, b, true);
     if (st != GL_OK) return st;
@@ -863,6 +1648,8 @@ gl_status gl_flop_model(int64_t* per_item)
     per_item[5] = gl::kFlopGKPiece;
     per_item[6] = gl::kFlopIter;
     per_item[7] = gl::kFlopLimb;
+    per_item[8] = gl::kFlopTrapNode;
+    per_item[9] = gl::kFlopArc;
     return GL_OK;
 }
 
@@ -907,15 +1694,18 @@ __global__ void k_sur_samples(const double* __restrict__ params, int64_t n, cons
     if (bin_out) bin_out[i] = bin;
 }
 
-// table[bin] = max over samples of |(pred - target) * scale| (non-negative
-// floats order like their bit patterns, so an integer max is exact)
+// table[bin] = max over samples of the scaled error |pred - target| (rounded
+// up to float; non-negative floats order like their bit patterns, so an
+// integer max is exact)
 __global__ void k_sur_bound(const float* __restrict__ pred, const float* __restrict__ target,
                             const double* __restrict__ scale, const int* __restrict__ bin, int64_t n,
                             float* __restrict__ table)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || bin[i] < 0) return;
-    const float e = (float)(fabs((double)pred[i] - (double)target[i]) * scale[i]);
+    const double ed = fabs((double)pred[i] - (double)target[i]);
+    float e = (float)ed;
+    if ((double)e < ed) e = __uint_as_float(__float_as_uint(e) + 1u);  // round up
     atomicMax((unsigned int*)&table[bin[i]], __float_as_uint(e));
 }
 
@@ -1006,7 +1796,8 @@ k_sur_enum(const double* __restrict__ times, int shared_grid, const gl::SetConst
     }
 }
 
-// accept F = F_sphere + scale * pred where safety * table[bin] * ... <= tol,
+// accept F = F_sphere + scale * pred where safety * table[bin] * scale <= tol
+// (the bin's calibrated scaled error carried to this sample's flux units),
 // otherwise queue the sub-sample for the exact kernel
 __global__ void k_sur_gate(const float* __restrict__ pred, const double* __restrict__ fsph,
                            const double* __restrict__ scale, const int* __restrict__ bin,
@@ -1017,7 +1808,7 @@ __global__ void k_sur_gate(const float* __restrict__ pred, const double* __restr
     bool queue = false;
     if (g < n && bin[g] >= 0) {
         const float tb = table[bin[g]];
-        const double bound = safety * (double)tb;
+        const double bound = safety * (double)tb * scale[g];
         if (tb >= 0.f && bound <= tol && gl::finite_d(bound)) F[g] = fsph[g] + scale[g] * (double)pred[g];
         else queue = true;
     }
@@ -1157,14 +1948,11 @@ gl_status gl_lightcurve_batch_surrogate(gl_ctx* ctx, gl_mlp* mlp, const float* t
     if (st != GL_OK) return st;
     hipStream_t s = b.stream;
     const int shared = b.offsets ? 0 : 1;
-    const int64_t cps = shared ? (b.n_times + kChunk - 1) / kChunk : 0;
     hipLaunchKernelGGL(k_prep, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, s, params, n_sets,
                        offsets, n_times, n_ss, t_exp, ctx->sc, ctx->seg_begin, ctx->seg_len,
                        ctx->chunk_off, ctx->ctr);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, ctx->chunk_off, n_sets, b.max_chunks, ctx->ctr);
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)((b.max_chunks + 3) / 4)), dim3(256), 0, s, times, n_sets,
-                       shared, cps, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off, ctx->ctr,
-                       ctx->masks, ctx->chunk_set, out);
+    launch_window(ctx, b, s, 0);
     hipLaunchKernelGGL(k_sub_count, dim3((unsigned)((b.max_chunks + 255) / 256)), dim3(256), 0, s, ctx->masks,
                        ctx->chunk_set, ctx->sc, ctx->ctr, ctx->chunk_sub);
     hipLaunchKernelGGL(k_scan_n, dim3(1), dim3(kScanThreads), 0, s, ctx->chunk_sub, ctx->ctr);

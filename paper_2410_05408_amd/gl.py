@@ -24,10 +24,13 @@ GL_NPARAM = 10
 
 EXPORTED = ("gl_ctx_create", "gl_ctx_destroy", "gl_lightcurve_batch", "gl_ctx_sync_status",
             "gl_ctx_last_error", "gl_autotune", "gl_ctx_get_plan", "gl_ctx_set_plan",
-            "gl_ctx_set_graph", "gl_ctx_set_timing", "gl_ctx_get_timing", "gl_census",
-            "gl_flop_model", "gl_version")
+            "gl_ctx_set_graph", "gl_ctx_set_capacity", "gl_ctx_set_timing", "gl_ctx_get_timing",
+            "gl_ctx_get_stage_timing", "gl_census", "gl_flop_model", "gl_version")
 CENSUS_NAMES = ("sub_in_window", "whole_on_star", "intersecting", "off_star_in_window",
-                "trapezoid_nodes", "gk21_pieces", "newton_steps", "limb_arcs")
+                "trapezoid_nodes", "gk21_pieces", "newton_steps", "limb_arcs",
+                "nested_trapezoid_nodes", "ellipse_arcs")
+GL_NSTAGES = 8
+STAGE_NAMES = ("setup", "classify", "trapezoid", "hard", "nested", "arcs", "average", "fused")
 
 
 class GLError(RuntimeError):
@@ -72,6 +75,10 @@ def lib():
         dpp = ctypes.POINTER(ctypes.c_double)
         L.gl_ctx_get_timing.argtypes = [vp, dpp, dpp, ctypes.POINTER(i)]
         L.gl_ctx_get_timing.restype = i
+        L.gl_ctx_get_stage_timing.argtypes = [vp, dpp, ctypes.POINTER(i)]
+        L.gl_ctx_get_stage_timing.restype = i
+        L.gl_ctx_set_capacity.argtypes = [vp, i64, i64, i64]
+        L.gl_ctx_set_capacity.restype = i
         L.gl_census.argtypes = batch_args + [ctypes.POINTER(ctypes.c_int64)]
         L.gl_census.restype = i
         L.gl_flop_model.argtypes = [ctypes.POINTER(ctypes.c_int64)]
@@ -187,10 +194,23 @@ def gl_ctx_get_timing(ctx):
     return c.value, p.value, n.value
 
 
+def gl_ctx_get_stage_timing(ctx):
+    """Returns ({stage name: ms summed over the timed batches}, n_batches_timed)."""
+    st = (ctypes.c_double * GL_NSTAGES)()
+    n = ctypes.c_int()
+    _check(ctx, lib().gl_ctx_get_stage_timing(ctx, st, ctypes.byref(n)))
+    return dict(zip(STAGE_NAMES, list(st))), n.value
+
+
+def gl_ctx_set_capacity(ctx, sub_samples: int = 0, hard_samples: int = 0, arcs: int = 0) -> None:
+    """Work-list capacities of the exact path (0 = default)."""
+    _check(ctx, lib().gl_ctx_set_capacity(ctx, int(sub_samples), int(hard_samples), int(arcs)))
+
+
 def gl_census(ctx, params, times, out, offsets=None, n_ss=None, t_exp=None, stream=None):
-    """Runs the batch with the counting kernel; returns a dict of counts."""
+    """Runs the batch with the counting kernels; returns a dict of counts."""
     _validate(params, times, offsets, n_ss, t_exp, out)
-    counts = (ctypes.c_int64 * 8)()
+    counts = (ctypes.c_int64 * len(CENSUS_NAMES))()
     st = lib().gl_census(ctx, _ptr(params), params.shape[1], _ptr(times), _ptr(offsets),
                          times.numel(), _ptr(n_ss), _ptr(t_exp), _ptr(out),
                          _stream_handle(stream), counts)
@@ -199,7 +219,7 @@ def gl_census(ctx, params, times, out, offsets=None, n_ss=None, t_exp=None, stre
 
 
 def gl_flop_model():
-    per = (ctypes.c_int64 * 8)()
+    per = (ctypes.c_int64 * len(CENSUS_NAMES))()
     st = lib().gl_flop_model(per)
     if st != GL_OK:
         raise GLError(st, "gl_flop_model")

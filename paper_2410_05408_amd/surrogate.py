@@ -3,9 +3,9 @@
 The network (library kernels, BF16 matrix cores) predicts the scaled residual
 (F_oblate - F_sphere) / (k^2 (1 - q)) of the exact oblate flux against the
 equal-projected-area sphere; the library's gate accepts F_sphere + prediction
-only where the calibrated error bound of the sample's bin, times a safety
-factor, is within the tolerance, and computes every other sub-sample with the
-exact kernel.  This module only orchestrates: every number is produced by the
+only where the calibrated scaled-error bound of the sample's bin, times the
+sample's own scale k^2 (1 - q) and a safety factor, is within the tolerance,
+and computes every other sub-sample with the exact kernel.  This module only orchestrates: every number is produced by the
 library (gl_surrogate_samples, gl_mlp_*, gl_surrogate_bound,
 gl_lightcurve_batch_surrogate); PyTorch provides buffers, index permutations
 and streams.
@@ -102,7 +102,7 @@ class Surrogate:
         return self.net.forward(feat)
 
     def calibrate(self, data: Samples):
-        """Per-bin maximum flux error of the network on calibration samples;
+        """Per-bin maximum scaled error of the network on calibration samples;
         bins without samples stay negative (always computed exactly)."""
         import torch
         pred = self.predict(data.feat)

@@ -309,3 +309,64 @@ def test_autotune_keeps_results(gpu_lib, ctx):
     say(f"  tuned waves/CU {wpc}")
     after, _ = run(gl, ctx, w)
     assert np.array_equal(before, after)
+
+
+def test_work_list_overflow_paths(gpu_lib, ctx, oracle):
+    """Tiny work-list capacities: chunks that do not fit go to the fused
+    kernel, arcs that do not fit are integrated in place; results agree with
+    the oracle and (to rounding) with the default capacities."""
+    from paper_2410_05408_amd import workloads as W
+    gl = gpu_lib
+    w = W.adversarial_batch(n_dense=40)
+    ref_gpu, st = run(gl, ctx, w)
+    assert st == gl.GL_OK
+    ref = oracle.flux_batch(w.params, w.times, offsets=w.offsets, n_ss=w.n_ss, t_exp=w.t_exp)
+    try:
+        for caps in ((64, 64, 64), (4000, 200, 100), (200000, 5000, 300), (200000, 20000, 20000)):
+            say(f"case: capacities sub/hard/arc = {caps}")
+            gl.gl_ctx_set_capacity(ctx.handle, *caps)
+            got, st = run(gl, ctx, w)
+            assert st == gl.GL_OK
+            d_def = np.abs(got - ref_gpu).max()
+            d_orc = np.abs(got - ref).max()
+            say(f"  vs default capacities {d_def:.2e}, vs oracle {d_orc:.2e}")
+            assert d_orc <= TOL
+            assert d_def <= 1e-12
+    finally:
+        gl.gl_ctx_set_capacity(ctx.handle, 0, 0, 0)
+
+
+def test_census_classes_add_up(gpu_lib, ctx):
+    import torch
+    from paper_2410_05408_amd import workloads as W
+    gl = gpu_lib
+    say("case: census of a walker batch")
+    w = W.walker_batch(n_sets=256)
+    d = gl.to_device(w, "cuda:0")
+    out = torch.empty(w.n_out, dtype=torch.float64, device="cuda")
+    c = gl.gl_census(ctx.handle, d["params"], d["times"], out, n_ss=d["n_ss"], t_exp=d["t_exp"])
+    say(f"  {c}")
+    assert c["sub_in_window"] == c["whole_on_star"] + c["intersecting"] + c["off_star_in_window"]
+    assert c["gk21_pieces"] >= c["ellipse_arcs"] >= c["intersecting"] > 0
+    assert c["limb_arcs"] == c["intersecting"]
+    ref = ctx.batch(d["params"], d["times"], n_ss=d["n_ss"], t_exp=d["t_exp"])
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+
+
+def test_stage_timing(gpu_lib, ctx):
+    import torch
+    from paper_2410_05408_amd import workloads as W
+    gl = gpu_lib
+    say("case: per-stage timing events")
+    w = W.walker_batch(n_sets=128)
+    d = gl.to_device(w, "cuda:0")
+    gl.gl_ctx_set_timing(ctx.handle, 3)
+    for _ in range(3):
+        ctx.batch(d["params"], d["times"], n_ss=d["n_ss"], t_exp=d["t_exp"])
+    st, n = gl.gl_ctx_get_stage_timing(ctx.handle)
+    gl.gl_ctx_set_timing(ctx.handle, 0)
+    torch.cuda.synchronize()
+    say(f"  {n} batches: {st}")
+    assert n == 3 and len(st) == gl.GL_NSTAGES
+    assert all(v >= 0.0 for v in st.values()) and st["trapezoid"] > 0.0
