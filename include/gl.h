@@ -138,8 +138,8 @@ gl_status gl_ctx_set_graph(gl_ctx *ctx, int on);
  *  0 set-up (parameter preparation, chunk scan), 1 window test and
  *  classification, 2 whole-ellipse trapezoid, 3 hard samples (intersection
  *  quartic, break points, limb arcs), 4 nested trapezoid for whole ellipses
- *  near the limb, 5 ellipse arcs (Gauss-Kronrod levels 0..4, with the final
- *  combination of each hard sample), 6 supersample average, 7 fused kernel
+ *  near the limb, 5 ellipse arcs (Gauss-Kronrod levels 0..4, then the
+ *  combination of each hard sample's sums), 6 supersample average, 7 fused kernel
  *  for chunks beyond the work-list capacities. */
 #define GL_NSTAGES 8
 
@@ -253,11 +253,14 @@ gl_status gl_surrogate_bound(gl_ctx *ctx, const float *pred, const float *target
  * F = F_sphere + scale * network(features) when
  * safety * table[bin] * scale <= tol (its bin's calibrated error in flux
  * units, with a safety factor), and the exact kernel's value otherwise;
- * outputs are box-averaged in order.
+ * outputs are box-averaged in order.  zero_bins (device uint8 per bin, or
+ * NULL) marks bins where the prediction is taken as 0, i.e. the equal-area
+ * sphere alone (per-bin choice of the better calibrated predictor).
  * Synchronous (it sizes its buffers from the device); *n_sub_out and
  * *n_fallback_out (host, may be NULL) receive the number of in-window
  * sub-samples and of those computed exactly. */
-gl_status gl_lightcurve_batch_surrogate(gl_ctx *ctx, gl_mlp *mlp, const float *table, double safety,
+gl_status gl_lightcurve_batch_surrogate(gl_ctx *ctx, gl_mlp *mlp, const float *table,
+                                        const uint8_t *zero_bins, double safety,
                                         double tol, const double *params, int64_t n_sets,
                                         const double *times, const int64_t *offsets, int64_t n_times,
                                         const int32_t *n_ss, const double *t_exp, double *out,

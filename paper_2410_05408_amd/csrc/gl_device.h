@@ -108,6 +108,38 @@ GL_HD double sqrt_nn(double x)
 #endif
 }
 
+// Integrand-grade forms for quadrature nodes, where a relative error of a few
+// 1e-15 per node is far below the rules' own error: the reciprocal after one
+// Newton step (the estimate's 2^-24 error squared, about 2e-15) and the
+// square root after the Goldschmidt step and one Newton correction (about one
+// ulp, without the final rounding correction).  Host builds use the IEEE forms.
+GL_HD double rcp_q(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+#else
+    return 1.0 / x;
+#endif
+}
+
+GL_HD double sqrt_q(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    const bool pos = x > 1e-300;
+    const double xc = pos ? x : 1.0;
+    const double y = __builtin_amdgcn_rsq(xc);
+    double g = xc * y, h = 0.5 * y;
+    const double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    const double r = fma(fma(-g, g, xc), h, g);
+    return pos ? r : 0.0;
+#else
+    return x > 0.0 ? sqrt(x) : 0.0;
+#endif
+}
+
 // sin and cos of a in [-pi, pi] (orbital phase): a = k pi/2 + r with
 // |r| <= pi/4 (pi/2 split in two parts, Cody-Waite style), Taylor series of
 // sin r and cos r to r^17 and r^16 (the next terms are below 1e-17), then the
@@ -316,12 +348,15 @@ GL_HD double bracket_root(const Poly4& q, double lo, double hi, double flo, doub
     return x;
 }
 
-// Real roots (ascending) and critical points (ascending) of the quartic.
+// Real roots and critical points of the quartic in fixed slots, ascending
+// among the valid ones.  Every index below is static, so the slots stay in
+// registers.
 struct QuarticRoots {
     int n_roots;
     double r[4];
-    int n_crit;
+    bool rv[4];
     double c[3];
+    bool cv[3];
 };
 
 template <class CT>
@@ -330,52 +365,42 @@ GL_HD void solve_quartic_inl(const Poly4& q, QuarticRoots& out, CT& ct)
     // Cauchy bound on all roots of q and of q'
     const double inv = 1.0 / fabs(q.a4);
     const double Bnd = 1.0 + fmax(fmax(fabs(q.a3), fabs(q.a2)), fmax(fabs(q.a1), fabs(q.a0))) * inv;
-    // inflection points: roots of q'' = 12 a4 t^2 + 6 a3 t + 2 a2
-    double infl[2];
-    int n_infl = 0;
+    // inflection points (roots of q'' = 12 a4 t^2 + 6 a3 t + 2 a2) clamped into
+    // [-Bnd, Bnd]; without real ones both sit at -Bnd.  Between consecutive
+    // edges q' is monotone (empty intervals never show a sign change).
+    double i0 = -Bnd, i1 = -Bnd;
     {
         const double qa = 12.0 * q.a4, qb = 6.0 * q.a3, qc = 2.0 * q.a2;
         const double disc = qb * qb - 4.0 * qa * qc;
         if (disc > 0.0) {
             const double sd = sqrt(disc);
             const double qq = -0.5 * (qb + copysign(sd, qb));
-            double x1 = qq / qa, x2 = (qq != 0.0) ? qc / qq : -x1;
-            if (x1 > x2) {
-                const double tmp = x1;
-                x1 = x2;
-                x2 = tmp;
-            }
-            infl[0] = x1;
-            infl[1] = x2;
-            n_infl = 2;
+            const double x1 = qq / qa, x2 = (qq != 0.0) ? qc / qq : -x1;
+            i0 = fmin(fmax(fmin(x1, x2), -Bnd), Bnd);
+            i1 = fmin(fmax(fmax(x1, x2), -Bnd), Bnd);
         }
     }
-    // critical points: roots of q' on the intervals where q' is monotone
-    double edges[4];
-    int ne = 0;
-    edges[ne++] = -Bnd;
-    for (int i = 0; i < n_infl; ++i)
-        if (infl[i] > -Bnd && infl[i] < Bnd) edges[ne++] = infl[i];
-    edges[ne++] = Bnd;
-    out.n_crit = 0;
-    for (int i = 0; i + 1 < ne; ++i) {
-        const double lo = edges[i], hi = edges[i + 1];
+    const double e[4] = {-Bnd, i0, i1, Bnd};
+    // critical points: a root of q' in each interval where it changes sign
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double lo = e[i], hi = e[i + 1];
         const double flo = dp4(q, lo), fhi = dp4(q, hi);
-        if ((flo < 0.0) != (fhi < 0.0) && flo != 0.0 && fhi != 0.0)
-            out.c[out.n_crit++] = bracket_root<1>(q, lo, hi, flo, fhi, ct);
+        out.cv[i] = (flo < 0.0) != (fhi < 0.0) && flo != 0.0 && fhi != 0.0;
+        out.c[i] = out.cv[i] ? bracket_root<1>(q, lo, hi, flo, fhi, ct) : lo;
     }
-    // roots of q on the intervals between critical points
-    double e2[5];
-    int m = 0;
-    e2[m++] = -Bnd;
-    for (int i = 0; i < out.n_crit; ++i) e2[m++] = out.c[i];
-    e2[m++] = Bnd;
+    // roots of q between consecutive critical points; an empty critical slot
+    // keeps the left end of its interval, which only splits a stretch where
+    // q is monotone
+    const double pt[5] = {-Bnd, out.c[0], out.c[1], out.c[2], Bnd};
     out.n_roots = 0;
-    for (int i = 0; i + 1 < m; ++i) {
-        const double lo = e2[i], hi = e2[i + 1];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double lo = pt[i], hi = pt[i + 1];
         const double flo = p4(q, lo), fhi = p4(q, hi);
-        if ((flo < 0.0) != (fhi < 0.0) && flo != 0.0 && fhi != 0.0 && out.n_roots < 4)
-            out.r[out.n_roots++] = bracket_root<0>(q, lo, hi, flo, fhi, ct);
+        out.rv[i] = (flo < 0.0) != (fhi < 0.0) && flo != 0.0 && fhi != 0.0;
+        out.r[i] = out.rv[i] ? bracket_root<0>(q, lo, hi, flo, fhi, ct) : 0.0;
+        out.n_roots += out.rv[i] ? 1 : 0;
     }
 }
 
@@ -435,7 +460,7 @@ GL_HD double gk_piece(const Frame& F, double cc, double sc, double mid, double h
     auto node = [&](int j) {
         const double tau = mid + half * GK21_M[j];
         const double t2 = tau * tau;
-        const double inv = rcp(1.0 + t2);
+        const double inv = rcp_q(1.0 + t2);
         const double cu = (1.0 - t2) * inv, su = 2.0 * tau * inv;
         const double c = cc * cu - sc * su, sn = sc * cu + cc * su;
         const double x = F.x0 + F.Xc * c + F.Xs * sn;
@@ -444,8 +469,8 @@ GL_HD double gk_piece(const Frame& F, double cc, double sc, double mid, double h
         const double dy = -F.Yc * sn + F.Ys * c;
         const double x2 = x * x, y2 = y * y;
         const double om = fmax(0.0, 1.0 - x2 - y2);
-        const double w = sqrt_nn(om);
-        const double G = 1.0 + om * rcp(1.0 + w);           // (1 + w + w^2)/(1 + w)
+        const double w = sqrt_q(om);
+        const double G = 1.0 + om * rcp_q(1.0 + w);         // (1 + w + w^2)/(1 + w)
         const double flat = F.P0 + F.P1 * c + F.P2 * sn;     // x y' - y x'
         const double quad = x * (x2 * (1.0 / 3.0) + y2) * dy - y * (x2 + y2 * (1.0 / 3.0)) * dx;
         const double fl = inv * flat, li = fl * G;           // dpsi = 2 dtau / (1 + tau^2)
@@ -558,8 +583,8 @@ GL_HD double trap_lin_inl(const SetConst& s, double x0, double y0, int oi)
         const double x = x0 + s.A * c;
         const double y = y0 + s.B * c + s.C * sn;
         const double om = fmax(0.0, 1.0 - x * x - y * y);
-        const double w = sqrt_nn(om);
-        return (1.0 + om * rcp(1.0 + w)) * (s.AC + P1 * c + P2 * sn);
+        const double w = sqrt_q(om);
+        return (1.0 + om * rcp_q(1.0 + w)) * (s.AC + P1 * c + P2 * sn);
     };
     double acc = node(1.0, 0.0) + node(-1.0, 0.0);
     double c = rc, sn = rs;
@@ -589,8 +614,8 @@ GL_HD bool trap_lin_nested_inl(const SetConst& s, double x0, double y0, double& 
         const double x = x0 + s.A * c;
         const double y = y0 + s.B * c + s.C * sn;
         const double om = fmax(0.0, 1.0 - x * x - y * y);
-        const double w = sqrt_nn(om);
-        return (1.0 + om * rcp(1.0 + w)) * (s.AC + P1 * c + P2 * sn);
+        const double w = sqrt_q(om);
+        return (1.0 + om * rcp_q(1.0 + w)) * (s.AC + P1 * c + P2 * sn);
     };
     // level 8: nodes k pi/4
     double sum = node(1.0, 0.0) + node(-1.0, 0.0) + node(0.0, 1.0) + node(0.0, -1.0);
@@ -658,7 +683,9 @@ struct TauArc {
     double cc, sc, h;
 };
 
-GL_HD int arc_between(double ta, double tb, TauArc* out)
+// split: -1 decide here (span > pi), 0 / 1 take the decision given (a second
+// pass over the same arc repeats the first pass's count exactly).
+GL_HD int arc_between(double ta, double tb, TauArc* out, int split = -1)
 {
     const double Na = sqrt_nn(1.0 + ta * ta), Nb = sqrt_nn(1.0 + tb * tb);
     const double sg = (tb > ta) ? 1.0 : -1.0;
@@ -666,7 +693,7 @@ GL_HD int arc_between(double ta, double tb, TauArc* out)
     const double h = sg * (tb - ta) / (Na * Nb + sg * (1.0 + ta * tb));
     const double inv = sg / (Na * Nb);
     const double cc = (1.0 - ta * tb) * inv, sc = (ta + tb) * inv;
-    if (h <= 1.0) {
+    if (split < 0 ? h <= 1.0 : split == 0) {
         out[0] = {cc, sc, h};
         return 1;
     }
@@ -767,10 +794,21 @@ struct HardPrep {
     Poly4 q;
     QuarticRoots R;
     double c0a, s0a;  // cos, sin of the anchor th0
-    double tc[3];
+    double tc[3];     // cluster points in the slots of their critical points
+    bool tv[3];
     int ntc;
     double t_near;    // the local maximum nearest the limb
     bool inf_inside;  // t = +-inf (th = th0 + pi) lies on the star
+
+    // a single cluster point at t (a whole ellipse whose nested rule did not settle)
+    GL_HD void single_cluster(double t)
+    {
+        tc[0] = t;
+        tc[1] = tc[2] = 0.0;
+        tv[0] = true;
+        tv[1] = tv[2] = false;
+        ntc = 1;
+    }
 };
 
 template <class CT, bool INLINE_SOLVE = false>
@@ -831,7 +869,11 @@ GL_HD void hard_prepare(const SetConst& s, double x0, double y0, HardPrep& H, CT
     H.ntc = 0;
     H.t_near = 0.0;
     double d_near = 1e300;
-    for (int i = 0; i < H.R.n_crit; ++i) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        H.tc[i] = 0.0;
+        H.tv[i] = false;
+        if (!H.R.cv[i]) continue;
         const double t = H.R.c[i];
         const double pv = p4(q, t), pp = ddp4(q, t);
         if (pv < 0.0 && pp < 0.0) {
@@ -840,7 +882,11 @@ GL_HD void hard_prepare(const SetConst& s, double x0, double y0, HardPrep& H, CT
                 d_near = dth;
                 H.t_near = t;
             }
-            if (dth < kSplitDist) H.tc[H.ntc++] = t;
+            if (dth < kSplitDist) {
+                H.tc[i] = t;
+                H.tv[i] = true;
+                ++H.ntc;
+            }
         }
     }
 }
@@ -854,61 +900,105 @@ GL_HD int hard_class(const HardPrep& H)
 }
 
 // Break points of the boundary of E cap D in t, ascending (kind 0 = root,
-// 1 = cluster point).  A whole ellipse needs at least one cluster point
-// (a single one gets the diametrically opposite point as its partner).
+// 1 = cluster point), in bp[0..nb) (nb is returned; the rest of the 7 slots
+// hold +huge).  A whole ellipse needs at least one cluster point (a single
+// one gets the diametrically opposite point as its partner).  Merged by a
+// 16-comparator sorting network so that every index is static.
+GL_HD void sort_pair(double& ka, int& da, double& kb, int& db)
+{
+    const bool sw = kb < ka;
+    const double k0 = sw ? kb : ka, k1 = sw ? ka : kb;
+    const int d0 = sw ? db : da, d1 = sw ? da : db;
+    ka = k0;
+    kb = k1;
+    da = d0;
+    db = d1;
+}
+
 GL_HD int hard_breaks(HardPrep& H, double* bp, int* kind)
 {
-    int nb = 0;
-    if (H.R.n_roots < 2) {
-        if (H.ntc == 1) {
-            // second break point diametrically opposite: psi + pi <-> -1/t
-            const double t = H.tc[0];
-            const double o = (t != 0.0) ? -1.0 / t : -1e16;
-            if (o < t) {
-                H.tc[1] = t;
-                H.tc[0] = o;
-            } else {
-                H.tc[1] = o;
-            }
-            H.ntc = 2;
-        }
-        for (int i = 0; i < H.ntc; ++i) {
-            bp[nb] = H.tc[i];
-            kind[nb++] = 1;
-        }
-    } else {
-        int i = 0, j = 0;
-        while (i < H.R.n_roots || j < H.ntc) {
-            if (j >= H.ntc || (i < H.R.n_roots && H.R.r[i] <= H.tc[j])) {
-                bp[nb] = H.R.r[i++];
-                kind[nb++] = 0;
-            } else {
-                bp[nb] = H.tc[j++];
-                kind[nb++] = 1;
-            }
-        }
+    constexpr double kNone = 1e300;
+    const bool whole = H.R.n_roots < 2;
+    if (whole && H.ntc == 1) {
+        // second break point diametrically opposite: psi + pi <-> -1/t
+        // the one cluster point (empty slots hold 0; a sum, not a selection
+        // of slots, keeps the slots in registers)
+        const double t = H.tc[0] + H.tc[1] + H.tc[2];
+        const double o = (t != 0.0) ? -1.0 / t : -1e16;
+        H.tc[0] = fmin(t, o);
+        H.tc[1] = fmax(t, o);
+        H.tc[2] = 0.0;
+        H.tv[0] = H.tv[1] = true;
+        H.tv[2] = false;
+        H.ntc = 2;
     }
-    return nb;
+    double k[7];
+    int d[7];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        k[i] = (!whole && H.R.rv[i]) ? H.R.r[i] : kNone;
+        d[i] = 0;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        k[4 + i] = H.tv[i] ? H.tc[i] : kNone;
+        d[4 + i] = 1;
+    }
+    sort_pair(k[0], d[0], k[6], d[6]);
+    sort_pair(k[2], d[2], k[3], d[3]);
+    sort_pair(k[4], d[4], k[5], d[5]);
+    sort_pair(k[0], d[0], k[2], d[2]);
+    sort_pair(k[1], d[1], k[4], d[4]);
+    sort_pair(k[3], d[3], k[6], d[6]);
+    sort_pair(k[0], d[0], k[1], d[1]);
+    sort_pair(k[2], d[2], k[5], d[5]);
+    sort_pair(k[3], d[3], k[4], d[4]);
+    sort_pair(k[1], d[1], k[2], d[2]);
+    sort_pair(k[4], d[4], k[6], d[6]);
+    sort_pair(k[2], d[2], k[3], d[3]);
+    sort_pair(k[4], d[4], k[5], d[5]);
+    sort_pair(k[1], d[1], k[2], d[2]);
+    sort_pair(k[3], d[3], k[4], d[4]);
+    sort_pair(k[5], d[5], k[6], d[6]);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        bp[i] = k[i];
+        kind[i] = d[i];
+    }
+    return (whole ? 0 : H.R.n_roots) + H.ntc;
 }
 
 // Walks the boundary between consecutive break points: ellipse arcs on the
 // star go to arc(cc, sc, h) (as tau-rule arcs, split when longer than pi);
-// limb arcs are added to S in closed form when `limbs` is set.
+// limb arcs are added to S in closed form when `limbs` is set.  The decisions
+// (which pieces are inside, which arcs are split) are taken once and kept in
+// `plan` (2 bits per piece); a walk with a plan from an earlier walk repeats
+// them exactly and returns the same number of ellipse arcs.
 template <class ArcFn, class CT>
-GL_HD void boundary_walk(const HardPrep& H, const Frame& F, const double* bp, const int* kind,
-                         int nb, Sums& S, bool limbs, ArcFn&& arc, CT& ct)
+GL_HD int boundary_walk(const HardPrep& H, const Frame& F, const double* bp, const int* kind,
+                        int nb, Sums& S, bool limbs, ArcFn&& arc, CT& ct, unsigned& plan,
+                        bool replay = false)
 {
-    for (int i = 0; i < nb; ++i) {
-        const int i1 = (i + 1 == nb) ? 0 : i + 1;
-        const double ta = bp[i], tb = bp[i1];
+    int n_arcs = 0;
+    if (!replay) plan = 0u;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        if (i >= nb) break;
+        const bool wrap = i + 1 == nb;  // the arc from the last break point back to the first
+        const double ta = bp[i], tb = wrap ? bp[0] : bp[i + 1 < 7 ? i + 1 : 0];
+        const int ka = kind[i], kb = wrap ? kind[0] : kind[i + 1 < 7 ? i + 1 : 0];
         bool inside;
-        if (kind[i] == 1 || kind[i1] == 1) inside = true;  // cluster points lie on the star
-        else if (i1 != 0) inside = p4(H.q, 0.5 * (ta + tb)) < 0.0;
-        else inside = H.inf_inside;                         // the arc through t = inf
+        if (replay) inside = (plan >> (2 * i)) & 1u;
+        else if (ka == 1 || kb == 1) inside = true;  // cluster points lie on the star
+        else if (!wrap) inside = p4(H.q, 0.5 * (ta + tb)) < 0.0;
+        else inside = H.inf_inside;                    // the arc through t = inf
         if (inside) {
             TauArc arcs[2];
-            const int na = arc_between(ta, tb, arcs);
-            for (int k = 0; k < na; ++k) arc(arcs[k].cc, arcs[k].sc, arcs[k].h);
+            const int na = arc_between(ta, tb, arcs, replay ? (int)((plan >> (2 * i + 1)) & 1u) : -1);
+            if (!replay) plan |= (1u << (2 * i)) | ((na == 2 ? 1u : 0u) << (2 * i + 1));
+            arc(arcs[0].cc, arcs[0].sc, arcs[0].h);
+            if (na == 2) arc(arcs[1].cc, arcs[1].sc, arcs[1].h);
+            n_arcs += na;
         } else if (limbs) {
             double xa, ya, xb, yb;
             point_at(F, ta, xa, ya);
@@ -917,6 +1007,7 @@ GL_HD void boundary_walk(const HardPrep& H, const Frame& F, const double* bp, co
             ct.limb();
         }
     }
+    return n_arcs;
 }
 
 // Occulted fraction from the three boundary sums.
@@ -941,8 +1032,7 @@ GL_HD double occulted_hard(const SetConst& s, double x0, double y0, int* cls_out
         const bool ok = trap_lin_nested(s, x0, y0, sl, lev);
         ct.trap(8 << (lev - 1));
         if (ok) return whole_delta(s, x0, y0, sl);
-        H.tc[0] = H.t_near;  // did not settle: cluster at the point nearest the limb
-        H.ntc = 1;
+        H.single_cluster(H.t_near);  // did not settle: cluster at the point nearest the limb
     }
     double bp[7];
     int kind[7];
@@ -950,8 +1040,9 @@ GL_HD double occulted_hard(const SetConst& s, double x0, double y0, int* cls_out
     Frame F;
     make_frame(s, x0, y0, H.c0a, H.s0a, F);
     Sums S = {0.0, 0.0, 0.0};
+    unsigned plan;
     boundary_walk(H, F, bp, kind, nb, S, true,
-                  [&](double cc, double sc, double h) { arc_gk(F, cc, sc, h, S, ct); }, ct);
+                  [&](double cc, double sc, double h) { arc_gk(F, cc, sc, h, S, ct); }, ct, plan);
     return sums_delta(s, S);
 }
 

@@ -20,8 +20,8 @@
 //   k_nested    one thread per nested entry: nested periodic trapezoid.
 //   k_gk<L>     level L = 0..4 of the self-checking arc rule: one thread per
 //               Gauss-Kronrod piece (2^L pieces per arc, summed across lanes);
-//               arcs whose error estimate is too large go on to level L + 1;
-//               the arc that completes a hard sample writes its flux.
+//               arcs whose error estimate is too large go on to level L + 1.
+//   k_combine   one thread per hard entry: limb sums + its arcs -> flux.
 //   k_average   one wavefront per listed chunk: box average of each output's
 //               sub-samples in a fixed order (deterministic).
 //   k_compute   the fused per-lane evaluation, for chunks whose sub-samples
@@ -105,14 +105,12 @@ struct Group {
 };
 
 // A hard sample after its boundary walk: the frame anchor, the closed-form
-// limb sums and its range in the arc list.  `left` counts the arcs still
-// open; the arc that closes the last one combines the sums.
+// limb sums and its range in the arc list.
 struct HardRec {
     double x0, y0, c0a, s0a;
     gl::Sums limb;
     int set, sub;
-    int arc_begin, n_arcs;
-    int left, pad;
+    int arc_begin, n_arcs;  // n_arcs = 0: the flux slot is already written
 };
 
 // One ellipse arc on the star (tau-rule description) of the hard sample in
@@ -267,6 +265,16 @@ __device__ __forceinline__ int64_t reserve(Counters* ctr, int l, int j, unsigned
     return uniform64((int64_t)p);
 }
 
+// Entries appended to shard j of list l.  The trapezoid and hard lists share
+// one counter word per shard (low and high 32 bits), so that a classifying
+// wavefront reserves in both with one atomic.
+__device__ __forceinline__ int64_t list_count(const Counters* ctr, int l, int j)
+{
+    if (l == L_TRAP) return (int64_t)(ctr->lc[L_TRAP][j].v & 0xffffffffull);
+    if (l == L_HARD) return (int64_t)(ctr->lc[L_TRAP][j].v >> 32);
+    return (int64_t)ctr->lc[l][j].v;
+}
+
 // Wavefront view of a sharded list: lanes 0..kShards-1 hold the shard counts
 // (clamped to the capacity) and their inclusive prefix sums.
 struct ShardMap {
@@ -277,7 +285,7 @@ __device__ __forceinline__ ShardMap shard_map(const Counters* ctr, int l, int64_
 {
     const int lane = threadIdx.x & 63;
     ShardMap m;
-    m.cnt = lane < kShards ? std::min<int64_t>((int64_t)ctr->lc[l][lane].v, scap) : 0;
+    m.cnt = lane < kShards ? std::min<int64_t>(list_count(ctr, l, lane), scap) : 0;
     m.incl = m.cnt;
     for (int d = 1; d < 64; d <<= 1) {
         const int64_t v = __shfl_up(m.incl, d);
@@ -316,8 +324,13 @@ __device__ __forceinline__ void to_fused(Counters* ctr, const Pipe& P, int* chun
 // chunk that does not fit is queued for the fused kernel.
 constexpr int kWinChunks = 4;
 
+// SHARED (one time grid for every set): grid (ceil(chunks per set / 16),
+// n_sets) of 4-wavefront blocks, the set is the block row.  CSR: a 1-D grid
+// over all chunks, the set of the first chunk found by binary search and
+// stepped along from there.
+template <bool SHARED>
 __global__ void __launch_bounds__(256)
-k_window(const double* __restrict__ times, int64_t n_sets, int shared_grid, int64_t cps,
+k_window(const double* __restrict__ times, int64_t n_sets, int64_t cps,
          const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_begin,
          const int64_t* __restrict__ seg_len, const int64_t* __restrict__ chunk_off,
          Counters* __restrict__ ctr, unsigned long long* __restrict__ masks,
@@ -325,22 +338,38 @@ k_window(const double* __restrict__ times, int64_t n_sets, int shared_grid, int6
          int* __restrict__ chunk_fb)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t g = uniform64((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    const int wv = threadIdx.x >> 6;
     const int64_t total = (int64_t)ctr->total_chunks;
     int cnt[kWinChunks];
+    int64_t g, c_first, s, lc_first = 0;
+    if (SHARED) {
+        s = blockIdx.y;
+        lc_first = ((int64_t)blockIdx.x * 4 + wv) * kWinChunks;
+        c_first = s * cps + lc_first;
+        g = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 + wv;
+    } else {
+        g = (int64_t)blockIdx.x * 4 + wv;
+        c_first = g * kWinChunks;
+        s = 0;
+        if (c_first < total) s = uniform64(set_of_chunk(chunk_off, n_sets, c_first));
+    }
 #pragma unroll
     for (int k = 0; k < kWinChunks; ++k) {
         cnt[k] = 0;
-        const int64_t c = g * kWinChunks + k;
-        if (c >= total) continue;
-        const int64_t s = uniform64(shared_grid ? c / cps : set_of_chunk(chunk_off, n_sets, c));
-        const int64_t pos = (c - chunk_off[s]) * kChunk + lane;  // position inside the set's segment
+        const int64_t c = c_first + k;
+        if (SHARED) {
+            if (lc_first + k >= cps) continue;
+        } else {
+            if (c >= total) continue;
+            while (s + 1 < n_sets && chunk_off[s + 1] <= c) ++s;  // uniform
+        }
+        const int64_t pos = (SHARED ? lc_first + k : c - chunk_off[s]) * kChunk + lane;  // position in the segment
         const bool in_seg = pos < seg_len[s];
         const int64_t i = seg_begin[s] + pos;
         const gl::SetConst& S = sc[s];
         bool work = false;
         if (in_seg) {
-            const double t = shared_grid ? times[pos] : times[i];
+            const double t = SHARED ? times[pos] : times[i];
             if (!S.valid || !gl::finite_d(t)) {
                 out[i] = __builtin_nan("");
                 if (S.valid) atomicOr(&ctr->status, 4u);
@@ -374,7 +403,7 @@ k_window(const double* __restrict__ times, int64_t n_sets, int shared_grid, int6
 #pragma unroll
     for (int k = 0; k < kWinChunks; ++k) {
         if (cnt[k] == 0) continue;
-        const int64_t c = g * kWinChunks + k;
+        const int64_t c = c_first + k;  // the chunk whose count is cnt[k]
         const int ng = (cnt[k] + kChunk - 1) / kChunk;
         const bool ok = os + cnt[k] <= scs && ow < scw && og + ng <= scg;
         const int64_t base = ok ? (int64_t)shard * scs + os : -1;
@@ -445,8 +474,14 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
         const int sub = (int)(base + f);
         bool fb = false;
         const unsigned long long mt = __ballot(cls >= 0);
+        const unsigned long long mh = __ballot(cls == gl::kHard);
+        // one atomic reserves both: trapezoid count in the low half of the
+        // shard's counter word, hard count in the high half
+        const unsigned long long both =
+            (unsigned long long)reserve(ctr, L_TRAP, shard,
+                                        (unsigned long long)__popcll(mt) | ((unsigned long long)__popcll(mh) << 32));
         if (mt) {
-            const int64_t tp = reserve(ctr, L_TRAP, shard, (unsigned long long)__popcll(mt));
+            const int64_t tp = (int64_t)(both & 0xffffffffull);
             const int64_t tcap = P.scap[L_TRAP];
             Entry* tl = P.trap + (int64_t)shard * tcap;
             if (tp + __popcll(mt) > tcap) {
@@ -464,9 +499,8 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
                 if (cls >= 0) tl[tp + rank] = Entry{x0, y0, (int)s, sub | (cls << kSubBits)};
             }
         }
-        const unsigned long long mh = __ballot(cls == gl::kHard);
         if (mh) {
-            const int64_t hp = reserve(ctr, L_HARD, shard, (unsigned long long)__popcll(mh));
+            const int64_t hp = (int64_t)(both >> 32);
             const int64_t hcap = P.scap[L_HARD];
             Entry* hl = P.hard + (int64_t)shard * hcap;
             const int64_t slot = hp + __popcll(mh & lt);
@@ -487,28 +521,82 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
     }
 }
 
-// Whole ellipses well inside the disk: one entry per thread, the trapezoid
-// order was chosen by k_classify from the singularity bound.
+// Whole ellipses well inside the disk, the trapezoid order chosen by
+// k_classify from the singularity bound.  A workgroup takes kTrapRounds x
+// kTrapThreads consecutive entries, sorts their list slots by rule order in
+// LDS (counting sort from wavefront ballots), then each thread integrates
+// kTrapRounds of them in sorted order, so the lanes of a wavefront mostly run
+// the same number of nodes.
+constexpr int kTrapThreads = 512;
+constexpr int kTrapWaves = kTrapThreads / 64;
+constexpr int kTrapRounds = 4;
+constexpr int kTrapBuckets = gl::kTrapOrders + 1;  // the last bucket holds empty slots
+
 template <bool CENSUS>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kTrapThreads)
 k_trap(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
 {
-    const int lane = threadIdx.x & 63;
+    __shared__ int lds_slot[kTrapRounds * kTrapThreads];
+    __shared__ int lds_off[kTrapBuckets][kTrapRounds * kTrapWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const unsigned long long lt = lanemask_lt(lane);
     const int64_t scap = P.scap[L_TRAP];
     const ShardMap m = shard_map(ctr, L_TRAP, scap);
     unsigned long long nodes = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); g0 < m.total; g0 += stride) {
-        const int64_t g = g0 + lane;
-        const int64_t slot = shard_slot(m, g < m.total ? g : 0, scap);
-        if (g >= m.total) continue;
-        const Entry e = P.trap[slot];
-        if (e.set < 0) continue;  // slot of an overflowing chunk
-        const int oi = e.sub >> kSubBits, sub = e.sub & kSubMask;
-        const gl::SetConst& S = sc[e.set];
-        const double sl = gl::trap_lin_inl(S, e.x0, e.y0, oi);
-        P.fsub[sub] = 1.0 - gl::whole_delta(S, e.x0, e.y0, sl);
-        if (CENSUS) nodes += gl::kTrapN[oi];
+    constexpr int kBlock = kTrapRounds * kTrapThreads;
+    for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < m.total; b0 += (int64_t)gridDim.x * kBlock) {
+        int bucket[kTrapRounds], rank[kTrapRounds], slot[kTrapRounds];
+#pragma unroll
+        for (int r = 0; r < kTrapRounds; ++r) {
+            const int64_t g = b0 + r * kTrapThreads + tid;
+            const int64_t sl = shard_slot(m, g < m.total ? g : 0, scap);
+            int k = gl::kTrapOrders;
+            if (g < m.total) {
+                const Entry& e = P.trap[sl];
+                if (e.set >= 0) k = e.sub >> kSubBits;
+            }
+            bucket[r] = k;
+            slot[r] = (int)sl;
+            rank[r] = 0;
+#pragma unroll
+            for (int q = 0; q < kTrapBuckets; ++q) {
+                const unsigned long long mq = __ballot(k == q);
+                if (k == q) rank[r] = __popcll(mq & lt);
+                if (lane == 0) lds_off[q][r * kTrapWaves + wv] = __popcll(mq);
+            }
+        }
+        __syncthreads();
+        // exclusive offsets, bucket-major then (round, wavefront): one wavefront
+        if (wv == 0) {
+            int run = 0;
+            for (int q = 0; q < kTrapBuckets; ++q) {
+                const int v = lane < kTrapRounds * kTrapWaves ? lds_off[q][lane] : 0;
+                int incl = v;
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int u = __shfl_up(incl, d);
+                    if (lane >= d) incl += u;
+                }
+                if (lane < kTrapRounds * kTrapWaves) lds_off[q][lane] = run + incl - v;
+                run += __shfl(incl, 63);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kTrapRounds; ++r)
+            lds_slot[lds_off[bucket[r]][r * kTrapWaves + wv] + rank[r]] = slot[r];
+        const int n_valid = lds_off[gl::kTrapOrders][0];  // start of the empty bucket
+        __syncthreads();
+        for (int r = 0; r < kTrapRounds; ++r) {
+            const int pos = r * kTrapThreads + tid;
+            if (pos >= n_valid) break;
+            const Entry e = P.trap[lds_slot[pos]];
+            const int oi = e.sub >> kSubBits, sub = e.sub & kSubMask;
+            const gl::SetConst& S = sc[e.set];
+            const double sl = gl::trap_lin_inl(S, e.x0, e.y0, oi);
+            P.fsub[sub] = 1.0 - gl::whole_delta(S, e.x0, e.y0, sl);
+            if (CENSUS) nodes += gl::kTrapN[oi];
+        }
+        __syncthreads();
     }
     if (CENSUS) census_add(ctr, 4, nodes);
 }
@@ -516,9 +604,12 @@ k_trap(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
 // Hard entries: intersection quartic and break points per thread; the limb
 // arcs are summed in closed form, the ellipse arcs are appended to the arc
 // list (one reservation per wavefront, positions from a wavefront scan).
-// Samples off the disk get their flux here; whole ellipses near the limb with
-// no cluster point go to the nested-trapezoid list.  If the arc list is full,
-// the arcs are integrated in place.
+// Samples off the disk get their flux here.  Whole ellipses near the limb
+// with no cluster point, and samples whose arcs do not fit the arc list, go
+// to the in-place list (pushed to the shard of their own hard slot, so that
+// list never overflows and this kernel makes no calls).
+constexpr int kInPlace = 1 << kSubBits;  // in-place entry flag: arcs integrated per lane
+
 template <bool CENSUS>
 __global__ void __launch_bounds__(64)
 k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
@@ -543,13 +634,15 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
         double bp[7];
         int kind[7];
         int nb = 0, na = 0;
-        bool open = false, nested = false;
+        unsigned plan = 0u;
+        bool open = false, to_list = false;
+        int flag = 0;
         if (valid) {
             const gl::SetConst& S = sc[e.set];
             if (CENSUS) gl::hard_prepare<gl::Census, true>(S, e.x0, e.y0, H, ct);
             else gl::hard_prepare<gl::NoCensus, true>(S, e.x0, e.y0, H, nc);
             const int cls = gl::hard_class(H);
-            if (cls == gl::CLS_FULL && H.ntc == 0) nested = true;
+            if (cls == gl::CLS_FULL && H.ntc == 0) to_list = true;
             else if (cls != gl::CLS_OUT) open = true;
             if (CENSUS) {
                 c_off += cls == gl::CLS_OUT;
@@ -560,35 +653,11 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
                 nb = gl::hard_breaks(H, bp, kind);
                 gl::Frame F0{};
                 gl::Sums none{0.0, 0.0, 0.0};
-                gl::boundary_walk(H, F0, bp, kind, nb, none, false,
-                                  [&](double, double, double) { ++na; }, nc);
+                na = gl::boundary_walk(H, F0, bp, kind, nb, none, false,
+                                       [&](double, double, double) {}, nc, plan);
             } else {
-                if (!nested) P.fsub[e.sub] = 1.0;
+                if (!to_list) P.fsub[e.sub] = 1.0;
                 P.hrec[slot].n_arcs = 0;
-            }
-        }
-        // nested-trapezoid list
-        const unsigned long long mn = __ballot(nested);
-        if (mn) {
-            const int64_t np = reserve(ctr, L_NEST, shard, (unsigned long long)__popcll(mn));
-            const int64_t ns = np + __popcll(mn & lt);
-            if (nested) {
-                if (ns < ncap) {
-                    P.nest[(int64_t)shard * ncap + ns] = e;
-                } else {
-                    // list shard full: the nested rule here (rare)
-                    double sl;
-                    int lev;
-                    if (gl::trap_lin_nested(sc[e.set], e.x0, e.y0, sl, lev)) {
-                        P.fsub[e.sub] = 1.0 - gl::whole_delta(sc[e.set], e.x0, e.y0, sl);
-                    } else {
-                        H.tc[0] = H.t_near;
-                        H.ntc = 1;
-                        open = true;
-                        nb = gl::hard_breaks(H, bp, kind);
-                        na = 0;  // integrated in place below
-                    }
-                }
             }
         }
         // positions in the arc list: inclusive wavefront scan of na
@@ -606,29 +675,43 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
             gl::make_frame(S, e.x0, e.y0, H.c0a, H.s0a, F);
             gl::Sums Sm{0.0, 0.0, 0.0};
             const int64_t first = ap + incl - na;
-            if (over || na == 0) {
-                if (CENSUS)
-                    gl::boundary_walk(H, F, bp, kind, nb, Sm, true,
-                                      [&](double cc, double scv, double h) { gl::arc_gk(F, cc, scv, h, Sm, ct); }, ct);
-                else
-                    gl::boundary_walk(H, F, bp, kind, nb, Sm, true,
-                                      [&](double cc, double scv, double h) { gl::arc_gk(F, cc, scv, h, Sm, nc); }, nc);
-                P.fsub[e.sub] = 1.0 - gl::sums_delta(S, Sm);
-                P.hrec[slot].n_arcs = 0;
-                // this lane's reserved arc slots below the capacity are marked empty
+            if (over && na > 0) {
+                // arcs do not fit: the whole sample is integrated in place later;
+                // this lane's reserved slots below the capacity are marked empty
                 for (int64_t k = first; k < first + na && k < acap; ++k) al[k].hard = -1;
+                P.hrec[slot].n_arcs = 0;
+                to_list = true;
+                flag = kInPlace;
             } else {
+                // second walk: the first walk's decisions, so exactly na arcs
+                // land in this lane's reserved range
                 int64_t k = first;
-                if (CENSUS)
-                    gl::boundary_walk(H, F, bp, kind, nb, Sm, true,
-                                      [&](double cc, double scv, double h) { al[k++] = ArcRec{cc, scv, h, (int)slot, 0}; }, ct);
-                else
-                    gl::boundary_walk(H, F, bp, kind, nb, Sm, true,
-                                      [&](double cc, double scv, double h) { al[k++] = ArcRec{cc, scv, h, (int)slot, 0}; }, nc);
-                P.hrec[slot] = HardRec{e.x0, e.y0, H.c0a, H.s0a, Sm, e.set, e.sub,
-                                       (int)((int64_t)shard * acap + first), na, na, 0};
-                if (CENSUS) c_arcs += na;
+                auto put = [&](double cc, double scv, double h) {
+                    if (k < first + na) al[k] = ArcRec{cc, scv, h, (int)slot, 0};
+                    ++k;
+                };
+                if (CENSUS) gl::boundary_walk(H, F, bp, kind, nb, Sm, true, put, ct, plan, true);
+                else gl::boundary_walk(H, F, bp, kind, nb, Sm, true, put, nc, plan, true);
+                if (na == 0) {  // limb arcs only
+                    P.fsub[e.sub] = 1.0 - gl::sums_delta(S, Sm);
+                    P.hrec[slot].n_arcs = 0;
+                } else {
+                    P.hrec[slot] = HardRec{e.x0, e.y0, H.c0a, H.s0a, Sm, e.set, e.sub,
+                                           (int)((int64_t)shard * acap + first), na};
+                    if (CENSUS) c_arcs += na;
+                }
             }
+        }
+        // in-place list, in the shard of the entry's own hard slot
+        const int hs = to_list ? (int)(slot / scap) : -1;
+        unsigned long long pending = __ballot(to_list);
+        while (pending) {
+            const int j = __shfl(hs, __builtin_ctzll(pending));
+            const unsigned long long mj = __ballot(to_list && hs == j);
+            const int64_t np = reserve(ctr, L_NEST, j, (unsigned long long)__popcll(mj));
+            if (to_list && hs == j)
+                P.nest[(int64_t)j * ncap + np + __popcll(mj & lt)] = Entry{e.x0, e.y0, e.set, e.sub | flag};
+            pending &= ~mj;
         }
     }
     if (CENSUS) {
@@ -637,15 +720,14 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
         census_add(ctr, 3, c_off);
         census_add(ctr, 6, (unsigned long long)ct.iters);
         census_add(ctr, 7, (unsigned long long)ct.limbs);
-        census_add(ctr, 8, (unsigned long long)ct.trap_nodes);
         census_add(ctr, 9, c_arcs);
-        census_add(ctr, 5, (unsigned long long)ct.arcs);  // pieces integrated in place
     }
 }
 
-// Whole ellipses near the limb with no cluster point: nested periodic
-// trapezoid 8 -> 64 per thread; a sample whose rule does not settle takes the
-// cluster-arc route in place (rare).
+// In-place list: whole ellipses near the limb with no cluster point take the
+// nested periodic trapezoid 8 -> 64 per thread (cluster arcs in place if it
+// does not settle); samples whose arcs did not fit the arc list take the
+// whole boundary walk with the arc rule in place.
 template <bool CENSUS>
 __global__ void __launch_bounds__(64)
 k_nested(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
@@ -661,37 +743,42 @@ k_nested(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P
         const int64_t slot = shard_slot(m, g < m.total ? g : 0, scap);
         if (g >= m.total) continue;
         const Entry e = P.nest[slot];
+        const int sub = e.sub & kSubMask;
+        const bool in_place = (e.sub & kInPlace) != 0;
         const gl::SetConst& S = sc[e.set];
-        double sl;
-        int lev;
-        const bool ok = gl::trap_lin_nested_inl(S, e.x0, e.y0, sl, lev);
-        if (CENSUS) nodes += 8 << (lev - 1);
-        if (ok) {
-            P.fsub[e.sub] = 1.0 - gl::whole_delta(S, e.x0, e.y0, sl);
-            continue;
+        if (!in_place) {
+            double sl;
+            int lev;
+            const bool ok = gl::trap_lin_nested_inl(S, e.x0, e.y0, sl, lev);
+            if (CENSUS) nodes += 8 << (lev - 1);
+            if (ok) {
+                P.fsub[sub] = 1.0 - gl::whole_delta(S, e.x0, e.y0, sl);
+                continue;
+            }
         }
         gl::HardPrep H;
         if (CENSUS) gl::hard_prepare(S, e.x0, e.y0, H, ct);
         else gl::hard_prepare(S, e.x0, e.y0, H, nc);
-        H.tc[0] = H.t_near;  // did not settle: cluster at the point nearest the limb
-        H.ntc = 1;
+        if (!in_place) H.single_cluster(H.t_near);  // did not settle: cluster at the point nearest the limb
         double bp[7];
         int kind[7];
         const int nb = gl::hard_breaks(H, bp, kind);
         gl::Frame F;
         gl::make_frame(S, e.x0, e.y0, H.c0a, H.s0a, F);
         gl::Sums Sm{0.0, 0.0, 0.0};
+        unsigned plan;
         if (CENSUS)
             gl::boundary_walk(H, F, bp, kind, nb, Sm, true,
-                              [&](double cc, double scv, double h) { gl::arc_gk(F, cc, scv, h, Sm, ct); }, ct);
+                              [&](double cc, double scv, double h) { gl::arc_gk(F, cc, scv, h, Sm, ct); }, ct, plan);
         else
             gl::boundary_walk(H, F, bp, kind, nb, Sm, true,
-                              [&](double cc, double scv, double h) { gl::arc_gk(F, cc, scv, h, Sm, nc); }, nc);
-        P.fsub[e.sub] = 1.0 - gl::sums_delta(S, Sm);
+                              [&](double cc, double scv, double h) { gl::arc_gk(F, cc, scv, h, Sm, nc); }, nc, plan);
+        P.fsub[sub] = 1.0 - gl::sums_delta(S, Sm);
     }
     if (CENSUS) {
         census_add(ctr, 8, nodes);
         census_add(ctr, 6, (unsigned long long)ct.iters);
+        census_add(ctr, 7, (unsigned long long)ct.limbs);
         census_add(ctr, 5, (unsigned long long)ct.arcs);
     }
 }
@@ -701,8 +788,6 @@ k_nested(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P
 // lanes of an arc sum their Kronrod sums and differences by a butterfly (same
 // order on every lane).  Accepted when the summed difference is within the
 // tolerance (or at the last level); otherwise the arc enters level L + 1.
-// The arc that closes the last open arc of its hard sample adds the limb sums
-// and every arc of the sample in list order and writes the sample's flux.
 template <int L, bool CENSUS>
 __global__ void __launch_bounds__(64)
 k_gk(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
@@ -747,21 +832,7 @@ k_gk(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
         }
         const bool lead = valid && q == 0 && A.hard >= 0;
         const bool accept = err <= gl::kArcTol || L == gl::kArcMaxLevel;
-        if (lead && accept) {
-            P.arc_res[a] = K;
-            HardRec& R = P.hrec[A.hard];
-            const int before = __hip_atomic_fetch_add(&R.left, -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            if (before == 1) {
-                gl::Sums S = R.limb;
-                for (int k = 0; k < R.n_arcs; ++k) {
-                    const gl::Sums& B = P.arc_res[R.arc_begin + k];
-                    S.flat += B.flat;
-                    S.lin += B.lin;
-                    S.quad += B.quad;
-                }
-                P.fsub[R.sub] = 1.0 - gl::sums_delta(sc[R.set], S);
-            }
-        }
+        if (lead && accept) P.arc_res[a] = K;
         if (L < gl::kArcMaxLevel) {
             // an arc re-enters the shard of its home slot in the arc list, so a
             // level-list shard never holds more arcs than an arc-list shard
@@ -780,6 +851,33 @@ k_gk(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
         }
     }
     if (CENSUS) census_add(ctr, 5, pieces);
+}
+
+// Hard samples with ellipse arcs: limb sums plus the accepted arc sums in
+// list order -> flux.
+__global__ void __launch_bounds__(256)
+k_combine(const gl::SetConst* __restrict__ sc, const Counters* __restrict__ ctr, Pipe P)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t scap = P.scap[L_HARD];
+    const ShardMap m = shard_map(ctr, L_HARD, scap);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); g0 < m.total; g0 += stride) {
+        const int64_t g = g0 + lane;
+        const int64_t slot = shard_slot(m, g < m.total ? g : 0, scap);
+        if (g >= m.total) continue;
+        const HardRec& R = P.hrec[slot];
+        const int na = R.n_arcs;
+        if (na <= 0) continue;
+        gl::Sums S = R.limb;
+        for (int k = 0; k < na; ++k) {
+            const gl::Sums& B = P.arc_res[R.arc_begin + k];
+            S.flat += B.flat;
+            S.lin += B.lin;
+            S.quad += B.quad;
+        }
+        P.fsub[R.sub] = 1.0 - gl::sums_delta(sc[R.set], S);
+    }
 }
 
 // One wavefront per listed chunk: each in-window output averages its
@@ -1260,12 +1358,18 @@ gl_status check_args(gl_ctx* ctx, Batch& b)
 // Window test over all chunks (fills the out-of-window outputs, chunk masks).
 void launch_window(gl_ctx* ctx, const Batch& b, hipStream_t st, int lists)
 {
-    const int shared = b.offsets ? 0 : 1;
-    const int64_t cps = shared ? (b.n_times + kChunk - 1) / kChunk : 0;
-    const int64_t groups = (b.max_chunks + kWinChunks - 1) / kWinChunks;
-    hipLaunchKernelGGL(k_window, dim3((unsigned)((groups + 3) / 4)), dim3(256), 0, st, b.times,
-                       b.n_sets, shared, cps, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off,
-                       ctx->ctr, ctx->masks, ctx->chunk_set, b.out, lists, ctx->pipe, ctx->chunk_fb);
+    if (!b.offsets) {
+        const int64_t cps = (b.n_times + kChunk - 1) / kChunk;
+        const int64_t bx = (cps + 4 * kWinChunks - 1) / (4 * kWinChunks);
+        hipLaunchKernelGGL(k_window<true>, dim3((unsigned)bx, (unsigned)b.n_sets), dim3(256), 0, st, b.times,
+                           b.n_sets, cps, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off,
+                           ctx->ctr, ctx->masks, ctx->chunk_set, b.out, lists, ctx->pipe, ctx->chunk_fb);
+    } else {
+        const int64_t groups = (b.max_chunks + kWinChunks - 1) / kWinChunks;
+        hipLaunchKernelGGL(k_window<false>, dim3((unsigned)((groups + 3) / 4)), dim3(256), 0, st, b.times,
+                           b.n_sets, (int64_t)0, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off,
+                           ctx->ctr, ctx->masks, ctx->chunk_set, b.out, lists, ctx->pipe, ctx->chunk_fb);
+    }
 }
 
 template <bool CENSUS>
@@ -1311,13 +1415,15 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
                        ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks, ctx->chunk_set,
                        ctx->chunk_fb);
     GL_STAGE_DONE();
-    hipLaunchKernelGGL(k_trap<CENSUS>, dim3((waves + 3) / 4), dim3(256), 0, st, ctx->sc, ctx->ctr, P);
+    hipLaunchKernelGGL(k_trap<CENSUS>, dim3((waves + kTrapWaves - 1) / kTrapWaves), dim3(kTrapThreads), 0, st,
+                       ctx->sc, ctx->ctr, P);
     GL_STAGE_DONE();
     hipLaunchKernelGGL(k_hard<CENSUS>, dim3(waves), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
     GL_STAGE_DONE();
     hipLaunchKernelGGL(k_nested<CENSUS>, dim3((unsigned)(n_cu * 4)), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
     GL_STAGE_DONE();
     launch_arcs<CENSUS>(ctx, st, waves);
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)(n_cu * 4)), dim3(256), 0, st, ctx->sc, ctx->ctr, P);
     GL_STAGE_DONE();
     hipLaunchKernelGGL(k_average, dim3((unsigned)(n_cu * 8)), dim3(64), 0, st, ctx->sc,
                        ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks, ctx->chunk_set,
@@ -1798,18 +1904,22 @@ k_sur_enum(const double* __restrict__ times, int shared_grid, const gl::SetConst
 
 // accept F = F_sphere + scale * pred where safety * table[bin] * scale <= tol
 // (the bin's calibrated scaled error carried to this sample's flux units),
-// otherwise queue the sub-sample for the exact kernel
+// otherwise queue the sub-sample for the exact kernel; in bins flagged in
+// zero_bins the prediction is 0 (the equal-area sphere alone)
 __global__ void k_sur_gate(const float* __restrict__ pred, const double* __restrict__ fsph,
                            const double* __restrict__ scale, const int* __restrict__ bin,
-                           const float* __restrict__ table, double safety, double tol, int64_t n,
+                           const float* __restrict__ table, const uint8_t* __restrict__ zero_bins,
+                           double safety, double tol, int64_t n,
                            double* __restrict__ F, int64_t* __restrict__ fb, Counters* __restrict__ ctr)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool queue = false;
     if (g < n && bin[g] >= 0) {
-        const float tb = table[bin[g]];
+        const int b = bin[g];
+        const float tb = table[b];
         const double bound = safety * (double)tb * scale[g];
-        if (tb >= 0.f && bound <= tol && gl::finite_d(bound)) F[g] = fsph[g] + scale[g] * (double)pred[g];
+        const double pr = (zero_bins && zero_bins[b]) ? 0.0 : (double)pred[g];
+        if (tb >= 0.f && bound <= tol && gl::finite_d(bound)) F[g] = fsph[g] + scale[g] * pr;
         else queue = true;
     }
     const unsigned long long qm = __ballot(queue);
@@ -1931,7 +2041,8 @@ gl_status gl_surrogate_bound(gl_ctx* ctx, const float* pred, const float* target
 
 int gl_surrogate_num_bins(void) { return gl::kSurBins; }
 
-gl_status gl_lightcurve_batch_surrogate(gl_ctx* ctx, gl_mlp* mlp, const float* table, double safety,
+gl_status gl_lightcurve_batch_surrogate(gl_ctx* ctx, gl_mlp* mlp, const float* table,
+                                        const uint8_t* zero_bins, double safety,
                                         double tol, const double* params, int64_t n_sets,
                                         const double* times, const int64_t* offsets, int64_t n_times,
                                         const int32_t* n_ss, const double* t_exp, double* out,
@@ -1974,7 +2085,7 @@ gl_status gl_lightcurve_batch_surrogate(gl_ctx* ctx, gl_mlp* mlp, const float* t
         if (st != GL_OK) return fail(ctx, st, "surrogate network forward");
         hipLaunchKernelGGL(k_reset_head, dim3(1), dim3(1), 0, s, ctx->ctr);
         hipLaunchKernelGGL(k_sur_gate, dim3((unsigned)((n_sub + 255) / 256)), dim3(256), 0, s, ctx->s_pred,
-                           ctx->s_fsph, ctx->s_scale, ctx->s_bin, table, safety, tol, n_sub, ctx->s_F,
+                           ctx->s_fsph, ctx->s_scale, ctx->s_bin, table, zero_bins, safety, tol, n_sub, ctx->s_F,
                            ctx->s_fb, ctx->ctr);
         const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)ctx->n_cu * ctx->waves_per_cu,
                                                                     (n_sub + 63) / 64));

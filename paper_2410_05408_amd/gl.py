@@ -409,8 +409,8 @@ def _sur_lib():
         L.gl_surrogate_num_bins.restype = i
         L.gl_surrogate_bound.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
         L.gl_surrogate_bound.restype = i
-        L.gl_lightcurve_batch_surrogate.argtypes = [vp, vp, vp, d, d, vp, i64, vp, vp, i64, vp, vp, vp,
-                                                    vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.gl_lightcurve_batch_surrogate.argtypes = [vp, vp, vp, vp, d, d, vp, i64, vp, vp, i64, vp, vp,
+                                                    vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.gl_lightcurve_batch_surrogate.restype = i
         L._sur_typed = True
     return L
@@ -435,12 +435,12 @@ def gl_surrogate_bound(ctx, pred, target, scale, bin, table, stream=None):
 
 
 def gl_lightcurve_batch_surrogate(ctx, mlp, table, safety, tol, params, times, out, offsets=None,
-                                  n_ss=None, t_exp=None, stream=None):
+                                  n_ss=None, t_exp=None, stream=None, zero_bins=None):
     """Returns (n_sub, n_fallback)."""
     _validate(params, times, offsets, n_ss, t_exp, out)
     a, b = ctypes.c_int64(), ctypes.c_int64()
     st = _sur_lib().gl_lightcurve_batch_surrogate(
-        ctx, mlp.h, _ptr(table), float(safety), float(tol), _ptr(params), params.shape[1],
+        ctx, mlp.h, _ptr(table), _ptr(zero_bins), float(safety), float(tol), _ptr(params), params.shape[1],
         _ptr(times), _ptr(offsets), times.numel(), _ptr(n_ss), _ptr(t_exp), _ptr(out),
         _stream_handle(stream), ctypes.byref(a), ctypes.byref(b))
     _check(ctx, st)

@@ -62,6 +62,7 @@ class Surrogate:
         self.net.set_weights(w)
         self.bins = gl.gl_surrogate_num_bins()
         self.table = torch.full((self.bins,), -1.0, dtype=torch.float32, device="cuda")
+        self.zero_bins = None  # bins where the sphere alone calibrated better
         self.max_batch = max_batch
         self.history = []
 
@@ -101,14 +102,23 @@ class Surrogate:
     def predict(self, feat):
         return self.net.forward(feat)
 
-    def calibrate(self, data: Samples):
-        """Per-bin maximum scaled error of the network on calibration samples;
-        bins without samples stay negative (always computed exactly)."""
+    def calibrate(self, data: Samples, choose: bool = True):
+        """Per-bin maximum scaled error on calibration samples; bins without
+        samples stay negative (always computed exactly).  With `choose`, each
+        bin keeps the better of the network and the zero-residual predictor
+        (the equal-area sphere alone), so the gate never accepts less than the
+        sphere would."""
         import torch
         pred = self.predict(data.feat)
         self.table.zero_()
         gl.gl_surrogate_bound(self.ctx.handle, pred, data.target, data.scale, data.bin, self.table)
         counts = torch.bincount(data.bin[data.bin >= 0].long(), minlength=self.bins)
+        if choose:
+            zero = torch.zeros_like(self.table)
+            gl.gl_surrogate_bound(self.ctx.handle, torch.zeros_like(pred), data.target, data.scale,
+                                  data.bin, zero)
+            self.zero_bins = (zero < self.table).to(torch.uint8)
+            self.table = torch.minimum(self.table, zero)
         self.table[counts == 0] = -1.0
         torch.cuda.synchronize()
         return self.table
@@ -118,4 +128,5 @@ class Surrogate:
         returns (n_sub, n_fallback)."""
         return gl.gl_lightcurve_batch_surrogate(self.ctx.handle, self.net, self.table, safety, tol,
                                                 d["params"], d["times"], out, offsets=d["offsets"],
-                                                n_ss=d["n_ss"], t_exp=d["t_exp"], stream=stream)
+                                                n_ss=d["n_ss"], t_exp=d["t_exp"], stream=stream,
+                                                zero_bins=self.zero_bins)

@@ -63,7 +63,7 @@ def test_gated_light_curves_within_1ppm_and_network_gains(gpu_lib, ctx):
     assert hist[-1] < 0.5 * hist[0]
     sur.calibrate(cal)
     zero = S.Surrogate(ctx, max_batch=8192, zero=True)
-    zero.calibrate(cal)
+    zero.calibrate(cal, choose=False)
 
     w = W.walker_batch(n_sets=256)
     d = gl.to_device(w, "cuda:0")
