@@ -449,6 +449,12 @@ struct Sums {
 constexpr double kArcTol = GL_ARC_TOL;    // |K21 - G10| accepted on an arc
 constexpr double kTrapTol = GL_TRAP_TOL;  // |T_2n - T_n| accepted on a whole turn
 constexpr int kArcMaxLevel = 4;           // an arc is re-split at most into 16 pieces
+// Arcs with h = tan(span/4) above this start at two pieces: on the MCMC-walker
+// workload nearly all of them fail the one-piece check (which is then wasted
+// work), nearly all shorter ones pass it.
+constexpr double kArcStartSplit = 0.7;
+
+GL_HD int arc_start_level(double h) { return h > kArcStartSplit ? 1 : 0; }
 
 // One piece tau in [mid - half, mid + half] of the arc psi = psi_c + 2 atan(tau):
 // clustered Gauss-Kronrod 10/21 rule.  Adds the Kronrod sums to K and returns
@@ -496,13 +502,13 @@ GL_HD double gk_piece(const Frame& F, double cc, double sc, double mid, double h
     return half * (fabs(kf - gf) + (2.0 / 3.0) * fabs(kl - gl));
 }
 
-// Whole arc tau in [-h, h]: one Gauss-Kronrod piece, re-split uniformly into
-// 2, 4, ... pieces until the summed Gauss-Kronrod difference is below kArcTol
-// (starting at 2^L0 pieces when the coarser levels are already known to fail).
+// Whole arc tau in [-h, h]: one or two Gauss-Kronrod pieces (arc_start_level),
+// re-split uniformly into 2, 4, ... pieces until the summed Gauss-Kronrod
+// difference is below kArcTol (L0 >= 0 forces the starting level).
 template <class CT>
-GL_HD_CALL void arc_gk(const Frame& F, double cc, double sc, double h, Sums& S, CT& ct, int L0 = 0)
+GL_HD_CALL void arc_gk(const Frame& F, double cc, double sc, double h, Sums& S, CT& ct, int L0 = -1)
 {
-    for (int L = L0;; ++L) {
+    for (int L = L0 < 0 ? arc_start_level(h) : L0;; ++L) {
         const int np = 1 << L;
         const double half = h / np;
         Sums K = {0.0, 0.0, 0.0};
@@ -695,6 +701,7 @@ GL_HD int arc_between(double ta, double tb, TauArc* out, int split = -1)
     const double cc = (1.0 - ta * tb) * inv, sc = (ta + tb) * inv;
     if (split < 0 ? h <= 1.0 : split == 0) {
         out[0] = {cc, sc, h};
+        out[1] = out[0];  // (both slots always written: they stay in registers)
         return 1;
     }
     const double q = sqrt_nn(1.0 + h * h);
@@ -969,11 +976,12 @@ GL_HD int hard_breaks(HardPrep& H, double* bp, int* kind)
 }
 
 // Walks the boundary between consecutive break points: ellipse arcs on the
-// star go to arc(cc, sc, h) (as tau-rule arcs, split when longer than pi);
-// limb arcs are added to S in closed form when `limbs` is set.  The decisions
-// (which pieces are inside, which arcs are split) are taken once and kept in
-// `plan` (2 bits per piece); a walk with a plan from an earlier walk repeats
-// them exactly and returns the same number of ellipse arcs.
+// star go to arc(cc, sc, h, level) (as tau-rule arcs, split when longer than
+// pi, with the starting level of the arc rule); limb arcs are added to S in
+// closed form when `limbs` is set.  The decisions (which pieces are inside,
+// which arcs are split, each arc's starting level) are taken once and kept in
+// `plan` (4 bits per piece); a walk replaying a plan from an earlier walk
+// repeats them exactly.  Returns the number of ellipse arcs.
 template <class ArcFn, class CT>
 GL_HD int boundary_walk(const HardPrep& H, const Frame& F, const double* bp, const int* kind,
                         int nb, Sums& S, bool limbs, ArcFn&& arc, CT& ct, unsigned& plan,
@@ -987,17 +995,21 @@ GL_HD int boundary_walk(const HardPrep& H, const Frame& F, const double* bp, con
         const bool wrap = i + 1 == nb;  // the arc from the last break point back to the first
         const double ta = bp[i], tb = wrap ? bp[0] : bp[i + 1 < 7 ? i + 1 : 0];
         const int ka = kind[i], kb = wrap ? kind[0] : kind[i + 1 < 7 ? i + 1 : 0];
+        const unsigned bits = replay ? (plan >> (4 * i)) & 15u : 0u;
         bool inside;
-        if (replay) inside = (plan >> (2 * i)) & 1u;
+        if (replay) inside = bits & 1u;
         else if (ka == 1 || kb == 1) inside = true;  // cluster points lie on the star
         else if (!wrap) inside = p4(H.q, 0.5 * (ta + tb)) < 0.0;
         else inside = H.inf_inside;                    // the arc through t = inf
         if (inside) {
             TauArc arcs[2];
-            const int na = arc_between(ta, tb, arcs, replay ? (int)((plan >> (2 * i + 1)) & 1u) : -1);
-            if (!replay) plan |= (1u << (2 * i)) | ((na == 2 ? 1u : 0u) << (2 * i + 1));
-            arc(arcs[0].cc, arcs[0].sc, arcs[0].h);
-            if (na == 2) arc(arcs[1].cc, arcs[1].sc, arcs[1].h);
+            const int na = arc_between(ta, tb, arcs, replay ? (int)((bits >> 1) & 1u) : -1);
+            const int l0 = replay ? (int)((bits >> 2) & 1u) : arc_start_level(arcs[0].h);
+            const int l1 = replay ? (int)((bits >> 3) & 1u) : (na == 2 ? arc_start_level(arcs[1].h) : 0);
+            if (!replay)
+                plan |= (1u | (na == 2 ? 2u : 0u) | ((unsigned)l0 << 2) | ((unsigned)l1 << 3)) << (4 * i);
+            arc(arcs[0].cc, arcs[0].sc, arcs[0].h, l0);
+            if (na == 2) arc(arcs[1].cc, arcs[1].sc, arcs[1].h, l1);
             n_arcs += na;
         } else if (limbs) {
             double xa, ya, xb, yb;
@@ -1042,7 +1054,7 @@ GL_HD double occulted_hard(const SetConst& s, double x0, double y0, int* cls_out
     Sums S = {0.0, 0.0, 0.0};
     unsigned plan;
     boundary_walk(H, F, bp, kind, nb, S, true,
-                  [&](double cc, double sc, double h) { arc_gk(F, cc, sc, h, S, ct); }, ct, plan);
+                  [&](double cc, double sc, double h, int lev) { arc_gk(F, cc, sc, h, S, ct, lev); }, ct, plan);
     return sums_delta(s, S);
 }
 

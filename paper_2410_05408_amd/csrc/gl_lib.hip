@@ -59,9 +59,9 @@ enum : int {
     L_TRAP,      // whole ellipses for the trapezoid stage
     L_HARD,      // hard samples
     L_NEST,      // whole ellipses near the limb for the nested trapezoid
-    L_ARC,       // ellipse arcs
-    L_LVL1,      // arcs entering level 1 .. kArcMaxLevel of the arc rule
-    kLists = L_LVL1 + gl::kArcMaxLevel
+    L_ARC,       // ellipse arcs (storage)
+    L_LVL0,      // indices of the arcs at level 0 .. kArcMaxLevel of the arc rule
+    kLists = L_LVL0 + gl::kArcMaxLevel + 1
 };
 
 struct alignas(128) LineCount {
@@ -95,13 +95,20 @@ constexpr int kSubMask = (1 << kSubBits) - 1;
 
 // A chunk on the work lists and its first flux slot.
 struct WorkChunk {
-    int64_t c, base;  // base -1: empty slot
+    int64_t c, base;          // base -1: empty slot
+    unsigned long long mask;  // in-window outputs of the chunk
+    int64_t i0;               // output index of the chunk's first output
+    int nss, pad;
 };
 
-// Up to 64 consecutive sub-samples [f0, min(f0 + 64, cnt)) of chunk c.
+// Up to 64 consecutive sub-samples [f0, min(f0 + 64, cnt)) of chunk c, with
+// what classifying them needs (no further index lookups).
 struct Group {
-    int64_t c, base;  // c -1: empty slot
+    int64_t c, base;          // c -1: empty slot
+    unsigned long long mask;  // in-window outputs of the chunk
+    int64_t tb;               // index in `times` of the chunk's first output
     int f0, cnt;
+    int set, pad;
 };
 
 // A hard sample after its boundary walk: the frame anchor, the closed-form
@@ -133,7 +140,7 @@ struct Pipe {
     HardRec* hrec;         // indexed like `hard`
     ArcRec* arcs;
     gl::Sums* arc_res;     // indexed like `arcs`
-    int* lvl[kLevels];     // arcs re-split at level L (index 0 unused)
+    int* lvl[kLevels];     // arcs evaluated at level L
     int64_t scap[kLists];  // entries per shard
 };
 
@@ -143,7 +150,7 @@ __global__ void k_prep(const double* __restrict__ params, int64_t n_sets,
                        const int32_t* __restrict__ n_ss, const double* __restrict__ t_exp,
                        gl::SetConst* __restrict__ sc, int64_t* __restrict__ seg_begin,
                        int64_t* __restrict__ seg_len, int64_t* __restrict__ chunk_off,
-                       Counters* __restrict__ ctr)
+                       Counters* __restrict__ ctr, int64_t cps_shared)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s == 0) {
@@ -182,7 +189,17 @@ __global__ void k_prep(const double* __restrict__ params, int64_t n_sets,
     sc[s] = c;
     seg_begin[s] = b;
     seg_len[s] = e - b;
-    chunk_off[s] = (e - b + kChunk - 1) / kChunk;
+    if (cps_shared > 0) {
+        // shared grid, every set has cps_shared chunks: the exclusive scan in
+        // closed form (no k_scan launch)
+        chunk_off[s] = s * cps_shared;
+        if (s == n_sets - 1) {
+            chunk_off[n_sets] = n_sets * cps_shared;
+            ctr->total_chunks = (unsigned long long)(n_sets * cps_shared);
+        }
+    } else {
+        chunk_off[s] = (e - b + kChunk - 1) / kChunk;
+    }
 }
 
 // exclusive scan of chunk_off[0..n) in place; chunk_off[n] = total.  A total
@@ -340,7 +357,9 @@ k_window(const double* __restrict__ times, int64_t n_sets, int64_t cps,
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int64_t total = (int64_t)ctr->total_chunks;
-    int cnt[kWinChunks];
+    int cnt[kWinChunks], set_k[kWinChunks], nss_k[kWinChunks];
+    unsigned long long mask_k[kWinChunks];
+    int64_t i0_k[kWinChunks], tb_k[kWinChunks];
     int64_t g, c_first, s, lc_first = 0;
     if (SHARED) {
         s = blockIdx.y;
@@ -356,6 +375,9 @@ k_window(const double* __restrict__ times, int64_t n_sets, int64_t cps,
 #pragma unroll
     for (int k = 0; k < kWinChunks; ++k) {
         cnt[k] = 0;
+        set_k[k] = nss_k[k] = 0;
+        mask_k[k] = 0ull;
+        i0_k[k] = tb_k[k] = 0;
         const int64_t c = c_first + k;
         if (SHARED) {
             if (lc_first + k >= cps) continue;
@@ -384,7 +406,14 @@ k_window(const double* __restrict__ times, int64_t n_sets, int64_t cps,
             masks[c] = m;
             chunk_set[c] = (int)s;
         }
-        if (m) cnt[k] = __popcll(m) * S.n_ss;
+        if (m) {
+            cnt[k] = __popcll(m) * S.n_ss;
+            set_k[k] = (int)s;
+            nss_k[k] = S.n_ss;
+            mask_k[k] = m;
+            i0_k[k] = seg_begin[s] + (pos - lane);
+            tb_k[k] = SHARED ? pos - lane : i0_k[k];
+        }
     }
     if (!lists) return;
     int tot_sub = 0, tot_wc = 0, tot_grp = 0;
@@ -409,10 +438,12 @@ k_window(const double* __restrict__ times, int64_t n_sets, int64_t cps,
         const int64_t base = ok ? (int64_t)shard * scs + os : -1;
         if (lane == 0) {
             chunk_fb[c] = 0;
-            if (ow < scw) P.wc[(int64_t)shard * scw + ow] = WorkChunk{c, base};
+            if (ow < scw)
+                P.wc[(int64_t)shard * scw + ow] = WorkChunk{c, base, mask_k[k], i0_k[k], nss_k[k], 0};
         }
         if (lane < ng && og + lane < scg)
-            P.grp[(int64_t)shard * scg + og + lane] = Group{ok ? c : -1, base, lane * kChunk, cnt[k]};
+            P.grp[(int64_t)shard * scg + og + lane] =
+                Group{ok ? c : -1, base, mask_k[k], tb_k[k], lane * kChunk, cnt[k], set_k[k], 0};
         if (!ok && lane == 0) to_fused(ctr, P, chunk_fb, c);
         os += cnt[k];
         ow += 1;
@@ -446,11 +477,10 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
         if (c < 0) continue;
         const int64_t base = uniform64(G.base);
         const int f0 = __builtin_amdgcn_readfirstlane(G.f0), cnt = __builtin_amdgcn_readfirstlane(G.cnt);
-        const unsigned long long M = (unsigned long long)uniform64((int64_t)masks[c]);
-        const int64_t s = uniform64(chunk_set[c]);
+        const unsigned long long M = (unsigned long long)uniform64((int64_t)G.mask);
+        const int64_t s = __builtin_amdgcn_readfirstlane(G.set);
         const gl::SetConst& S = sc[s];
-        const int64_t lc = c - chunk_off[s];
-        const int64_t tb = shared_grid ? lc * kChunk : seg_begin[s] + lc * kChunk;
+        const int64_t tb = uniform64(G.tb);
         if ((M >> lane) & 1ull) lds_t[__popcll(M & lt)] = times[tb + lane];
         __syncthreads();
         const int nss = S.n_ss;
@@ -618,6 +648,7 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
     const unsigned long long lt = lanemask_lt(lane);
     const int shard = (int)(blockIdx.x % kShards);
     const int64_t scap = P.scap[L_HARD], acap = P.scap[L_ARC], ncap = P.scap[L_NEST];
+    const int64_t lcap = P.scap[L_LVL0];
     const ShardMap m = shard_map(ctr, L_HARD, scap);
     unsigned long long c_whole = 0, c_part = 0, c_off = 0, c_arcs = 0;
     gl::Census ct;
@@ -633,7 +664,7 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
         gl::HardPrep H;
         double bp[7];
         int kind[7];
-        int nb = 0, na = 0;
+        int nb = 0, na = 0, na1 = 0;  // arcs, of which starting at level 1
         unsigned plan = 0u;
         bool open = false, to_list = false;
         int flag = 0;
@@ -654,21 +685,28 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
                 gl::Frame F0{};
                 gl::Sums none{0.0, 0.0, 0.0};
                 na = gl::boundary_walk(H, F0, bp, kind, nb, none, false,
-                                       [&](double, double, double) {}, nc, plan);
+                                       [&](double, double, double, int lev) { na1 += lev; }, nc, plan);
             } else {
                 if (!to_list) P.fsub[e.sub] = 1.0;
                 P.hrec[slot].n_arcs = 0;
             }
         }
-        // positions in the arc list: inclusive wavefront scan of na
-        int incl = na;
+        // positions in the arc list and in the level-0 / level-1 index lists:
+        // inclusive wavefront scans (arcs, level-1 starts packed in one word)
+        int incl = na | (na1 << 16);
         for (int d = 1; d < 64; d <<= 1) {
             const int v = __shfl_up(incl, d);
             if (lane >= d) incl += v;
         }
-        const int wtotal = __shfl(incl, 63);
+        const int wpack = __shfl(incl, 63);
+        const int wtotal = wpack & 0xffff, wtot1 = wpack >> 16;
+        const int incl0 = (incl & 0xffff) - (incl >> 16), incl1 = incl >> 16;  // level-0 and level-1 prefixes
+        incl &= 0xffff;
         const int64_t ap = reserve(ctr, L_ARC, shard, (unsigned long long)wtotal);
         const bool over = ap + wtotal > acap;
+        // index lists: reserved only when the arcs are stored
+        const int64_t l0p = over ? 0 : reserve(ctr, L_LVL0, shard, (unsigned long long)(wtotal - wtot1));
+        const int64_t l1p = over ? 0 : reserve(ctr, L_LVL0 + 1, shard, (unsigned long long)wtot1);
         if (open) {
             const gl::SetConst& S = sc[e.set];
             gl::Frame F;
@@ -684,10 +722,17 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
                 flag = kInPlace;
             } else {
                 // second walk: the first walk's decisions, so exactly na arcs
-                // land in this lane's reserved range
+                // land in this lane's reserved range; their indices go to the
+                // index list of their starting level (same shard: never full)
                 int64_t k = first;
-                auto put = [&](double cc, double scv, double h) {
-                    if (k < first + na) al[k] = ArcRec{cc, scv, h, (int)slot, 0};
+                int64_t k0 = l0p + incl0 - (na - na1), k1 = l1p + incl1 - na1;
+                auto put = [&](double cc, double scv, double h, int lev) {
+                    if (k < first + na) {
+                        al[k] = ArcRec{cc, scv, h, (int)slot, 0};
+                        const int a = (int)((int64_t)shard * acap + k);
+                        if (lev == 0) P.lvl[0][(int64_t)shard * lcap + (k0++)] = a;
+                        else P.lvl[1][(int64_t)shard * lcap + (k1++)] = a;
+                    }
                     ++k;
                 };
                 if (CENSUS) gl::boundary_walk(H, F, bp, kind, nb, Sm, true, put, ct, plan, true);
@@ -769,10 +814,12 @@ k_nested(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P
         unsigned plan;
         if (CENSUS)
             gl::boundary_walk(H, F, bp, kind, nb, Sm, true,
-                              [&](double cc, double scv, double h) { gl::arc_gk(F, cc, scv, h, Sm, ct); }, ct, plan);
+                              [&](double cc, double scv, double h, int lev) { gl::arc_gk(F, cc, scv, h, Sm, ct, lev); },
+                              ct, plan);
         else
             gl::boundary_walk(H, F, bp, kind, nb, Sm, true,
-                              [&](double cc, double scv, double h) { gl::arc_gk(F, cc, scv, h, Sm, nc); }, nc, plan);
+                              [&](double cc, double scv, double h, int lev) { gl::arc_gk(F, cc, scv, h, Sm, nc, lev); },
+                              nc, plan);
         P.fsub[sub] = 1.0 - gl::sums_delta(S, Sm);
     }
     if (CENSUS) {
@@ -793,8 +840,8 @@ __global__ void __launch_bounds__(64)
 k_gk(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
 {
     constexpr int np = 1 << L;
-    constexpr int lin = (L == 0) ? L_ARC : L_LVL1 + L - 1;                  // input list
-    constexpr int lout = (L < gl::kArcMaxLevel) ? L_LVL1 + L : L_LVL1;      // output list
+    constexpr int lin = L_LVL0 + L;                                          // input list
+    constexpr int lout = (L < gl::kArcMaxLevel) ? L_LVL0 + L + 1 : L_LVL0;  // output list
     const int lane = threadIdx.x;
     const unsigned long long lt = lanemask_lt(lane);
     const int64_t scap = P.scap[lin];
@@ -811,7 +858,7 @@ k_gk(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
         gl::Sums K{0.0, 0.0, 0.0};
         double err = 0.0;
         if (valid) {
-            a = (L == 0) ? (int)slot : P.lvl[L][slot];
+            a = P.lvl[L][slot];
             A = P.arcs[a];
             if (A.hard >= 0) {  // (negative: slot of an overflowing wavefront, skipped)
                 const HardRec& R = P.hrec[A.hard];
@@ -851,6 +898,35 @@ k_gk(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
         }
     }
     if (CENSUS) census_add(ctr, 5, pieces);
+}
+
+// Arcs that failed levels 0 and 1 (rare): one thread per arc runs the rule
+// from level 2 on in place.
+template <bool CENSUS>
+__global__ void __launch_bounds__(64)
+k_gk_tail(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
+{
+    const int lane = threadIdx.x;
+    const int64_t scap = P.scap[L_LVL0 + 2];
+    const ShardMap m = shard_map(ctr, L_LVL0 + 2, scap);
+    gl::Census ct;
+    gl::NoCensus nc;
+    for (int64_t g0 = (int64_t)blockIdx.x * 64; g0 < m.total; g0 += (int64_t)gridDim.x * 64) {
+        const int64_t g = g0 + lane;
+        const int64_t slot = shard_slot(m, g < m.total ? g : 0, scap);
+        if (g >= m.total) continue;
+        const int a = P.lvl[2][slot];
+        const ArcRec A = P.arcs[a];
+        const HardRec& R = P.hrec[A.hard];
+        const gl::SetConst& S = sc[R.set];
+        gl::Frame F;
+        gl::make_frame(S, R.x0, R.y0, R.c0a, R.s0a, F);
+        gl::Sums K{0.0, 0.0, 0.0};
+        if (CENSUS) gl::arc_gk(F, A.cc, A.sc, A.h, K, ct, 2);
+        else gl::arc_gk(F, A.cc, A.sc, A.h, K, nc, 2);
+        P.arc_res[a] = K;
+    }
+    if (CENSUS) census_add(ctr, 5, (unsigned long long)ct.arcs);
 }
 
 // Hard samples with ellipse arcs: limb sums plus the accepted arc sums in
@@ -896,10 +972,9 @@ k_average(const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_b
         const int64_t base = uniform64(W.base), c = uniform64(W.c);
         if (base < 0) continue;
         if (__builtin_amdgcn_readfirstlane(chunk_fb[c])) continue;  // evaluated by the fused kernel
-        const unsigned long long M = (unsigned long long)uniform64((int64_t)masks[c]);
-        const int64_t s = uniform64(chunk_set[c]);
-        const int nss = sc[s].n_ss;
-        const int64_t i0 = seg_begin[s] + (c - chunk_off[s]) * kChunk;
+        const unsigned long long M = (unsigned long long)uniform64((int64_t)W.mask);
+        const int nss = __builtin_amdgcn_readfirstlane(W.nss);
+        const int64_t i0 = uniform64(W.i0);
         if ((M >> lane) & 1ull) {
             const int64_t o = __popcll(M & lanemask_lt(lane));
             const double* f = P.fsub + base + o * nss;
@@ -1289,7 +1364,7 @@ gl_status ensure_pipe(gl_ctx* ctx, int64_t n_chunks)
     sc_[L_HARD] = (ch + kShards - 1) / kShards;
     sc_[L_NEST] = sc_[L_HARD];
     sc_[L_ARC] = (ca + kShards - 1) / kShards;
-    for (int L = 1; L < kLevels; ++L) sc_[L_LVL1 + L - 1] = sc_[L_ARC];
+    for (int L = 0; L < kLevels; ++L) sc_[L_LVL0 + L] = sc_[L_ARC];
     Pipe& P = ctx->pipe;
     bool same = ctx->have_pipe && ctx->pipe_chunks >= n_chunks;
     for (int l = 0; l < kLists && same; ++l) same = P.scap[l] == sc_[l];
@@ -1309,7 +1384,7 @@ gl_status ensure_pipe(gl_ctx* ctx, int64_t n_chunks)
               hipMalloc(&P.hrec, sizeof(HardRec) * K * sc_[L_HARD]) == hipSuccess &&
               hipMalloc(&P.arcs, sizeof(ArcRec) * K * sc_[L_ARC]) == hipSuccess &&
               hipMalloc(&P.arc_res, sizeof(gl::Sums) * K * sc_[L_ARC]) == hipSuccess;
-    for (int L = 1; L < kLevels && ok; ++L)
+    for (int L = 0; L < kLevels && ok; ++L)
         ok = hipMalloc(&P.lvl[L], sizeof(int) * K * sc_[L_ARC]) == hipSuccess;
     if (!ok) {
         free_pipe(ctx);
@@ -1378,13 +1453,10 @@ void launch_arcs(gl_ctx* ctx, hipStream_t st, unsigned grid)
     const Pipe& P = ctx->pipe;
     hipLaunchKernelGGL((k_gk<0, CENSUS>), dim3(grid), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
     hipLaunchKernelGGL((k_gk<1, CENSUS>), dim3(grid), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
-    // few arcs reach the deeper levels: smaller persistent grids there
-    const unsigned small = std::max(1u, grid / 8);
-    hipLaunchKernelGGL((k_gk<2, CENSUS>), dim3(small), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
-    hipLaunchKernelGGL((k_gk<3, CENSUS>), dim3(small), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
-    hipLaunchKernelGGL((k_gk<4, CENSUS>), dim3(small), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
+    // few arcs reach the deeper levels: one small launch finishes them per lane
+    hipLaunchKernelGGL((k_gk_tail<CENSUS>), dim3(std::max(1u, grid / 16)), dim3(64), 0, st, ctx->sc,
+                       ctx->ctr, P);
 }
-static_assert(kLevels == 5, "launch_arcs launches levels 0..4");
 
 template <bool CENSUS>
 gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
@@ -1402,16 +1474,18 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     do { if (ev) GL_HIP(hipEventRecord(ev[e++], st), "hipEventRecord"); } while (0)
     const Pipe& P = ctx->pipe;
     const unsigned prep_blocks = (unsigned)((b.n_sets + 255) / 256);
+    const int64_t cps_shared = shared ? (b.n_times + kChunk - 1) / kChunk : 0;
     hipLaunchKernelGGL(k_prep, dim3(prep_blocks), dim3(256), 0, st, b.params, b.n_sets,
                        b.offsets, b.n_times, b.n_ss, b.t_exp, ctx->sc, ctx->seg_begin,
-                       ctx->seg_len, ctx->chunk_off, ctx->ctr);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, ctx->chunk_off, b.n_sets,
-                       b.max_chunks, ctx->ctr);
+                       ctx->seg_len, ctx->chunk_off, ctx->ctr, cps_shared);
+    if (!shared)
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, ctx->chunk_off, b.n_sets,
+                           b.max_chunks, ctx->ctr);
     GL_STAGE_DONE();
     const int64_t n_cu = ctx->n_cu;
     launch_window(ctx, b, st, 1);
     const unsigned waves = (unsigned)std::max<int64_t>(4, n_cu * ctx->waves_per_cu);
-    hipLaunchKernelGGL(k_classify<CENSUS>, dim3(waves), dim3(64), 0, st, b.times, shared, ctx->sc,
+    hipLaunchKernelGGL(k_classify<CENSUS>, dim3((unsigned)(n_cu * 24)), dim3(64), 0, st, b.times, shared, ctx->sc,
                        ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks, ctx->chunk_set,
                        ctx->chunk_fb);
     GL_STAGE_DONE();
@@ -1423,13 +1497,13 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     hipLaunchKernelGGL(k_nested<CENSUS>, dim3((unsigned)(n_cu * 4)), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
     GL_STAGE_DONE();
     launch_arcs<CENSUS>(ctx, st, waves);
-    hipLaunchKernelGGL(k_combine, dim3((unsigned)(n_cu * 4)), dim3(256), 0, st, ctx->sc, ctx->ctr, P);
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)(n_cu * 8)), dim3(256), 0, st, ctx->sc, ctx->ctr, P);
     GL_STAGE_DONE();
-    hipLaunchKernelGGL(k_average, dim3((unsigned)(n_cu * 8)), dim3(64), 0, st, ctx->sc,
+    hipLaunchKernelGGL(k_average, dim3((unsigned)(n_cu * 32)), dim3(64), 0, st, ctx->sc,
                        ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks, ctx->chunk_set,
                        ctx->chunk_fb, b.out);
     GL_STAGE_DONE();
-    hipLaunchKernelGGL(k_compute<CENSUS>, dim3((unsigned)n_cu), dim3(64), 0, st, b.times, shared,
+    hipLaunchKernelGGL(k_compute<CENSUS>, dim3((unsigned)std::max<int64_t>(1, n_cu / 4)), dim3(64), 0, st, b.times, shared,
                        ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, ctx->masks, ctx->chunk_set,
                        P.fb_chunk, b.out);
     GL_STAGE_DONE();
@@ -2061,7 +2135,7 @@ gl_status gl_lightcurve_batch_surrogate(gl_ctx* ctx, gl_mlp* mlp, const float* t
     const int shared = b.offsets ? 0 : 1;
     hipLaunchKernelGGL(k_prep, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, s, params, n_sets,
                        offsets, n_times, n_ss, t_exp, ctx->sc, ctx->seg_begin, ctx->seg_len,
-                       ctx->chunk_off, ctx->ctr);
+                       ctx->chunk_off, ctx->ctr, (int64_t)0);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, ctx->chunk_off, n_sets, b.max_chunks, ctx->ctr);
     launch_window(ctx, b, s, 0);
     hipLaunchKernelGGL(k_sub_count, dim3((unsigned)((b.max_chunks + 255) / 256)), dim3(256), 0, s, ctx->masks,
