@@ -340,9 +340,13 @@ GL_HD double bracket_root(const Poly4& q, double lo, double hi, double flo, doub
         if (fabs(f) <= 8e-16 * noise) return x;
         if ((f < 0.0) == (flo < 0.0)) lo = x;
         else hi = x;
-        double xn = x - f / df;
+        double xn = x - f * rcp(df);
         if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-        if (fabs(xn - x) <= 2e-16 * fmax(1.0, ax) || hi - lo <= 2e-16 * fmax(1.0, ax)) return xn;
+        // a Newton step below 1e-8 leaves an error of its square (quadratic
+        // convergence); near a double root, where convergence is linear, an
+        // error of 1e-8 in t moves the region boundary by a sliver of area
+        // O(1e-16) (the limb closes the contour radially there)
+        if (fabs(xn - x) <= 1e-8 * fmax(1.0, ax) || hi - lo <= 2e-16 * fmax(1.0, ax)) return xn;
         x = xn;
     }
     return x;

@@ -260,6 +260,19 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Occupancy requests of the list kernels (waves per SIMD; 0 = the compiler's
+// choice), for launch-plan experiments at build time.
+#ifndef GL_WAVES_TRAP
+#define GL_WAVES_TRAP 0
+#endif
+#ifndef GL_WAVES_HARD
+#define GL_WAVES_HARD 4  // measured: 4 waves/SIMD (a few spills) beats 3 (no spills) by ~10 %
+#endif
+#ifndef GL_WAVES_GK
+#define GL_WAVES_GK 0
+#endif
+#define GL_WAVES(n) __attribute__((amdgpu_waves_per_eu((n) > 0 ? (n) : 1)))
+
 // ---------------------------------------------------------------- work-list helpers
 __device__ __forceinline__ unsigned long long lanemask_lt(int lane)
 {
@@ -563,7 +576,7 @@ constexpr int kTrapRounds = 4;
 constexpr int kTrapBuckets = gl::kTrapOrders + 1;  // the last bucket holds empty slots
 
 template <bool CENSUS>
-__global__ void __launch_bounds__(kTrapThreads)
+__global__ void __launch_bounds__(kTrapThreads) GL_WAVES(GL_WAVES_TRAP)
 k_trap(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
 {
     __shared__ int lds_slot[kTrapRounds * kTrapThreads];
@@ -641,7 +654,7 @@ k_trap(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
 constexpr int kInPlace = 1 << kSubBits;  // in-place entry flag: arcs integrated per lane
 
 template <bool CENSUS>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) GL_WAVES(GL_WAVES_HARD)
 k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
 {
     const int lane = threadIdx.x;
@@ -836,7 +849,7 @@ k_nested(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P
 // order on every lane).  Accepted when the summed difference is within the
 // tolerance (or at the last level); otherwise the arc enters level L + 1.
 template <int L, bool CENSUS>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) GL_WAVES(GL_WAVES_GK)
 k_gk(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
 {
     constexpr int np = 1 << L;
