@@ -173,7 +173,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the exact path "
-              "shards by walker with no communication, see DESIGN.md", file=sys.stderr)
+              "shards by walker with no communication between GPUs", file=sys.stderr)
         sys.exit(2)
 
     import torch
