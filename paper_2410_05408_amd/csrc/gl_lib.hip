@@ -4,8 +4,9 @@
 //   k_prep      one thread per parameter set: domain checks, derived constants
 //               (projected ellipse from eqs. dx, dy1, dy2, orbit, limb darkening),
 //               CSR segment checks, number of 64-output chunks per set.
-//   k_scan      one workgroup: exclusive scan of the chunk counts.
-//   k_window    one wavefront per 4 chunks of 64 consecutive outputs of one set:
+//   k_scan      one workgroup: exclusive scan of the chunk counts (CSR only).
+//   k_window    one wavefront per 16 (shared grid) or 4 (CSR) chunks of 64
+//               consecutive outputs of one set (k_window_grid / k_window):
 //               outputs whose exposure cannot overlap the star are written as
 //               1 (NaN for an invalid set); chunks with in-window outputs get
 //               flux slots for their sub-samples, a work-chunk entry and one
@@ -111,21 +112,24 @@ struct Group {
     int set, pad;
 };
 
-// A hard sample after its boundary walk: the frame anchor, the closed-form
-// limb sums and its range in the arc list.
+// A hard sample after its boundary walk: the closed-form limb sums and its
+// range in the arc list (what the final combination reads).  Its ellipse
+// frame is kept beside it, in an array of its own indexed the same way.
 struct HardRec {
-    double x0, y0, c0a, s0a;
     gl::Sums limb;
     int set, sub;
     int arc_begin, n_arcs;  // n_arcs = 0: the flux slot is already written
 };
 
-// One ellipse arc on the star (tau-rule description) of the hard sample in
-// slot `hard`.
+// One ellipse arc on the star (tau-rule description).
 struct ArcRec {
     double cc, sc, h;
-    int hard;  // -1: empty slot
-    int pad;
+};
+
+// Entry of a level list: an arc and the hard slot whose frame it uses, so
+// that the two records load side by side.
+struct ArcRef {
+    int arc, hard;
 };
 
 // Device pointers and per-shard capacities of the work lists.
@@ -138,9 +142,10 @@ struct Pipe {
     Entry* hard;
     Entry* nest;
     HardRec* hrec;         // indexed like `hard`
+    gl::Frame* hfr;        // indexed like `hard`: ellipse frame of a sample with arcs
     ArcRec* arcs;
     gl::Sums* arc_res;     // indexed like `arcs`
-    int* lvl[kLevels];     // arcs evaluated at level L
+    ArcRef* lvl[kLevels];  // arcs evaluated at level L
     int64_t scap[kLists];  // entries per shard
 };
 
@@ -272,6 +277,12 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
 #define GL_WAVES_GK 0
 #endif
 #define GL_WAVES(n) __attribute__((amdgpu_waves_per_eu((n) > 0 ? (n) : 1)))
+// Persistent grid of the arc-rule levels in wavefronts per CU (0: the plan's);
+// 20 = five per SIMD, what their register use allows (measured ~4 % faster
+// than the plan's 16 on the arc stage).
+#ifndef GL_GK_WAVES_PER_CU
+#define GL_GK_WAVES_PER_CU 20
+#endif
 
 // ---------------------------------------------------------------- work-list helpers
 __device__ __forceinline__ unsigned long long lanemask_lt(int lane)
@@ -345,22 +356,119 @@ __device__ __forceinline__ void to_fused(Counters* ctr, const Pipe& P, int* chun
     if (atomicExch(&chunk_fb[c], 1) == 0) P.fb_chunk[atomicAdd(&ctr->n_fb, 1ull)] = c;
 }
 
-// Window test: one wavefront per group of kWinChunks consecutive chunks (their
-// memory operations overlap): outputs whose exposure cannot overlap the star
-// are written as 1 (NaN for an invalid set or a non-finite time); a 64-bit
-// mask of the others and the chunk's set are kept.  With `lists`, every chunk
-// with in-window outputs gets its flux slots, a work-chunk entry and one group
-// entry per 64 sub-samples (one reservation per list for the wavefront); a
-// chunk that does not fit is queued for the fused kernel.
+// Window test: outputs whose exposure cannot overlap the star are written as
+// 1 (NaN for an invalid set or a non-finite time); a 64-bit mask of the others
+// and the chunk's set are kept.  With `lists`, every chunk with in-window
+// outputs gets its flux slots, a work-chunk entry and one group entry per 64
+// sub-samples (one reservation per list for the wavefront); a chunk that does
+// not fit is queued for the fused kernel.
+
+// Appends the wavefront's chunks with in-window outputs to the lists: lane k
+// describes chunk c_k (cnt_k sub-samples, 0 if none), positions come from
+// wavefront scans, one reservation per list.
+__device__ __forceinline__ void window_lists(Counters* ctr, const Pipe& P, int* chunk_fb, int shard,
+                                             int64_t c_k, int cnt_k, unsigned long long mask_k,
+                                             int64_t i0_k, int64_t tb_k, int nss_k, int set_k)
+{
+    const int lane = threadIdx.x & 63;
+    const int ng_k = (cnt_k + kChunk - 1) / kChunk;
+    // inclusive scans: sub-samples and (work chunks | groups << 16)
+    int64_t isub = cnt_k;
+    int iwg = (cnt_k > 0 ? 1 : 0) | (ng_k << 16);
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t v = __shfl_up(isub, d);
+        const int u = __shfl_up(iwg, d);
+        if (lane >= d) {
+            isub += v;
+            iwg += u;
+        }
+    }
+    const int64_t tot_sub = __shfl(isub, 63);
+    const int tot_wg = __shfl(iwg, 63);
+    int64_t os = reserve(ctr, L_SUB, shard, (unsigned long long)tot_sub);
+    int64_t ow = reserve(ctr, L_WC, shard, (unsigned long long)(tot_wg & 0xffff));
+    int64_t og = reserve(ctr, L_GRP, shard, (unsigned long long)(tot_wg >> 16));
+    if (cnt_k == 0) return;
+    os += isub - cnt_k;
+    ow += (iwg & 0xffff) - 1;
+    og += (iwg >> 16) - ng_k;
+    const int64_t scs = P.scap[L_SUB], scw = P.scap[L_WC], scg = P.scap[L_GRP];
+    const bool ok = os + cnt_k <= scs && ow < scw && og + ng_k <= scg;
+    const int64_t base = ok ? (int64_t)shard * scs + os : -1;
+    chunk_fb[c_k] = 0;
+    if (ow < scw) P.wc[(int64_t)shard * scw + ow] = WorkChunk{c_k, base, mask_k, i0_k, nss_k, 0};
+    for (int j = 0; j < ng_k && og + j < scg; ++j)
+        P.grp[(int64_t)shard * scg + og + j] = Group{ok ? c_k : -1, base, mask_k, tb_k, j * kChunk, cnt_k, set_k, 0};
+    if (!ok) to_fused(ctr, P, chunk_fb, c_k);
+}
+
+// One time grid for every set: one wavefront per kWinGrid consecutive chunks
+// of one set (bx = ceil(chunks per set / kWinGrid) wavefronts per set, set
+// major);
+// every time load is issued before the first test, and lane k keeps chunk k's
+// mask for one store of all of them.
+constexpr int kWinGrid = 16;
+
+__global__ void __launch_bounds__(64)
+k_window_grid(const double* __restrict__ times, int64_t n_times, int64_t cps,
+              const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr,
+              unsigned long long* __restrict__ masks, int* __restrict__ chunk_set,
+              double* __restrict__ out, int lists, Pipe P, int* __restrict__ chunk_fb)
+{
+    const int lane = threadIdx.x;
+    const int64_t bx = (cps + kWinGrid - 1) / kWinGrid;
+    const int64_t s = (int64_t)blockIdx.x / bx;
+    const int64_t lc0 = ((int64_t)blockIdx.x - s * bx) * kWinGrid;  // first chunk, within the set
+    const int nk = (int)std::min<int64_t>(kWinGrid, cps - lc0);
+    const int64_t ob = s * n_times;  // the set's first output
+    const gl::SetConst& S = sc[s];
+    double t[kWinGrid];
+#pragma unroll
+    for (int k = 0; k < kWinGrid; ++k) {
+        const int64_t pos = (lc0 + k) * kChunk + lane;
+        t[k] = (k < nk && pos < n_times) ? times[pos] : 0.0;
+    }
+    const bool valid = S.valid;
+    const double reach = S.half_win + 0.5 * S.t_exp;
+    unsigned long long my_mask = 0ull, any = 0ull;
+#pragma unroll
+    for (int k = 0; k < kWinGrid; ++k) {
+        const int64_t pos = (lc0 + k) * kChunk + lane;
+        bool work = false;
+        if (k < nk && pos < n_times) {
+            if (!valid || !gl::finite_d(t[k])) {
+                out[ob + pos] = __builtin_nan("");
+                if (valid) atomicOr(&ctr->status, 4u);
+            } else {
+                work = fabs(gl::phase_time(S, t[k])) < reach;
+                // streamed past the caches: the 1s are never read back, and
+                // keeping them out of L2 leaves it to the work lists
+                if (!work) __builtin_nontemporal_store(1.0, out + ob + pos);
+            }
+        }
+        const unsigned long long m = __ballot(work);
+        if (lane == k) my_mask = m;
+        any |= m;
+    }
+    const int64_t c = s * cps + lc0 + lane;  // lane k: chunk k
+    if (lane < nk) {
+        masks[c] = my_mask;
+        chunk_set[c] = (int)s;
+    }
+    if (!lists || !any) return;
+    const int cnt = lane < nk ? __popcll(my_mask) * S.n_ss : 0;
+    const int64_t tb = (lc0 + lane) * kChunk;
+    const int shard = (int)(blockIdx.x % kShards);
+    window_lists(ctr, P, chunk_fb, shard, c, cnt, my_mask, ob + tb, tb, S.n_ss, (int)s);
+}
+
+// CSR segments: one wavefront per group of kWinChunks consecutive chunks (their
+// memory operations overlap), the set of the first chunk found by binary
+// search and stepped along from there.
 constexpr int kWinChunks = 4;
 
-// SHARED (one time grid for every set): grid (ceil(chunks per set / 16),
-// n_sets) of 4-wavefront blocks, the set is the block row.  CSR: a 1-D grid
-// over all chunks, the set of the first chunk found by binary search and
-// stepped along from there.
-template <bool SHARED>
 __global__ void __launch_bounds__(256)
-k_window(const double* __restrict__ times, int64_t n_sets, int64_t cps,
+k_window(const double* __restrict__ times, int64_t n_sets,
          const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_begin,
          const int64_t* __restrict__ seg_len, const int64_t* __restrict__ chunk_off,
          Counters* __restrict__ ctr, unsigned long long* __restrict__ masks,
@@ -370,48 +478,33 @@ k_window(const double* __restrict__ times, int64_t n_sets, int64_t cps,
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int64_t total = (int64_t)ctr->total_chunks;
-    int cnt[kWinChunks], set_k[kWinChunks], nss_k[kWinChunks];
-    unsigned long long mask_k[kWinChunks];
-    int64_t i0_k[kWinChunks], tb_k[kWinChunks];
-    int64_t g, c_first, s, lc_first = 0;
-    if (SHARED) {
-        s = blockIdx.y;
-        lc_first = ((int64_t)blockIdx.x * 4 + wv) * kWinChunks;
-        c_first = s * cps + lc_first;
-        g = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 + wv;
-    } else {
-        g = (int64_t)blockIdx.x * 4 + wv;
-        c_first = g * kWinChunks;
-        s = 0;
-        if (c_first < total) s = uniform64(set_of_chunk(chunk_off, n_sets, c_first));
-    }
+    const int64_t g = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t c_first = g * kWinChunks;
+    int64_t s = 0;
+    if (c_first < total) s = uniform64(set_of_chunk(chunk_off, n_sets, c_first));
+    // lane k (k < kWinChunks) collects chunk k's description for the lists
+    int cnt_l = 0, nss_l = 0, set_l = 0;
+    unsigned long long mask_l = 0ull, any = 0ull;
+    int64_t i0_l = 0;
 #pragma unroll
     for (int k = 0; k < kWinChunks; ++k) {
-        cnt[k] = 0;
-        set_k[k] = nss_k[k] = 0;
-        mask_k[k] = 0ull;
-        i0_k[k] = tb_k[k] = 0;
         const int64_t c = c_first + k;
-        if (SHARED) {
-            if (lc_first + k >= cps) continue;
-        } else {
-            if (c >= total) continue;
-            while (s + 1 < n_sets && chunk_off[s + 1] <= c) ++s;  // uniform
-        }
-        const int64_t pos = (SHARED ? lc_first + k : c - chunk_off[s]) * kChunk + lane;  // position in the segment
+        if (c >= total) continue;
+        while (s + 1 < n_sets && chunk_off[s + 1] <= c) ++s;  // uniform
+        const int64_t pos = (c - chunk_off[s]) * kChunk + lane;  // position in the segment
         const bool in_seg = pos < seg_len[s];
         const int64_t i = seg_begin[s] + pos;
         const gl::SetConst& S = sc[s];
         bool work = false;
         if (in_seg) {
-            const double t = SHARED ? times[pos] : times[i];
+            const double t = times[i];
             if (!S.valid || !gl::finite_d(t)) {
                 out[i] = __builtin_nan("");
                 if (S.valid) atomicOr(&ctr->status, 4u);
             } else {
                 const double tau = gl::phase_time(S, t);
                 work = fabs(tau) < S.half_win + 0.5 * S.t_exp;
-                if (!work) out[i] = 1.0;
+                if (!work) __builtin_nontemporal_store(1.0, out + i);
             }
         }
         const unsigned long long m = __ballot(work);
@@ -419,49 +512,18 @@ k_window(const double* __restrict__ times, int64_t n_sets, int64_t cps,
             masks[c] = m;
             chunk_set[c] = (int)s;
         }
-        if (m) {
-            cnt[k] = __popcll(m) * S.n_ss;
-            set_k[k] = (int)s;
-            nss_k[k] = S.n_ss;
-            mask_k[k] = m;
-            i0_k[k] = seg_begin[s] + (pos - lane);
-            tb_k[k] = SHARED ? pos - lane : i0_k[k];
+        any |= m;
+        if (lane == k) {
+            mask_l = m;
+            cnt_l = __popcll(m) * S.n_ss;
+            nss_l = S.n_ss;
+            set_l = (int)s;
+            i0_l = seg_begin[s] + (c - chunk_off[s]) * kChunk;
         }
     }
-    if (!lists) return;
-    int tot_sub = 0, tot_wc = 0, tot_grp = 0;
-#pragma unroll
-    for (int k = 0; k < kWinChunks; ++k) {
-        tot_sub += cnt[k];
-        tot_wc += cnt[k] > 0;
-        tot_grp += (cnt[k] + kChunk - 1) / kChunk;
-    }
-    if (tot_wc == 0) return;
-    const int shard = (int)(g % kShards);
-    int64_t os = reserve(ctr, L_SUB, shard, (unsigned long long)tot_sub);
-    int64_t ow = reserve(ctr, L_WC, shard, (unsigned long long)tot_wc);
-    int64_t og = reserve(ctr, L_GRP, shard, (unsigned long long)tot_grp);
-    const int64_t scs = P.scap[L_SUB], scw = P.scap[L_WC], scg = P.scap[L_GRP];
-#pragma unroll
-    for (int k = 0; k < kWinChunks; ++k) {
-        if (cnt[k] == 0) continue;
-        const int64_t c = c_first + k;  // the chunk whose count is cnt[k]
-        const int ng = (cnt[k] + kChunk - 1) / kChunk;
-        const bool ok = os + cnt[k] <= scs && ow < scw && og + ng <= scg;
-        const int64_t base = ok ? (int64_t)shard * scs + os : -1;
-        if (lane == 0) {
-            chunk_fb[c] = 0;
-            if (ow < scw)
-                P.wc[(int64_t)shard * scw + ow] = WorkChunk{c, base, mask_k[k], i0_k[k], nss_k[k], 0};
-        }
-        if (lane < ng && og + lane < scg)
-            P.grp[(int64_t)shard * scg + og + lane] =
-                Group{ok ? c : -1, base, mask_k[k], tb_k[k], lane * kChunk, cnt[k], set_k[k], 0};
-        if (!ok && lane == 0) to_fused(ctr, P, chunk_fb, c);
-        os += cnt[k];
-        ow += 1;
-        og += ng;
-    }
+    if (!lists || !any) return;
+    window_lists(ctr, P, chunk_fb, (int)(g % kShards), c_first + lane, cnt_l, mask_l, i0_l, i0_l, nss_l,
+                 set_l);
 }
 
 // Classification: one wavefront per group of up to 64 sub-samples of one
@@ -727,9 +789,8 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
             gl::Sums Sm{0.0, 0.0, 0.0};
             const int64_t first = ap + incl - na;
             if (over && na > 0) {
-                // arcs do not fit: the whole sample is integrated in place later;
-                // this lane's reserved slots below the capacity are marked empty
-                for (int64_t k = first; k < first + na && k < acap; ++k) al[k].hard = -1;
+                // arcs do not fit: the whole sample is integrated in place later
+                // (no index-list entry refers to this lane's reserved arc slots)
                 P.hrec[slot].n_arcs = 0;
                 to_list = true;
                 flag = kInPlace;
@@ -741,10 +802,10 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
                 int64_t k0 = l0p + incl0 - (na - na1), k1 = l1p + incl1 - na1;
                 auto put = [&](double cc, double scv, double h, int lev) {
                     if (k < first + na) {
-                        al[k] = ArcRec{cc, scv, h, (int)slot, 0};
-                        const int a = (int)((int64_t)shard * acap + k);
-                        if (lev == 0) P.lvl[0][(int64_t)shard * lcap + (k0++)] = a;
-                        else P.lvl[1][(int64_t)shard * lcap + (k1++)] = a;
+                        al[k] = ArcRec{cc, scv, h};
+                        const ArcRef r{(int)((int64_t)shard * acap + k), (int)slot};
+                        if (lev == 0) P.lvl[0][(int64_t)shard * lcap + (k0++)] = r;
+                        else P.lvl[1][(int64_t)shard * lcap + (k1++)] = r;
                     }
                     ++k;
                 };
@@ -754,8 +815,8 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
                     P.fsub[e.sub] = 1.0 - gl::sums_delta(S, Sm);
                     P.hrec[slot].n_arcs = 0;
                 } else {
-                    P.hrec[slot] = HardRec{e.x0, e.y0, H.c0a, H.s0a, Sm, e.set, e.sub,
-                                           (int)((int64_t)shard * acap + first), na};
+                    P.hrec[slot] = HardRec{Sm, e.set, e.sub, (int)((int64_t)shard * acap + first), na};
+                    P.hfr[slot] = F;
                     if (CENSUS) c_arcs += na;
                 }
             }
@@ -866,22 +927,17 @@ k_gk(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
         const bool valid = p < n;
         const int q = (int)(p & (np - 1));
         const int64_t slot = shard_slot(m, valid ? (p >> L) : 0, scap);
-        int a = -1;
-        ArcRec A{0.0, 0.0, 0.0, -1, 0};
+        ArcRef r{-1, -1};
         gl::Sums K{0.0, 0.0, 0.0};
         double err = 0.0;
-        if (valid) {
-            a = P.lvl[L][slot];
-            A = P.arcs[a];
-            if (A.hard >= 0) {  // (negative: slot of an overflowing wavefront, skipped)
-                const HardRec& R = P.hrec[A.hard];
-                const gl::SetConst& S = sc[R.set];
-                gl::Frame F;
-                gl::make_frame(S, R.x0, R.y0, R.c0a, R.s0a, F);
-                const double half = A.h / np;
-                err = gl::gk_piece<true>(F, A.cc, A.sc, -A.h + (2 * q + 1) * half, half, K);
-                if (CENSUS) pieces += 1;
-            }
+        if (valid) r = P.lvl[L][slot];
+        const int a = r.arc;
+        if (r.hard >= 0) {
+            const ArcRec A = P.arcs[a];
+            const gl::Frame F = P.hfr[r.hard];
+            const double half = A.h / np;
+            err = gl::gk_piece<true>(F, A.cc, A.sc, -A.h + (2 * q + 1) * half, half, K);
+            if (CENSUS) pieces += 1;
         }
 #pragma unroll
         for (int d = 1; d < np; d <<= 1) {
@@ -890,7 +946,7 @@ k_gk(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
             K.quad += __shfl_xor(K.quad, d);
             err += __shfl_xor(err, d);
         }
-        const bool lead = valid && q == 0 && A.hard >= 0;
+        const bool lead = q == 0 && r.hard >= 0;
         const bool accept = err <= gl::kArcTol || L == gl::kArcMaxLevel;
         if (lead && accept) P.arc_res[a] = K;
         if (L < gl::kArcMaxLevel) {
@@ -905,7 +961,7 @@ k_gk(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
                 const unsigned long long mj = __ballot(want && hs == j);
                 const int64_t op = reserve(ctr, lout, j, (unsigned long long)__popcll(mj));
                 if (want && hs == j)
-                    P.lvl[L + 1 < kLevels ? L + 1 : L][(int64_t)j * P.scap[lout] + op + __popcll(mj & lt)] = a;
+                    P.lvl[L + 1 < kLevels ? L + 1 : L][(int64_t)j * P.scap[lout] + op + __popcll(mj & lt)] = r;
                 pending &= ~mj;
             }
         }
@@ -928,16 +984,13 @@ k_gk_tail(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe 
         const int64_t g = g0 + lane;
         const int64_t slot = shard_slot(m, g < m.total ? g : 0, scap);
         if (g >= m.total) continue;
-        const int a = P.lvl[2][slot];
-        const ArcRec A = P.arcs[a];
-        const HardRec& R = P.hrec[A.hard];
-        const gl::SetConst& S = sc[R.set];
-        gl::Frame F;
-        gl::make_frame(S, R.x0, R.y0, R.c0a, R.s0a, F);
+        const ArcRef r = P.lvl[2][slot];
+        const ArcRec A = P.arcs[r.arc];
+        const gl::Frame F = P.hfr[r.hard];
         gl::Sums K{0.0, 0.0, 0.0};
         if (CENSUS) gl::arc_gk(F, A.cc, A.sc, A.h, K, ct, 2);
         else gl::arc_gk(F, A.cc, A.sc, A.h, K, nc, 2);
-        P.arc_res[a] = K;
+        P.arc_res[r.arc] = K;
     }
     if (CENSUS) census_add(ctr, 5, (unsigned long long)ct.arcs);
 }
@@ -959,18 +1012,26 @@ k_combine(const gl::SetConst* __restrict__ sc, const Counters* __restrict__ ctr,
         const int na = R.n_arcs;
         if (na <= 0) continue;
         gl::Sums S = R.limb;
-        for (int k = 0; k < na; ++k) {
-            const gl::Sums& B = P.arc_res[R.arc_begin + k];
-            S.flat += B.flat;
-            S.lin += B.lin;
-            S.quad += B.quad;
+        const int ab = R.arc_begin;
+        for (int k0 = 0; k0 < na; k0 += 4) {  // four arcs per memory round trip, added in order
+            gl::Sums B[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) B[k] = k0 + k < na ? P.arc_res[ab + k0 + k] : gl::Sums{0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (k0 + k < na) {
+                    S.flat += B[k].flat;
+                    S.lin += B[k].lin;
+                    S.quad += B[k].quad;
+                }
         }
         P.fsub[R.sub] = 1.0 - gl::sums_delta(sc[R.set], S);
     }
 }
 
 // One wavefront per listed chunk: each in-window output averages its
-// sub-sample fluxes in order.
+// sub-sample fluxes in order (loaded 16 at a time, so that one memory round
+// trip serves up to 16 of them, then summed one by one).
 __global__ void __launch_bounds__(64)
 k_average(const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_begin,
           const int64_t* __restrict__ chunk_off, const Counters* __restrict__ ctr, Pipe P,
@@ -992,7 +1053,14 @@ k_average(const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_b
             const int64_t o = __popcll(M & lanemask_lt(lane));
             const double* f = P.fsub + base + o * nss;
             double sum = 0.0;
-            for (int j = 0; j < nss; ++j) sum += f[j];
+            for (int j0 = 0; j0 < nss; j0 += 16) {
+                double v[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) v[j] = j0 + j < nss ? f[j0 + j] : 0.0;
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    if (j0 + j < nss) sum += v[j];
+            }
             out[i0 + lane] = sum / (double)nss;
         }
     }
@@ -1285,8 +1353,8 @@ void free_sur(gl_ctx* ctx)
 void free_pipe(gl_ctx* ctx)
 {
     Pipe& P = ctx->pipe;
-    void* b[] = {P.fsub, P.wc, P.grp, P.fb_chunk, P.trap, P.hard, P.nest, P.hrec, P.arcs, P.arc_res,
-                 ctx->chunk_fb};
+    void* b[] = {P.fsub, P.wc, P.grp, P.fb_chunk, P.trap, P.hard, P.nest, P.hrec, P.hfr, P.arcs,
+                 P.arc_res, ctx->chunk_fb};
     for (void* q : b) (void)hipFree(q);
     ctx->chunk_fb = nullptr;
     for (int L = 0; L < kLevels; ++L) (void)hipFree(P.lvl[L]);
@@ -1395,10 +1463,11 @@ gl_status ensure_pipe(gl_ctx* ctx, int64_t n_chunks)
               hipMalloc(&P.hard, sizeof(Entry) * K * sc_[L_HARD]) == hipSuccess &&
               hipMalloc(&P.nest, sizeof(Entry) * K * sc_[L_NEST]) == hipSuccess &&
               hipMalloc(&P.hrec, sizeof(HardRec) * K * sc_[L_HARD]) == hipSuccess &&
+              hipMalloc(&P.hfr, sizeof(gl::Frame) * K * sc_[L_HARD]) == hipSuccess &&
               hipMalloc(&P.arcs, sizeof(ArcRec) * K * sc_[L_ARC]) == hipSuccess &&
               hipMalloc(&P.arc_res, sizeof(gl::Sums) * K * sc_[L_ARC]) == hipSuccess;
     for (int L = 0; L < kLevels && ok; ++L)
-        ok = hipMalloc(&P.lvl[L], sizeof(int) * K * sc_[L_ARC]) == hipSuccess;
+        ok = hipMalloc(&P.lvl[L], sizeof(ArcRef) * K * sc_[L_ARC]) == hipSuccess;
     if (!ok) {
         free_pipe(ctx);
         return fail(ctx, GL_ERR_NOMEM, "work-list allocation");
@@ -1438,6 +1507,8 @@ gl_status check_args(gl_ctx* ctx, Batch& b)
         if (b.n_sets > ((int64_t)1 << 62) / std::max<int64_t>(b.n_times, 1))
             return fail(ctx, GL_ERR_SIZE, "n_sets * n_times overflows");
         b.max_chunks = cps * b.n_sets;
+        if ((cps + kWinGrid - 1) / kWinGrid * b.n_sets > (int64_t)INT32_MAX)
+            return fail(ctx, GL_ERR_SIZE, "batch too large for one window launch");
     }
     if (b.max_chunks > ((int64_t)1 << 40)) return fail(ctx, GL_ERR_SIZE, "batch too large");
     return GL_OK;
@@ -1448,14 +1519,14 @@ void launch_window(gl_ctx* ctx, const Batch& b, hipStream_t st, int lists)
 {
     if (!b.offsets) {
         const int64_t cps = (b.n_times + kChunk - 1) / kChunk;
-        const int64_t bx = (cps + 4 * kWinChunks - 1) / (4 * kWinChunks);
-        hipLaunchKernelGGL(k_window<true>, dim3((unsigned)bx, (unsigned)b.n_sets), dim3(256), 0, st, b.times,
-                           b.n_sets, cps, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off,
-                           ctx->ctr, ctx->masks, ctx->chunk_set, b.out, lists, ctx->pipe, ctx->chunk_fb);
+        const int64_t bx = (cps + kWinGrid - 1) / kWinGrid;
+        hipLaunchKernelGGL(k_window_grid, dim3((unsigned)(bx * b.n_sets)), dim3(64), 0, st, b.times,
+                           b.n_times, cps, ctx->sc, ctx->ctr, ctx->masks, ctx->chunk_set, b.out, lists,
+                           ctx->pipe, ctx->chunk_fb);
     } else {
         const int64_t groups = (b.max_chunks + kWinChunks - 1) / kWinChunks;
-        hipLaunchKernelGGL(k_window<false>, dim3((unsigned)((groups + 3) / 4)), dim3(256), 0, st, b.times,
-                           b.n_sets, (int64_t)0, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off,
+        hipLaunchKernelGGL(k_window, dim3((unsigned)((groups + 3) / 4)), dim3(256), 0, st, b.times,
+                           b.n_sets, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off,
                            ctx->ctr, ctx->masks, ctx->chunk_set, b.out, lists, ctx->pipe, ctx->chunk_fb);
     }
 }
@@ -1509,7 +1580,7 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     GL_STAGE_DONE();
     hipLaunchKernelGGL(k_nested<CENSUS>, dim3((unsigned)(n_cu * 4)), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
     GL_STAGE_DONE();
-    launch_arcs<CENSUS>(ctx, st, waves);
+    launch_arcs<CENSUS>(ctx, st, GL_GK_WAVES_PER_CU > 0 ? (unsigned)(n_cu * GL_GK_WAVES_PER_CU) : waves);
     hipLaunchKernelGGL(k_combine, dim3((unsigned)(n_cu * 8)), dim3(256), 0, st, ctx->sc, ctx->ctr, P);
     GL_STAGE_DONE();
     hipLaunchKernelGGL(k_average, dim3((unsigned)(n_cu * 32)), dim3(64), 0, st, ctx->sc,
