@@ -140,6 +140,22 @@ GL_HD double sqrt_q(double x)
 #endif
 }
 
+// As sqrt_q for an argument known to be positive and normal: nodes of the
+// whole-ellipse trapezoid rule, which stay a bounded distance inside the disk.
+GL_HD double sqrt_qp(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    return fma(fma(-g, g, x), h, g);
+#else
+    return sqrt(x);
+#endif
+}
+
 // sin and cos of a in [-pi, pi] (orbital phase): a = k pi/2 + r with
 // |r| <= pi/4 (pi/2 split in two parts, Cody-Waite style), Taylor series of
 // sin r and cos r to r^17 and r^16 (the next terms are below 1e-17), then the
@@ -466,27 +482,35 @@ GL_HD int arc_start_level(double h) { return h > kArcStartSplit ? 1 : 0; }
 template <bool UNROLL = false>
 GL_HD double gk_piece(const Frame& F, double cc, double sc, double mid, double half, Sums& K)
 {
+    // With u = 1 - tau^2 and inv = 1/(1 + tau^2), cos and sin of the angle are
+    // (cc u - 2 sc tau) inv and (sc u + 2 cc tau) inv, so every quantity that
+    // is linear in them is (a u + b tau) inv with a, b fixed on the piece:
+    // x - x0, y - y0, dx, dy and the flat integrand x y' - y x' - P0.
+    const double axu = F.Xc * cc + F.Xs * sc, axt = 2.0 * (F.Xs * cc - F.Xc * sc);
+    const double ayu = F.Yc * cc + F.Ys * sc, ayt = 2.0 * (F.Ys * cc - F.Yc * sc);
+    const double dxu = 0.5 * axt, dxt = -2.0 * axu;
+    const double dyu = 0.5 * ayt, dyt = -2.0 * ayu;
+    const double fu = F.P1 * cc + F.P2 * sc, ft = 2.0 * (F.P2 * cc - F.P1 * sc);
     double kf = 0.0, kl = 0.0, kq = 0.0, gf = 0.0, gl = 0.0;
     auto node = [&](int j) {
         const double tau = mid + half * GK21_M[j];
-        const double t2 = tau * tau;
-        const double inv = rcp_q(1.0 + t2);
-        const double cu = (1.0 - t2) * inv, su = 2.0 * tau * inv;
-        const double c = cc * cu - sc * su, sn = sc * cu + cc * su;
-        const double x = F.x0 + F.Xc * c + F.Xs * sn;
-        const double y = F.y0 + F.Yc * c + F.Ys * sn;
-        const double dx = -F.Xc * sn + F.Xs * c;
-        const double dy = -F.Yc * sn + F.Ys * c;
+        const double d = fma(tau, tau, 1.0);
+        const double inv = rcp_q(d);
+        const double u = 2.0 - d;
+        const double x = fma(inv, fma(axu, u, axt * tau), F.x0);
+        const double y = fma(inv, fma(ayu, u, ayt * tau), F.y0);
+        const double tdx = fma(dxu, u, dxt * tau), tdy = fma(dyu, u, dyt * tau);  // dx, dy / inv
         const double x2 = x * x, y2 = y * y;
         const double om = fmax(0.0, 1.0 - x2 - y2);
         const double w = sqrt_q(om);
         const double G = 1.0 + om * rcp_q(1.0 + w);         // (1 + w + w^2)/(1 + w)
-        const double flat = F.P0 + F.P1 * c + F.P2 * sn;     // x y' - y x'
-        const double quad = x * (x2 * (1.0 / 3.0) + y2) * dy - y * (x2 + y2 * (1.0 / 3.0)) * dx;
-        const double fl = inv * flat, li = fl * G;           // dpsi = 2 dtau / (1 + tau^2)
+        const double inv2 = inv * inv;
+        const double fl = fma(inv2, fma(fu, u, ft * tau), inv * F.P0);  // (x y' - y x') dpsi/dtau / 2
+        const double li = fl * G;
+        const double tq = x * (x2 * (1.0 / 3.0) + y2) * tdy - y * (x2 + y2 * (1.0 / 3.0)) * tdx;
         kf += GK21_WK[j] * fl;
         kl += GK21_WK[j] * li;
-        kq += GK21_WK[j] * (inv * quad);
+        kq += GK21_WK[j] * (inv2 * tq);
         gf += GK21_WG[j] * fl;
         gl += GK21_WG[j] * li;
     };
@@ -589,11 +613,12 @@ GL_HD double trap_lin_inl(const SetConst& s, double x0, double y0, int oi)
     const int n = kTrapN[oi];
     double rc, rs;
     trap_step(oi, rc, rs);
+    // (1 - r^2 > 0 at every node: the class guarantees a margin to the limb)
     auto node = [&](double c, double sn) {
         const double x = x0 + s.A * c;
         const double y = y0 + s.B * c + s.C * sn;
-        const double om = fmax(0.0, 1.0 - x * x - y * y);
-        const double w = sqrt_q(om);
+        const double om = 1.0 - x * x - y * y;
+        const double w = sqrt_qp(om);
         return (1.0 + om * rcp_q(1.0 + w)) * (s.AC + P1 * c + P2 * sn);
     };
     double acc = node(1.0, 0.0) + node(-1.0, 0.0);
