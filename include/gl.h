@@ -266,6 +266,23 @@ gl_status gl_lightcurve_batch_surrogate(gl_ctx *ctx, gl_mlp *mlp, const float *t
                                         const int32_t *n_ss, const double *t_exp, double *out,
                                         void *stream, int64_t *n_sub_out, int64_t *n_fallback_out);
 
+/* A trained surrogate on disk (host memory in and out; no device call, so
+ * these also run without a GPU): params float[n_params] in the packed layout
+ * of gl_mlp_get_weights, table float[n_bins] (the calibrated bound table of
+ * gl_lightcurve_batch_surrogate), zero_bins uint8[n_bins] (may be NULL: saved
+ * as all 0, or not returned).  n_params must equal gl_mlp_num_params() and
+ * n_bins gl_surrogate_num_bins(), else GL_ERR_SIZE.  The file holds a fixed
+ * header (magic, version, network widths, counts), the three arrays
+ * (little-endian) and a 64-bit FNV-1a hash of them.  Errors: GL_ERR_NULL for
+ * a NULL path, params or table; GL_ERR_SIZE when the counts or widths differ
+ * from this library's (or the file's); GL_ERR_STATE when the file cannot be
+ * opened, written or read, or its magic, version, length or hash is wrong
+ * (the outputs are then untouched). */
+gl_status gl_surrogate_save(const char *path, const float *params, int64_t n_params, const float *table,
+                            const uint8_t *zero_bins, int n_bins);
+gl_status gl_surrogate_load(const char *path, float *params, int64_t n_params, float *table,
+                            uint8_t *zero_bins, int n_bins);
+
 /* Library version, e.g. "0.1.0". */
 const char *gl_version(void);
 

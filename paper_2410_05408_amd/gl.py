@@ -396,7 +396,7 @@ def unpack_params(packed, d_in=GL_MLP_DIN, width=GL_MLP_WIDTH, depth=4):
 
 # ---------------------------------------------------------------- surrogate path
 EXPORTED = EXPORTED + ("gl_surrogate_samples", "gl_surrogate_num_bins", "gl_surrogate_bound",
-                       "gl_lightcurve_batch_surrogate")
+                       "gl_lightcurve_batch_surrogate", "gl_surrogate_save", "gl_surrogate_load")
 
 
 def _sur_lib():
@@ -412,12 +412,45 @@ def _sur_lib():
         L.gl_lightcurve_batch_surrogate.argtypes = [vp, vp, vp, vp, d, d, vp, i64, vp, vp, i64, vp, vp,
                                                     vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.gl_lightcurve_batch_surrogate.restype = i
+        fp, u8p = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint8)
+        L.gl_surrogate_save.argtypes = [ctypes.c_char_p, fp, i64, fp, u8p, i]
+        L.gl_surrogate_save.restype = i
+        L.gl_surrogate_load.argtypes = [ctypes.c_char_p, fp, i64, fp, u8p, i]
+        L.gl_surrogate_load.restype = i
         L._sur_typed = True
     return L
 
 
 def gl_surrogate_num_bins() -> int:
     return _sur_lib().gl_surrogate_num_bins()
+
+
+def gl_surrogate_save(path: str, params: np.ndarray, table: np.ndarray, zero_bins=None) -> None:
+    """Writes a trained surrogate (host arrays: packed FP32 parameters, FP32
+    bound table, optional uint8 per-bin predictor choice)."""
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    t = np.ascontiguousarray(table, dtype=np.float32)
+    z = None if zero_bins is None else np.ascontiguousarray(zero_bins, dtype=np.uint8)
+    L = _sur_lib()
+    zp = z.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if z is not None else None
+    if z is not None and z.size != t.size:
+        raise GLError(GL_ERR_SIZE, "zero_bins and table differ in length")
+    st = L.gl_surrogate_save(os.fsencode(path), _fptr(p), p.size, _fptr(t), zp, t.size)
+    if st != GL_OK:
+        raise GLError(st, f"gl_surrogate_save({path})")
+
+
+def gl_surrogate_load(path: str):
+    """Reads a surrogate file: (params float32, table float32, zero_bins uint8)."""
+    L = _sur_lib()
+    p = np.empty(gl_mlp_num_params(), np.float32)
+    t = np.empty(gl_surrogate_num_bins(), np.float32)
+    z = np.empty(t.size, np.uint8)
+    st = L.gl_surrogate_load(os.fsencode(path), _fptr(p), p.size, _fptr(t),
+                             z.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), t.size)
+    if st != GL_OK:
+        raise GLError(st, f"gl_surrogate_load({path})")
+    return p, t, z
 
 
 def gl_surrogate_samples(ctx, params, times, feat, target, f_obl=None, f_sph=None, scale=None,

@@ -123,6 +123,24 @@ class Surrogate:
         torch.cuda.synchronize()
         return self.table
 
+    def save(self, path: str) -> None:
+        """Writes the network, the calibrated bound table and the per-bin
+        predictor choice (gl_surrogate_save)."""
+        zb = None if self.zero_bins is None else self.zero_bins.cpu().numpy()
+        gl.gl_surrogate_save(path, self.net.get_weights(), self.table.cpu().numpy(), zb)
+
+    @classmethod
+    def load(cls, ctx, path: str, device: int = 0, max_batch: int = 8192) -> "Surrogate":
+        """A surrogate read back from gl_surrogate_save's file, ready for
+        lightcurve() (no training or calibration needed)."""
+        import torch
+        w, table, zb = gl.gl_surrogate_load(path)
+        sur = cls(ctx, device=device, max_batch=max_batch)
+        sur.net.set_weights(w)
+        sur.table = torch.from_numpy(table).to("cuda")
+        sur.zero_bins = torch.from_numpy(zb).to("cuda")
+        return sur
+
     def lightcurve(self, d, out, tol=1e-6, safety=4.0, stream=None):
         """Gated light curves for a device workload dict (``gl.to_device``);
         returns (n_sub, n_fallback)."""

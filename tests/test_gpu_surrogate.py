@@ -4,7 +4,8 @@
   (oblate ellipse and the equal-area sphere);
 - the gated light curves stay within 1 ppm of the exact kernel on every point;
 - the trained network lets the gate accept more sub-samples than the same
-  gate around a zero-residual predictor (what the network gains).
+  gate around a zero-residual predictor (what the network gains);
+- a surrogate written to a file and read back gives the same light curves.
 """
 import math
 import sys
@@ -50,7 +51,7 @@ def test_targets_match_oracle(gpu_lib, ctx, oracle):
     assert max(errs_o) <= 1e-9 and max(errs_s) <= 1e-9
 
 
-def test_gated_light_curves_within_1ppm_and_network_gains(gpu_lib, ctx):
+def test_gated_light_curves_within_1ppm_and_network_gains(gpu_lib, ctx, tmp_path):
     import torch
     from paper_2410_05408_amd import surrogate as S
     from paper_2410_05408_amd import workloads as W
@@ -81,5 +82,16 @@ def test_gated_light_curves_within_1ppm_and_network_gains(gpu_lib, ctx):
     assert n_sub == n_sub_z
     assert n_fb < n_sub
     assert n_fb < n_fb_z  # what the trained network gains over the method without it
+    # a saved and reloaded surrogate gives the same light curves bit for bit
+    say("case: surrogate saved and loaded back")
+    path = str(tmp_path / "walker.glsur")
+    sur.save(path)
+    again = S.Surrogate.load(ctx, path, max_batch=8192)
+    out_l = torch.empty_like(exact)
+    n_sub_l, n_fb_l = again.lightcurve(d, out_l, tol=1e-6)
+    torch.cuda.synchronize()
+    assert (n_sub_l, n_fb_l) == (n_sub, n_fb)
+    assert torch.equal(out_l, out)
+    again.close()
     sur.close()
     zero.close()
