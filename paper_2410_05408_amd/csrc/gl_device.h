@@ -718,9 +718,7 @@ struct TauArc {
     double cc, sc, h;
 };
 
-// split: -1 decide here (span > pi), 0 / 1 take the decision given (a second
-// pass over the same arc repeats the first pass's count exactly).
-GL_HD int arc_between(double ta, double tb, TauArc* out, int split = -1)
+GL_HD int arc_between(double ta, double tb, TauArc* out)
 {
     const double Na = sqrt_nn(1.0 + ta * ta), Nb = sqrt_nn(1.0 + tb * tb);
     const double sg = (tb > ta) ? 1.0 : -1.0;
@@ -728,7 +726,7 @@ GL_HD int arc_between(double ta, double tb, TauArc* out, int split = -1)
     const double h = sg * (tb - ta) / (Na * Nb + sg * (1.0 + ta * tb));
     const double inv = sg / (Na * Nb);
     const double cc = (1.0 - ta * tb) * inv, sc = (ta + tb) * inv;
-    if (split < 0 ? h <= 1.0 : split == 0) {
+    if (h <= 1.0) {
         out[0] = {cc, sc, h};
         out[1] = out[0];  // (both slots always written: they stay in registers)
         return 1;
@@ -1007,38 +1005,27 @@ GL_HD int hard_breaks(HardPrep& H, double* bp, int* kind)
 // Walks the boundary between consecutive break points: ellipse arcs on the
 // star go to arc(cc, sc, h, level) (as tau-rule arcs, split when longer than
 // pi, with the starting level of the arc rule); limb arcs are added to S in
-// closed form when `limbs` is set.  The decisions (which pieces are inside,
-// which arcs are split, each arc's starting level) are taken once and kept in
-// `plan` (4 bits per piece); a walk replaying a plan from an earlier walk
-// repeats them exactly.  Returns the number of ellipse arcs.
+// closed form when `limbs` is set.  Returns the number of ellipse arcs.
 template <class ArcFn, class CT>
 GL_HD int boundary_walk(const HardPrep& H, const Frame& F, const double* bp, const int* kind,
-                        int nb, Sums& S, bool limbs, ArcFn&& arc, CT& ct, unsigned& plan,
-                        bool replay = false)
+                        int nb, Sums& S, bool limbs, ArcFn&& arc, CT& ct)
 {
     int n_arcs = 0;
-    if (!replay) plan = 0u;
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
         if (i >= nb) break;
         const bool wrap = i + 1 == nb;  // the arc from the last break point back to the first
         const double ta = bp[i], tb = wrap ? bp[0] : bp[i + 1 < 7 ? i + 1 : 0];
         const int ka = kind[i], kb = wrap ? kind[0] : kind[i + 1 < 7 ? i + 1 : 0];
-        const unsigned bits = replay ? (plan >> (4 * i)) & 15u : 0u;
         bool inside;
-        if (replay) inside = bits & 1u;
-        else if (ka == 1 || kb == 1) inside = true;  // cluster points lie on the star
+        if (ka == 1 || kb == 1) inside = true;  // cluster points lie on the star
         else if (!wrap) inside = p4(H.q, 0.5 * (ta + tb)) < 0.0;
-        else inside = H.inf_inside;                    // the arc through t = inf
+        else inside = H.inf_inside;              // the arc through t = inf
         if (inside) {
             TauArc arcs[2];
-            const int na = arc_between(ta, tb, arcs, replay ? (int)((bits >> 1) & 1u) : -1);
-            const int l0 = replay ? (int)((bits >> 2) & 1u) : arc_start_level(arcs[0].h);
-            const int l1 = replay ? (int)((bits >> 3) & 1u) : (na == 2 ? arc_start_level(arcs[1].h) : 0);
-            if (!replay)
-                plan |= (1u | (na == 2 ? 2u : 0u) | ((unsigned)l0 << 2) | ((unsigned)l1 << 3)) << (4 * i);
-            arc(arcs[0].cc, arcs[0].sc, arcs[0].h, l0);
-            if (na == 2) arc(arcs[1].cc, arcs[1].sc, arcs[1].h, l1);
+            const int na = arc_between(ta, tb, arcs);
+            arc(arcs[0].cc, arcs[0].sc, arcs[0].h, arc_start_level(arcs[0].h));
+            if (na == 2) arc(arcs[1].cc, arcs[1].sc, arcs[1].h, arc_start_level(arcs[1].h));
             n_arcs += na;
         } else if (limbs) {
             double xa, ya, xb, yb;
@@ -1081,9 +1068,8 @@ GL_HD double occulted_hard(const SetConst& s, double x0, double y0, int* cls_out
     Frame F;
     make_frame(s, x0, y0, H.c0a, H.s0a, F);
     Sums S = {0.0, 0.0, 0.0};
-    unsigned plan;
     boundary_walk(H, F, bp, kind, nb, S, true,
-                  [&](double cc, double sc, double h, int lev) { arc_gk(F, cc, sc, h, S, ct, lev); }, ct, plan);
+                  [&](double cc, double sc, double h, int lev) { arc_gk(F, cc, sc, h, S, ct, lev); }, ct);
     return sums_delta(s, S);
 }
 

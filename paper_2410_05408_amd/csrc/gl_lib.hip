@@ -706,19 +706,22 @@ k_trap(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
     if (CENSUS) census_add(ctr, 4, nodes);
 }
 
-// Hard entries: intersection quartic and break points per thread; the limb
-// arcs are summed in closed form, the ellipse arcs are appended to the arc
-// list (one reservation per wavefront, positions from a wavefront scan).
-// Samples off the disk get their flux here.  Whole ellipses near the limb
-// with no cluster point, and samples whose arcs do not fit the arc list, go
-// to the in-place list (pushed to the shard of their own hard slot, so that
-// list never overflows and this kernel makes no calls).
+// Hard entries: intersection quartic and break points per thread; one walk
+// of the boundary sums the limb arcs in closed form and keeps up to kHardArcs
+// ellipse arcs in LDS, which are then appended to the arc list (one
+// reservation per wavefront, positions from a wavefront scan).  Samples off
+// the disk get their flux here.  Whole ellipses near the limb with no cluster
+// point, samples with more arcs than that and samples whose arcs do not fit
+// the arc list go to the in-place list (pushed to the shard of their own hard
+// slot, so that list never overflows and this kernel makes no calls).
 constexpr int kInPlace = 1 << kSubBits;  // in-place entry flag: arcs integrated per lane
+constexpr int kHardArcs = 4;             // ellipse arcs a hard sample keeps for the arc list
 
 template <bool CENSUS>
 __global__ void __launch_bounds__(64) GL_WAVES(GL_WAVES_HARD)
 k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
 {
+    __shared__ double lds_arc[kHardArcs][3][64];  // kept arcs (cc, sc, h) per lane
     const int lane = threadIdx.x;
     const unsigned long long lt = lanemask_lt(lane);
     const int shard = (int)(blockIdx.x % kShards);
@@ -737,10 +740,10 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
         const bool valid = g < m.total && e.set >= 0;
         if (g < m.total && !valid) P.hrec[slot].n_arcs = 0;  // slot of an overflowing chunk
         gl::HardPrep H;
-        double bp[7];
-        int kind[7];
-        int nb = 0, na = 0, na1 = 0;  // arcs, of which starting at level 1
-        unsigned plan = 0u;
+        gl::Frame F{};
+        gl::Sums Sm{0.0, 0.0, 0.0};
+        int na = 0, na1 = 0;  // ellipse arcs walked, of which starting at level 1
+        unsigned lev1 = 0u;   // bit k: kept arc k starts at level 1
         bool open = false, to_list = false;
         int flag = 0;
         if (valid) {
@@ -756,11 +759,36 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
                 c_part += cls == gl::CLS_PARTIAL;
             }
             if (open) {
-                nb = gl::hard_breaks(H, bp, kind);
-                gl::Frame F0{};
-                gl::Sums none{0.0, 0.0, 0.0};
-                na = gl::boundary_walk(H, F0, bp, kind, nb, none, false,
-                                       [&](double, double, double, int lev) { na1 += lev; }, nc, plan);
+                // one walk: limb arcs summed in closed form, ellipse arcs kept
+                // in this lane's LDS slots until their positions are reserved
+                double bp[7];
+                int kind[7];
+                const int nb = gl::hard_breaks(H, bp, kind);
+                gl::make_frame(S, e.x0, e.y0, H.c0a, H.s0a, F);
+                auto keep = [&](double cc, double scv, double h, int lev) {
+                    if (na < kHardArcs) {
+                        lds_arc[na][0][lane] = cc;
+                        lds_arc[na][1][lane] = scv;
+                        lds_arc[na][2][lane] = h;
+                        lev1 |= (unsigned)lev << na;
+                    }
+                    na1 += lev;
+                    ++na;
+                };
+                if (CENSUS) gl::boundary_walk(H, F, bp, kind, nb, Sm, true, keep, ct);
+                else gl::boundary_walk(H, F, bp, kind, nb, Sm, true, keep, nc);
+                if (na > kHardArcs) {
+                    // more arcs than slots (rare): the sample is integrated in place later
+                    to_list = true;
+                    flag = kInPlace;
+                    open = false;
+                    na = na1 = 0;
+                    P.hrec[slot].n_arcs = 0;
+                } else if (na == 0) {  // limb arcs only
+                    P.fsub[e.sub] = 1.0 - gl::sums_delta(S, Sm);
+                    P.hrec[slot].n_arcs = 0;
+                    open = false;
+                }
             } else {
                 if (!to_list) P.fsub[e.sub] = 1.0;
                 P.hrec[slot].n_arcs = 0;
@@ -782,43 +810,30 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
         // index lists: reserved only when the arcs are stored
         const int64_t l0p = over ? 0 : reserve(ctr, L_LVL0, shard, (unsigned long long)(wtotal - wtot1));
         const int64_t l1p = over ? 0 : reserve(ctr, L_LVL0 + 1, shard, (unsigned long long)wtot1);
-        if (open) {
-            const gl::SetConst& S = sc[e.set];
-            gl::Frame F;
-            gl::make_frame(S, e.x0, e.y0, H.c0a, H.s0a, F);
-            gl::Sums Sm{0.0, 0.0, 0.0};
-            const int64_t first = ap + incl - na;
-            if (over && na > 0) {
+        if (open) {  // 1 <= na <= kHardArcs
+            if (over) {
                 // arcs do not fit: the whole sample is integrated in place later
                 // (no index-list entry refers to this lane's reserved arc slots)
                 P.hrec[slot].n_arcs = 0;
                 to_list = true;
                 flag = kInPlace;
             } else {
-                // second walk: the first walk's decisions, so exactly na arcs
-                // land in this lane's reserved range; their indices go to the
-                // index list of their starting level (same shard: never full)
-                int64_t k = first;
+                // the kept arcs go to this lane's reserved range, their indices
+                // to the index list of their starting level (same shard: never full)
+                const int64_t first = ap + incl - na;
                 int64_t k0 = l0p + incl0 - (na - na1), k1 = l1p + incl1 - na1;
-                auto put = [&](double cc, double scv, double h, int lev) {
-                    if (k < first + na) {
-                        al[k] = ArcRec{cc, scv, h};
-                        const ArcRef r{(int)((int64_t)shard * acap + k), (int)slot};
-                        if (lev == 0) P.lvl[0][(int64_t)shard * lcap + (k0++)] = r;
-                        else P.lvl[1][(int64_t)shard * lcap + (k1++)] = r;
+#pragma unroll
+                for (int k = 0; k < kHardArcs; ++k) {
+                    if (k < na) {
+                        al[first + k] = ArcRec{lds_arc[k][0][lane], lds_arc[k][1][lane], lds_arc[k][2][lane]};
+                        const ArcRef r{(int)((int64_t)shard * acap + first + k), (int)slot};
+                        if ((lev1 >> k) & 1u) P.lvl[1][(int64_t)shard * lcap + (k1++)] = r;
+                        else P.lvl[0][(int64_t)shard * lcap + (k0++)] = r;
                     }
-                    ++k;
-                };
-                if (CENSUS) gl::boundary_walk(H, F, bp, kind, nb, Sm, true, put, ct, plan, true);
-                else gl::boundary_walk(H, F, bp, kind, nb, Sm, true, put, nc, plan, true);
-                if (na == 0) {  // limb arcs only
-                    P.fsub[e.sub] = 1.0 - gl::sums_delta(S, Sm);
-                    P.hrec[slot].n_arcs = 0;
-                } else {
-                    P.hrec[slot] = HardRec{Sm, e.set, e.sub, (int)((int64_t)shard * acap + first), na};
-                    P.hfr[slot] = F;
-                    if (CENSUS) c_arcs += na;
                 }
+                P.hrec[slot] = HardRec{Sm, e.set, e.sub, (int)((int64_t)shard * acap + first), na};
+                P.hfr[slot] = F;
+                if (CENSUS) c_arcs += na;
             }
         }
         // in-place list, in the shard of the entry's own hard slot
@@ -885,15 +900,14 @@ k_nested(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P
         gl::Frame F;
         gl::make_frame(S, e.x0, e.y0, H.c0a, H.s0a, F);
         gl::Sums Sm{0.0, 0.0, 0.0};
-        unsigned plan;
         if (CENSUS)
             gl::boundary_walk(H, F, bp, kind, nb, Sm, true,
                               [&](double cc, double scv, double h, int lev) { gl::arc_gk(F, cc, scv, h, Sm, ct, lev); },
-                              ct, plan);
+                              ct);
         else
             gl::boundary_walk(H, F, bp, kind, nb, Sm, true,
                               [&](double cc, double scv, double h, int lev) { gl::arc_gk(F, cc, scv, h, Sm, nc, lev); },
-                              nc, plan);
+                              nc);
         P.fsub[sub] = 1.0 - gl::sums_delta(S, Sm);
     }
     if (CENSUS) {
