@@ -31,6 +31,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "gl_tables.h"
 
@@ -54,6 +55,8 @@ struct SetConst {
     double d;              // orbital distance: y0 = d sin(alpha)
     double w_orb;          // 2 pi / P
     double P, t0;
+    double inv_P;          // 1 / P
+    double zA, z2A_inv, zC0;  // k^2 - kq^2, 1 / (2 (k^2 - kq^2)) (0 when tiny), kq^2 - 1 (kq: minor semi-axis)
     double half_win;       // instantaneous overlap needs |t - t0 - nP| < half_win
     double c0, c1, c2;     // I = c0 + c1 mu + c2 r^2
     double inv_phi;        // 1 / Phi
@@ -123,18 +126,18 @@ GL_HD double rcp_q(double x)
 #endif
 }
 
+// (x >= 0: the estimate is taken at max(x, 1e-300), so that x = 0 gives
+// g = 0 and a result of exactly 0 with no select; below 1e-300 the result is
+// merely tiny.)
 GL_HD double sqrt_q(double x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    const bool pos = x > 1e-300;
-    const double xc = pos ? x : 1.0;
-    const double y = __builtin_amdgcn_rsq(xc);
-    double g = xc * y, h = 0.5 * y;
+    const double y = __builtin_amdgcn_rsq(fmax(x, 1e-300));
+    double g = x * y, h = 0.5 * y;
     const double e = fma(-g, h, 0.5);
     g = fma(g, e, g);
     h = fma(h, e, h);
-    const double r = fma(fma(-g, g, xc), h, g);
-    return pos ? r : 0.0;
+    return fma(fma(-g, g, x), h, g);
 #else
     return x > 0.0 ? sqrt(x) : 0.0;
 #endif
@@ -262,10 +265,17 @@ GL_HD bool make_set_const(const double* p, double t_exp, int n_ss, SetConst& s)
     s.K3 = 0.5 * (s.A * s.A + s.B * s.B - s.C * s.C);
     s.K4 = s.B * s.C;
     s.k = k;
+    {
+        const double kq = s.AC / k;  // minor semi-axis of the projected ellipse
+        s.zA = (k - kq) * (k + kq);
+        s.z2A_inv = s.zA > 1e-14 * k * k ? 1.0 / (2.0 * s.zA) : 0.0;
+        s.zC0 = kq * kq - 1.0;
+    }
     // orbit (eq. coord-map): sin(beta) = b/d, x0 = d cos(alpha) sin(beta)
     s.xb = d * (b / d);
     s.d = d;
     s.P = P;
+    s.inv_P = 1.0 / P;
     s.t0 = t0;
     s.w_orb = kTwoPi / P;
     // overlap needs rho^2 = b^2 cos^2(alpha) + d^2 sin^2(alpha) < (1 + k)^2 with
@@ -290,8 +300,10 @@ GL_HD bool make_set_const(const double* p, double t_exp, int n_ss, SetConst& s)
 // Time offset from the nearest mid-transit, in (-P/2, P/2].
 GL_HD double phase_time(const SetConst& s, double t)
 {
+    // (the transit index from dt / P or dt * (1/P) can differ only where dt
+    // is half a period from a transit, with the planet behind the star)
     const double dt = t - s.t0;
-    return dt - s.P * rint(dt / s.P);
+    return dt - s.P * rint(dt * s.inv_P);
 }
 
 // ---------------------------------------------------------------- work census
@@ -479,6 +491,15 @@ GL_HD int arc_start_level(double h) { return h > kArcStartSplit ? 1 : 0; }
 // One piece tau in [mid - half, mid + half] of the arc psi = psi_c + 2 atan(tau):
 // clustered Gauss-Kronrod 10/21 rule.  Adds the Kronrod sums to K and returns
 // the Gauss-Kronrod difference of the integrals of 1 and mu.
+// The Gauss-10 nodes of the 21-point rule are the odd ones.
+constexpr bool gk21_gauss_odd()
+{
+    for (int j = 0; j < 21; ++j)
+        if ((GK21_WG[j] != 0.0) != (j % 2 == 1)) return false;
+    return true;
+}
+static_assert(gk21_gauss_odd(), "Gauss weights expected at odd nodes only");
+
 template <bool UNROLL = false>
 GL_HD double gk_piece(const Frame& F, double cc, double sc, double mid, double half, Sums& K)
 {
@@ -492,7 +513,7 @@ GL_HD double gk_piece(const Frame& F, double cc, double sc, double mid, double h
     const double dyu = 0.5 * ayt, dyt = -2.0 * ayu;
     const double fu = F.P1 * cc + F.P2 * sc, ft = 2.0 * (F.P2 * cc - F.P1 * sc);
     double kf = 0.0, kl = 0.0, kq = 0.0, gf = 0.0, gl = 0.0;
-    auto node = [&](int j) {
+    auto node = [&](int j, auto gauss) {
         const double tau = mid + half * GK21_M[j];
         const double d = fma(tau, tau, 1.0);
         const double inv = rcp_q(d);
@@ -511,17 +532,24 @@ GL_HD double gk_piece(const Frame& F, double cc, double sc, double mid, double h
         kf += GK21_WK[j] * fl;
         kl += GK21_WK[j] * li;
         kq += GK21_WK[j] * (inv2 * tq);
-        gf += GK21_WG[j] * fl;
-        gl += GK21_WG[j] * li;
+        if constexpr (decltype(gauss)::value) {
+            gf += GK21_WG[j] * fl;
+            gl += GK21_WG[j] * li;
+        }
     };
     // same nodes in the same order either way; unrolled, the rule's constants
-    // become immediates (no table loads inside the loop)
+    // become immediates (no table loads inside the loop) and the Kronrod-only
+    // nodes (even j, zero Gauss weight) skip the Gauss sums
     if (UNROLL) {
 #pragma unroll
-        for (int j = 0; j < 21; ++j) node(j);
+        for (int jj = 0; jj < 10; ++jj) {
+            node(2 * jj, std::false_type{});
+            node(2 * jj + 1, std::true_type{});
+        }
+        node(20, std::false_type{});
     } else {
 #pragma unroll 1
-        for (int j = 0; j < 21; ++j) node(j);
+        for (int j = 0; j < 21; ++j) node(j, std::true_type{});
     }
     // dpsi factor 2, f_flat = flat/2, f_lin = (2/3) G flat/2, f_quad = quad/2
     K.flat += half * kf;
@@ -759,15 +787,15 @@ enum SampleClass : int { CLS_OUT = 0, CLS_FULL = 1, CLS_PARTIAL = 2 };
 // p = u + i v where |u| <= rho + k cosh b and |v| >= kq sinh b (kq: minor
 // semi-axis); a zero needs |u|^2 - |v|^2 = 1, hence
 //   k^2 (1 - q^2) c^2 + 2 rho k c + rho^2 + (kq)^2 - 1 >= 0,  c = cosh b.
-// Returns the smallest such c (>= 1), or 1 when no bound applies.
-GL_HD double zero_cosh_bound(double rho2, double rho, double k, double kq)
+// Returns the smallest such c (>= 1), or 1 when no bound applies.  The
+// coefficients that depend on the set only come precomputed (zA, z2A_inv, zC0).
+GL_HD double zero_cosh_bound(const SetConst& s, double rho2, double rho)
 {
-    const double A = (k - kq) * (k + kq);
-    const double B = 2.0 * rho * k;
-    const double C = rho2 + kq * kq - 1.0;
+    const double B = 2.0 * rho * s.k;
+    const double C = rho2 + s.zC0;
     if (C >= 0.0) return 1.0;
     double c;
-    if (A > 1e-14 * k * k) c = (-B + sqrt_nn(B * B - 4.0 * A * C)) * rcp(2.0 * A);
+    if (s.z2A_inv > 0.0) c = (-B + sqrt_nn(B * B - 4.0 * s.zA * C)) * s.z2A_inv;
     else c = B > 0.0 ? -C * rcp(B) : 1e300;
     return fmax(c, 1.0);
 }
@@ -785,7 +813,7 @@ GL_HD int easy_class(const SetConst& s, double x0, double y0)
     const double kp = 1.0 + s.k;
     if (rho2 >= kp * kp) return kOffDisk;
     const double rho = sqrt_nn(rho2);
-    const double cosh_bound = zero_cosh_bound(rho2, rho, s.k, s.AC * rcp(s.k));
+    const double cosh_bound = zero_cosh_bound(s, rho2, rho);
     const int oi = trap_order_cosh(cosh_bound);
     return oi < 0 ? kHard : oi;
 }
