@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (256 CU x 128 FLOP/clk x 2.4 GHz)
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 
 
 def log(msg):
@@ -128,8 +129,11 @@ def measured_traffic(kernel):
     return None if k is None else k["hbm_bytes_per_launch"]
 
 
-STAGE_KERNELS = {"classify": "k_window + k_classify", "trapezoid": "k_trap", "hard": "k_hard",
-                 "nested": "k_nested", "arcs": "k_gk (levels 0-4)"}
+STAGE_KERNELS = {"window": "k_window_grid", "classify": "k_classify", "trapezoid": "k_trap",
+                 "hard": "k_hard", "nested": "k_nested", "arcs": "k_gk<0>, k_gk<1>, k_gk_tail",
+                 "combine": "k_combine + k_average"}
+# stages whose work is FP64 arithmetic (the others move data)
+FLOP_STAGES = ("classify", "trapezoid", "hard", "nested", "arcs")
 
 
 def stage_flop_split(census, per):
@@ -137,8 +141,8 @@ def stage_flop_split(census, per):
     counts; every census item belongs to exactly one stage)."""
     f = {k: census[k] * per[k] for k in census}
     return {
-        "classify": f["sub_in_window"] + f["whole_on_star"] + f["off_star_in_window"],
-        "trapezoid": f["trapezoid_nodes"],
+        "classify": f["sub_in_window"] + f["off_star_in_window"],
+        "trapezoid": f["trapezoid_nodes"] + f["whole_on_star"],
         "hard": f["intersecting"] + f["newton_steps"] + f["limb_arcs"] + f["ellipse_arcs"],
         "nested": f["nested_trapezoid_nodes"],
         "arcs": f["gk21_pieces"],
@@ -230,11 +234,26 @@ def main():
     per = gl.gl_flop_model()
     flops = sum(census[k] * per[k] for k in census)
     stage_flops = stage_flop_split(census, per)
-    # dominant kernel: the compute stage that takes longest
-    dom = max(("classify", "trapezoid", "hard", "nested", "arcs"), key=lambda k: stage_ms[k])
+    # dominant kernel: the FP64 stage that takes longest (each is one kernel,
+    # except the arc rule's level launches)
+    dom = max(FLOP_STAGES, key=lambda k: stage_ms[k])
     dom_ms = stage_ms[dom]
     achieved = stage_flops[dom] / (dom_ms * 1e-3) / 1e12
     kern_ms = sum(v for k, v in stage_ms.items() if k != "setup")
+
+    def alu_roof(stage):
+        a = stage_flops[stage] / (stage_ms[stage] * 1e-3) / 1e12
+        return {"bound": "alu", "kernel": STAGE_KERNELS[stage], "achieved": a,
+                "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": a / FP64_VECTOR_PEAK_TFLOPS,
+                "traffic": measured_traffic(STAGE_KERNELS[stage]),
+                "algorithmic_flop_per_launch": stage_flops[stage], "kernel_ms": stage_ms[stage]}
+
+    # the fill and store phase against HBM: every output out of the transit
+    # window is written once (8 B) by the window kernel, which also reads the
+    # shared time grid once
+    n_in_window_out = census["sub_in_window"] // int(w.n_ss[0])
+    fill_bytes = 8 * (w.n_out - n_in_window_out) + 8 * int(w.times.size)
+    fill_gbs = fill_bytes / (stage_ms["window"] * 1e-3) / 1e9
 
     got = out.cpu().numpy().reshape(w.n_sets, -1)
     in_transit = int(np.sum(got < 1.0))
@@ -256,13 +275,15 @@ def main():
         "config": {"workload": "walker_batch", "path": "exact", "n_sets": w.n_sets,
                    "n_times": int(w.times.size), "n_ss": int(w.n_ss[0]),
                    "cadence_min": 29.4, "seed": 2},
-        "roofline": {"bound": "alu", "kernel": STAGE_KERNELS[dom], "achieved": achieved,
-                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": measured_traffic(STAGE_KERNELS[dom]),
-                     "algorithmic_flop_per_launch": stage_flops[dom], "kernel_ms": dom_ms,
-                     "whole_pipeline": {"algorithmic_flop": flops, "compute_ms": kern_ms,
-                                        "achieved": flops / (kern_ms * 1e-3) / 1e12}},
+        "roofline": dict(alu_roof(dom), whole_pipeline={
+            "algorithmic_flop": flops, "compute_ms": kern_ms,
+            "achieved": flops / (kern_ms * 1e-3) / 1e12}),
+        "roofline_stages": {
+            **{k: alu_roof(k) for k in FLOP_STAGES if k != dom},
+            "window": {"bound": "hbm", "kernel": STAGE_KERNELS["window"], "achieved": fill_gbs,
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fill_gbs / HBM_PEAK_GBS,
+                       "traffic": measured_traffic(STAGE_KERNELS["window"]),
+                       "algorithmic_bytes_per_launch": fill_bytes, "kernel_ms": stage_ms["window"]}},
         "stage_ms": stage_ms,
         "sub_samples_per_s": w.n_sub / (ms_per_step * 1e-3),
         "in_transit_points_per_s": in_transit / (ms_per_step * 1e-3),

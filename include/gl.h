@@ -135,13 +135,14 @@ gl_status gl_ctx_set_capacity(gl_ctx *ctx, int64_t sub_samples, int64_t hard_sam
 gl_status gl_ctx_set_graph(gl_ctx *ctx, int on);
 
 /* Stages of one batch, in launch order (timed separately):
- *  0 set-up (parameter preparation, chunk scan), 1 window test and
- *  classification, 2 whole-ellipse trapezoid, 3 hard samples (intersection
- *  quartic, break points, limb arcs), 4 nested trapezoid for whole ellipses
- *  near the limb, 5 ellipse arcs (Gauss-Kronrod levels 0..4, then the
- *  combination of each hard sample's sums), 6 supersample average, 7 fused kernel
- *  for chunks beyond the work-list capacities. */
-#define GL_NSTAGES 8
+ *  0 set-up (parameter preparation, chunk scan), 1 window test (fills the
+ *  outputs that cannot overlap the star), 2 classification, 3 whole-ellipse
+ *  trapezoid, 4 hard samples (intersection quartic, break points, limb arcs),
+ *  5 nested trapezoid for whole ellipses near the limb, 6 ellipse arcs
+ *  (Gauss-Kronrod levels 0..4), 7 combination of each hard sample's sums and
+ *  supersample averages, 8 fused kernel for chunks beyond the work-list
+ *  capacities. */
+#define GL_NSTAGES 9
 
 /* Instrumentation: with n_slots > 0, the next n_slots batches are launched
  * directly (no graph) with a HIP event recorded on their stream before the
@@ -149,7 +150,7 @@ gl_status gl_ctx_set_graph(gl_ctx *ctx, int on);
 gl_status gl_ctx_set_timing(gl_ctx *ctx, int n_slots);
 
 /* Waits for the recorded batches and returns the summed times (ms) of stages
- * 1..7 (compute) and 0..7 (pipeline) and how many batches were timed; frees
+ * 1..8 (compute) and 0..8 (pipeline) and how many batches were timed; frees
  * the slots for reuse.  Any output pointer may be NULL. */
 gl_status gl_ctx_get_timing(gl_ctx *ctx, double *compute_ms, double *pipeline_ms, int *n);
 

@@ -1582,6 +1582,7 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     GL_STAGE_DONE();
     const int64_t n_cu = ctx->n_cu;
     launch_window(ctx, b, st, 1);
+    GL_STAGE_DONE();
     const unsigned waves = (unsigned)std::max<int64_t>(4, n_cu * ctx->waves_per_cu);
     hipLaunchKernelGGL(k_classify<CENSUS>, dim3((unsigned)(n_cu * 24)), dim3(64), 0, st, b.times, shared, ctx->sc,
                        ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks, ctx->chunk_set,
@@ -1595,8 +1596,8 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     hipLaunchKernelGGL(k_nested<CENSUS>, dim3((unsigned)(n_cu * 4)), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
     GL_STAGE_DONE();
     launch_arcs<CENSUS>(ctx, st, GL_GK_WAVES_PER_CU > 0 ? (unsigned)(n_cu * GL_GK_WAVES_PER_CU) : waves);
-    hipLaunchKernelGGL(k_combine, dim3((unsigned)(n_cu * 8)), dim3(256), 0, st, ctx->sc, ctx->ctr, P);
     GL_STAGE_DONE();
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)(n_cu * 8)), dim3(256), 0, st, ctx->sc, ctx->ctr, P);
     hipLaunchKernelGGL(k_average, dim3((unsigned)(n_cu * 32)), dim3(64), 0, st, ctx->sc,
                        ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks, ctx->chunk_set,
                        ctx->chunk_fb, b.out);

@@ -29,8 +29,8 @@ EXPORTED = ("gl_ctx_create", "gl_ctx_destroy", "gl_lightcurve_batch", "gl_ctx_sy
 CENSUS_NAMES = ("sub_in_window", "whole_on_star", "intersecting", "off_star_in_window",
                 "trapezoid_nodes", "gk21_pieces", "newton_steps", "limb_arcs",
                 "nested_trapezoid_nodes", "ellipse_arcs")
-GL_NSTAGES = 8
-STAGE_NAMES = ("setup", "classify", "trapezoid", "hard", "nested", "arcs", "average", "fused")
+GL_NSTAGES = 9
+STAGE_NAMES = ("setup", "window", "classify", "trapezoid", "hard", "nested", "arcs", "combine", "fused")
 
 
 class GLError(RuntimeError):
