@@ -191,6 +191,11 @@ GL_HD void sincos_pi(double a, double& sn, double& cs)
     cs = (q == 0) ? c0 : (q == 1) ? -s0 : (q == 2) ? -c0 : s0;
 }
 
+// 1/31, 1/29, ..., 1/3, 1: the Taylor series of atan(u) / u in powers of -u^2.
+static constexpr double kAtanInvOdd[16] = {1.0 / 31, 1.0 / 29, 1.0 / 27, 1.0 / 25, 1.0 / 23, 1.0 / 21,
+                                           1.0 / 19, 1.0 / 17, 1.0 / 15, 1.0 / 13, 1.0 / 11, 1.0 / 9,
+                                           1.0 / 7,  1.0 / 5,  1.0 / 3,  1.0};
+
 // atan(z) for |z| <= 1: atan z = pi/6 + atan((z - 1/sqrt 3)/(1 + z/sqrt 3))
 // brings |z| below tan(pi/12); then the Taylor series to z^31.
 GL_HD double atan_unit(double z)
@@ -203,9 +208,12 @@ GL_HD double atan_unit(double z)
         base = 0.52359877559829887308;               // pi/6
     }
     const double u2 = u * u;
-    double p = 1.0 / 31.0;
-#pragma unroll
-    for (int n = 29; n >= 1; n -= 2) p = fma(p, -u2, 1.0 / n);
+    // coefficients read per term from a table in a loop that is not unrolled:
+    // unrolled, the compiler keeps the 15 doubles in registers across a
+    // caller's whole sample loop (and spills them)
+    double p = kAtanInvOdd[0];
+#pragma unroll 1
+    for (int i = 1; i < 16; ++i) p = fma(p, -u2, kAtanInvOdd[i]);
     const double r = base + u * p;
     return z < 0.0 ? -r : r;
 }
@@ -346,11 +354,14 @@ GL_HD double ddp4(const Poly4& q, double t)
 // bisection whenever a step leaves the bracket; stops when the step is at
 // rounding level or |f| is below the rounding noise of its own evaluation.
 template <int Deriv, class CT>
-GL_HD double bracket_root(const Poly4& q, double lo, double hi, double flo, double fhi, CT& ct)
+GL_HD double bracket_root(const Poly4& q, double lo, double hi, double flo, double fhi, CT& ct,
+                          double start = __builtin_nan(""))
 {
     const double a0 = fabs(q.a0), a1 = fabs(q.a1), a2 = fabs(q.a2), a3 = fabs(q.a3),
                  a4 = fabs(q.a4);
-    double x = lo - flo * (hi - lo) / (fhi - flo);
+    // first iterate: the given start when it lies inside the bracket, else the
+    // secant through the ends, else the midpoint
+    double x = (start > lo && start < hi) ? start : lo - flo * (hi - lo) / (fhi - flo);
     if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
     for (int it = 0; it < 100; ++it) {
         ct.iter();
@@ -425,13 +436,27 @@ GL_HD void solve_quartic_inl(const Poly4& q, QuarticRoots& out, CT& ct)
     // keeps the left end of its interval, which only splits a stretch where
     // q is monotone
     const double pt[5] = {-Bnd, out.c[0], out.c[1], out.c[2], Bnd};
+    double fq[5], dq[5];
+    // next to a critical point c, q(c + d) ~ q(c) + q''(c) d^2 / 2: a root there
+    // sits near |d| = sqrt(-2 q(c) / q''(c)), a better first iterate than the
+    // secant across the whole bracket (dq = 1e300 where the model does not apply)
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        fq[i] = p4(q, pt[i]);
+        dq[i] = 1e300;
+        if (i >= 1 && i <= 3 && out.cv[i - 1]) {
+            const double m = -2.0 * fq[i] * rcp(ddp4(q, pt[i]));
+            if (m > 0.0 && m < 1e300) dq[i] = sqrt_nn(m);
+        }
+    }
     out.n_roots = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const double lo = pt[i], hi = pt[i + 1];
-        const double flo = p4(q, lo), fhi = p4(q, hi);
+        const double flo = fq[i], fhi = fq[i + 1];
         out.rv[i] = (flo < 0.0) != (fhi < 0.0) && flo != 0.0 && fhi != 0.0;
-        out.r[i] = out.rv[i] ? bracket_root<0>(q, lo, hi, flo, fhi, ct) : 0.0;
+        const double start = dq[i] <= dq[i + 1] ? lo + dq[i] : hi - dq[i + 1];  // from the nearer model
+        out.r[i] = out.rv[i] ? bracket_root<0>(q, lo, hi, flo, fhi, ct, start) : 0.0;
         out.n_roots += out.rv[i] ? 1 : 0;
     }
 }
@@ -592,19 +617,19 @@ constexpr double kTrapW[kTrapOrders] = {
     kTwoPi / (3.0 * 8), kTwoPi / (3.0 * 12), kTwoPi / (3.0 * 16), kTwoPi / (3.0 * 20), kTwoPi / (3.0 * 24),
     kTwoPi / (3.0 * 32), kTwoPi / (3.0 * 40), kTwoPi / (3.0 * 48), kTwoPi / (3.0 * 64)};
 
+// cos and sin of the trapezoid steps 2 pi / n (a table read by index: as
+// literals the compiler keeps all of them in registers across a caller's loop).
+static constexpr double kTrapStepC[kTrapOrders] = {
+    0.70710678118654757, 0.86602540378443860, 0.92387953251128674, 0.95105651629515353, 0.96592582628906831,
+    0.98078528040323043, 0.98768834059513777, 0.99144486137381038, 0.99518472667219693};
+static constexpr double kTrapStepS[kTrapOrders] = {
+    0.70710678118654757, 0.5, 0.38268343236508978, 0.30901699437494740, 0.25881904510252074,
+    0.19509032201612825, 0.15643446504023087, 0.13052619222005157, 0.098017140329560604};
+
 GL_HD void trap_step(int i, double& c, double& s)
 {
-    switch (i) {
-    case 0: c = 0.70710678118654757; s = 0.70710678118654757; break;
-    case 1: c = 0.86602540378443860; s = 0.5; break;
-    case 2: c = 0.92387953251128674; s = 0.38268343236508978; break;
-    case 3: c = 0.95105651629515353; s = 0.30901699437494740; break;
-    case 4: c = 0.96592582628906831; s = 0.25881904510252074; break;
-    case 5: c = 0.98078528040323043; s = 0.19509032201612825; break;
-    case 6: c = 0.98768834059513777; s = 0.15643446504023087; break;
-    case 7: c = 0.99144486137381038; s = 0.13052619222005157; break;
-    default: c = 0.99518472667219693; s = 0.098017140329560604; break;
-    }
+    c = kTrapStepC[i];
+    s = kTrapStepS[i];
 }
 
 // Smallest trapezoid order n with n * d >= L, where d is the distance of the

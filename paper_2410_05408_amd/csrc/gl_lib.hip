@@ -277,6 +277,14 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
 #define GL_WAVES_GK 0
 #endif
 #define GL_WAVES(n) __attribute__((amdgpu_waves_per_eu((n) > 0 ? (n) : 1)))
+// Persistent grid of the trapezoid stage in wavefronts per CU (0: the plan's).
+#ifndef GL_TRAP_WAVES_PER_CU
+#define GL_TRAP_WAVES_PER_CU 0
+#endif
+// Persistent grid of the classification in wavefronts per CU.
+#ifndef GL_CLASSIFY_WAVES_PER_CU
+#define GL_CLASSIFY_WAVES_PER_CU 24
+#endif
 // Persistent grid of the arc-rule levels in wavefronts per CU (0: the plan's);
 // 20 = five per SIMD, what their register use allows (measured ~4 % faster
 // than the plan's 16 on the arc stage).
@@ -285,9 +293,10 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
 #endif
 
 // ---------------------------------------------------------------- work-list helpers
-__device__ __forceinline__ unsigned long long lanemask_lt(int lane)
+// Set bits of m below the calling lane (mbcnt: no lane mask is kept live).
+__device__ __forceinline__ int lanes_below(unsigned long long m)
 {
-    return (1ull << lane) - 1ull;
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
 // Adds a wave's census counts (one atomic per counter).
@@ -319,20 +328,20 @@ __device__ __forceinline__ int64_t list_count(const Counters* ctr, int l, int j)
 // Wavefront view of a sharded list: lanes 0..kShards-1 hold the shard counts
 // (clamped to the capacity) and their inclusive prefix sums.
 struct ShardMap {
-    int64_t cnt, incl, total;
+    int64_t incl;   // lane j < kShards: entries in shards 0..j (counts clamped to the capacity)
+    int64_t total;  // wavefront-uniform
 };
 
 __device__ __forceinline__ ShardMap shard_map(const Counters* ctr, int l, int64_t scap)
 {
     const int lane = threadIdx.x & 63;
     ShardMap m;
-    m.cnt = lane < kShards ? std::min<int64_t>(list_count(ctr, l, lane), scap) : 0;
-    m.incl = m.cnt;
+    m.incl = lane < kShards ? std::min<int64_t>(list_count(ctr, l, lane), scap) : 0;
     for (int d = 1; d < 64; d <<= 1) {
         const int64_t v = __shfl_up(m.incl, d);
         if (lane >= d) m.incl += v;
     }
-    m.total = __shfl(m.incl, kShards - 1);
+    m.total = uniform64(__shfl(m.incl, kShards - 1));
     return m;
 }
 
@@ -346,8 +355,8 @@ __device__ __forceinline__ int64_t shard_slot(const ShardMap& m, int64_t g, int6
         const int64_t v = __shfl(m.incl, j + step - 1);
         if (v <= g) j += step;
     }
-    const int64_t excl = __shfl(m.incl, j) - __shfl(m.cnt, j);
-    return (int64_t)j * scap + (g - excl);
+    const int64_t prev = __shfl(m.incl, j > 0 ? j - 1 : 0);  // entries before shard j
+    return (int64_t)j * scap + (g - (j > 0 ? prev : 0));
 }
 
 // Queues chunk c for the fused kernel once (the first caller wins).
@@ -541,7 +550,6 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
 {
     __shared__ double lds_t[kChunk];  // times of the chunk's in-window outputs, compacted
     const int lane = threadIdx.x;
-    const unsigned long long lt = lanemask_lt(lane);
     const int shard = (int)(blockIdx.x % kShards);
     const int64_t gcap = P.scap[L_GRP];
     const ShardMap m = shard_map(ctr, L_GRP, gcap);
@@ -556,7 +564,7 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
         const int64_t s = __builtin_amdgcn_readfirstlane(G.set);
         const gl::SetConst& S = sc[s];
         const int64_t tb = uniform64(G.tb);
-        if ((M >> lane) & 1ull) lds_t[__popcll(M & lt)] = times[tb + lane];
+        if ((M >> lane) & 1ull) lds_t[lanes_below(M)] = times[tb + lane];
         __syncthreads();
         const int nss = S.n_ss;
         const double inv_nss = 1.0 / (double)nss;
@@ -591,7 +599,7 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
             Entry* tl = P.trap + (int64_t)shard * tcap;
             if (tp + __popcll(mt) > tcap) {
                 // slots reserved below the capacity are marked empty
-                const int64_t slot = tp + __popcll(mt & lt);
+                const int64_t slot = tp + lanes_below(mt);
                 if (cls >= 0 && slot < tcap) tl[slot].set = -1;
                 fb = true;
             } else {
@@ -599,7 +607,7 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
 #pragma unroll
                 for (int k = 0; k < gl::kTrapOrders; ++k) {
                     const unsigned long long mk = __ballot(cls == k);
-                    rank += (k < cls) ? __popcll(mk) : (k == cls ? __popcll(mk & lt) : 0);
+                    rank += (k < cls) ? __popcll(mk) : (k == cls ? lanes_below(mk) : 0);
                 }
                 if (cls >= 0) tl[tp + rank] = Entry{x0, y0, (int)s, sub | (cls << kSubBits)};
             }
@@ -608,7 +616,7 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
             const int64_t hp = (int64_t)(both >> 32);
             const int64_t hcap = P.scap[L_HARD];
             Entry* hl = P.hard + (int64_t)shard * hcap;
-            const int64_t slot = hp + __popcll(mh & lt);
+            const int64_t slot = hp + lanes_below(mh);
             if (hp + __popcll(mh) > hcap) {
                 if (cls == gl::kHard && slot < hcap) hl[slot].set = -1;
                 fb = true;
@@ -632,9 +640,16 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
 // LDS (counting sort from wavefront ballots), then each thread integrates
 // kTrapRounds of them in sorted order, so the lanes of a wavefront mostly run
 // the same number of nodes.
-constexpr int kTrapThreads = 512;
+#ifndef GL_TRAP_THREADS
+#define GL_TRAP_THREADS 512
+#endif
+#ifndef GL_TRAP_ROUNDS
+#define GL_TRAP_ROUNDS 8
+#endif
+constexpr int kTrapThreads = GL_TRAP_THREADS;
 constexpr int kTrapWaves = kTrapThreads / 64;
-constexpr int kTrapRounds = 4;
+constexpr int kTrapRounds = GL_TRAP_ROUNDS;
+static_assert(kTrapRounds * kTrapWaves <= 64, "one wavefront scans the per-(round, wavefront) counts");
 constexpr int kTrapBuckets = gl::kTrapOrders + 1;  // the last bucket holds empty slots
 
 template <bool CENSUS>
@@ -644,7 +659,6 @@ k_trap(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
     __shared__ int lds_slot[kTrapRounds * kTrapThreads];
     __shared__ int lds_off[kTrapBuckets][kTrapRounds * kTrapWaves];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const unsigned long long lt = lanemask_lt(lane);
     const int64_t scap = P.scap[L_TRAP];
     const ShardMap m = shard_map(ctr, L_TRAP, scap);
     unsigned long long nodes = 0;
@@ -666,7 +680,7 @@ k_trap(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
 #pragma unroll
             for (int q = 0; q < kTrapBuckets; ++q) {
                 const unsigned long long mq = __ballot(k == q);
-                if (k == q) rank[r] = __popcll(mq & lt);
+                if (k == q) rank[r] = lanes_below(mq);
                 if (lane == 0) lds_off[q][r * kTrapWaves + wv] = __popcll(mq);
             }
         }
@@ -723,7 +737,6 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
 {
     __shared__ double lds_arc[kHardArcs][3][64];  // kept arcs (cc, sc, h) per lane
     const int lane = threadIdx.x;
-    const unsigned long long lt = lanemask_lt(lane);
     const int shard = (int)(blockIdx.x % kShards);
     const int64_t scap = P.scap[L_HARD], acap = P.scap[L_ARC], ncap = P.scap[L_NEST];
     const int64_t lcap = P.scap[L_LVL0];
@@ -844,7 +857,7 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
             const unsigned long long mj = __ballot(to_list && hs == j);
             const int64_t np = reserve(ctr, L_NEST, j, (unsigned long long)__popcll(mj));
             if (to_list && hs == j)
-                P.nest[(int64_t)j * ncap + np + __popcll(mj & lt)] = Entry{e.x0, e.y0, e.set, e.sub | flag};
+                P.nest[(int64_t)j * ncap + np + lanes_below(mj)] = Entry{e.x0, e.y0, e.set, e.sub | flag};
             pending &= ~mj;
         }
     }
@@ -925,13 +938,12 @@ k_nested(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P
 // tolerance (or at the last level); otherwise the arc enters level L + 1.
 template <int L, bool CENSUS>
 __global__ void __launch_bounds__(64) GL_WAVES(GL_WAVES_GK)
-k_gk(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
+k_gk(Counters* __restrict__ ctr, Pipe P)
 {
     constexpr int np = 1 << L;
     constexpr int lin = L_LVL0 + L;                                          // input list
     constexpr int lout = (L < gl::kArcMaxLevel) ? L_LVL0 + L + 1 : L_LVL0;  // output list
     const int lane = threadIdx.x;
-    const unsigned long long lt = lanemask_lt(lane);
     const int64_t scap = P.scap[lin];
     const ShardMap m = shard_map(ctr, lin, scap);
     const int64_t n = m.total << L;
@@ -975,7 +987,7 @@ k_gk(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
                 const unsigned long long mj = __ballot(want && hs == j);
                 const int64_t op = reserve(ctr, lout, j, (unsigned long long)__popcll(mj));
                 if (want && hs == j)
-                    P.lvl[L + 1 < kLevels ? L + 1 : L][(int64_t)j * P.scap[lout] + op + __popcll(mj & lt)] = r;
+                    P.lvl[L + 1 < kLevels ? L + 1 : L][(int64_t)j * P.scap[lout] + op + lanes_below(mj)] = r;
                 pending &= ~mj;
             }
         }
@@ -987,7 +999,7 @@ k_gk(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
 // from level 2 on in place.
 template <bool CENSUS>
 __global__ void __launch_bounds__(64)
-k_gk_tail(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
+k_gk_tail(Counters* __restrict__ ctr, Pipe P)
 {
     const int lane = threadIdx.x;
     const int64_t scap = P.scap[L_LVL0 + 2];
@@ -1064,7 +1076,7 @@ k_average(const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_b
         const int nss = __builtin_amdgcn_readfirstlane(W.nss);
         const int64_t i0 = uniform64(W.i0);
         if ((M >> lane) & 1ull) {
-            const int64_t o = __popcll(M & lanemask_lt(lane));
+            const int64_t o = lanes_below(M);
             const double* f = P.fsub + base + o * nss;
             double sum = 0.0;
             for (int j0 = 0; j0 < nss; j0 += 16) {
@@ -1549,11 +1561,10 @@ template <bool CENSUS>
 void launch_arcs(gl_ctx* ctx, hipStream_t st, unsigned grid)
 {
     const Pipe& P = ctx->pipe;
-    hipLaunchKernelGGL((k_gk<0, CENSUS>), dim3(grid), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
-    hipLaunchKernelGGL((k_gk<1, CENSUS>), dim3(grid), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
+    hipLaunchKernelGGL((k_gk<0, CENSUS>), dim3(grid), dim3(64), 0, st, ctx->ctr, P);
+    hipLaunchKernelGGL((k_gk<1, CENSUS>), dim3(grid), dim3(64), 0, st, ctx->ctr, P);
     // few arcs reach the deeper levels: one small launch finishes them per lane
-    hipLaunchKernelGGL((k_gk_tail<CENSUS>), dim3(std::max(1u, grid / 16)), dim3(64), 0, st, ctx->sc,
-                       ctx->ctr, P);
+    hipLaunchKernelGGL((k_gk_tail<CENSUS>), dim3(std::max(1u, grid / 16)), dim3(64), 0, st, ctx->ctr, P);
 }
 
 template <bool CENSUS>
@@ -1584,11 +1595,12 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     launch_window(ctx, b, st, 1);
     GL_STAGE_DONE();
     const unsigned waves = (unsigned)std::max<int64_t>(4, n_cu * ctx->waves_per_cu);
-    hipLaunchKernelGGL(k_classify<CENSUS>, dim3((unsigned)(n_cu * 24)), dim3(64), 0, st, b.times, shared, ctx->sc,
+    hipLaunchKernelGGL(k_classify<CENSUS>, dim3((unsigned)(n_cu * GL_CLASSIFY_WAVES_PER_CU)), dim3(64), 0, st, b.times, shared, ctx->sc,
                        ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks, ctx->chunk_set,
                        ctx->chunk_fb);
     GL_STAGE_DONE();
-    hipLaunchKernelGGL(k_trap<CENSUS>, dim3((waves + kTrapWaves - 1) / kTrapWaves), dim3(kTrapThreads), 0, st,
+    const unsigned twaves = GL_TRAP_WAVES_PER_CU > 0 ? (unsigned)(n_cu * GL_TRAP_WAVES_PER_CU) : waves;
+    hipLaunchKernelGGL(k_trap<CENSUS>, dim3((twaves + kTrapWaves - 1) / kTrapWaves), dim3(kTrapThreads), 0, st,
                        ctx->sc, ctx->ctr, P);
     GL_STAGE_DONE();
     hipLaunchKernelGGL(k_hard<CENSUS>, dim3(waves), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
