@@ -52,7 +52,11 @@ constexpr int kLevels = gl::kArcMaxLevel + 1;
 // counter on its own 128-byte line and its own region of the list: a
 // wavefront appends to shard (its workgroup index mod kShards), so the
 // atomics spread over many L2 lines instead of serialising on one.
-constexpr int kShards = 32;
+#ifndef GL_SHARDS
+#define GL_SHARDS 32
+#endif
+constexpr int kShards = GL_SHARDS;  // a power of two, at most 64 (one lane per shard)
+static_assert(kShards >= 2 && kShards <= 64 && (kShards & (kShards - 1)) == 0, "shard count");
 enum : int {
     L_SUB = 0,   // sub-sample flux slots (reserved per chunk)
     L_WC,        // chunks evaluated through the lists
