@@ -53,7 +53,7 @@ constexpr int kLevels = gl::kArcMaxLevel + 1;
 // wavefront appends to shard (its workgroup index mod kShards), so the
 // atomics spread over many L2 lines instead of serialising on one.
 #ifndef GL_SHARDS
-#define GL_SHARDS 32
+#define GL_SHARDS 64
 #endif
 constexpr int kShards = GL_SHARDS;  // a power of two, at most 64 (one lane per shard)
 static_assert(kShards >= 2 && kShards <= 64 && (kShards & (kShards - 1)) == 0, "shard count");
