@@ -112,10 +112,10 @@ GL_HD double sqrt_nn(double x)
 }
 
 // Integrand-grade forms for quadrature nodes, where a relative error of a few
-// 1e-15 per node is far below the rules' own error: the reciprocal after one
-// Newton step (the estimate's 2^-24 error squared, about 2e-15) and the
-// square root after the Goldschmidt step and one Newton correction (about one
-// ulp, without the final rounding correction).  Host builds use the IEEE forms.
+// 1e-15 per node is far below the rules' own error: the hardware estimates
+// (relative error below 2^-24, measured) after one Newton step each, which
+// squares that error: about 2e-15 for the reciprocal and 1.5 x 2^-48 = 4e-15
+// for the square root.  Host builds use the IEEE forms.
 GL_HD double rcp_q(double x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -128,16 +128,14 @@ GL_HD double rcp_q(double x)
 
 // (x >= 0: the estimate is taken at max(x, 1e-300), so that x = 0 gives
 // g = 0 and a result of exactly 0 with no select; below 1e-300 the result is
-// merely tiny.)
+// merely tiny.)  With y = (1 + eps)/sqrt(x): g = x y, e = 1/2 - g y/2 =
+// -eps - eps^2/2, and g (1 + e) = sqrt(x) (1 - 3 eps^2/2 - eps^3/2).
 GL_HD double sqrt_q(double x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
     const double y = __builtin_amdgcn_rsq(fmax(x, 1e-300));
-    double g = x * y, h = 0.5 * y;
-    const double e = fma(-g, h, 0.5);
-    g = fma(g, e, g);
-    h = fma(h, e, h);
-    return fma(fma(-g, g, x), h, g);
+    const double g = x * y;
+    return fma(g, fma(-g, 0.5 * y, 0.5), g);
 #else
     return x > 0.0 ? sqrt(x) : 0.0;
 #endif
@@ -149,11 +147,8 @@ GL_HD double sqrt_qp(double x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
     const double y = __builtin_amdgcn_rsq(x);
-    double g = x * y, h = 0.5 * y;
-    const double e = fma(-g, h, 0.5);
-    g = fma(g, e, g);
-    h = fma(h, e, h);
-    return fma(fma(-g, g, x), h, g);
+    const double g = x * y;
+    return fma(g, fma(-g, 0.5 * y, 0.5), g);
 #else
     return sqrt(x);
 #endif
