@@ -1053,34 +1053,79 @@ GL_HD int hard_breaks(HardPrep& H, double* bp, int* kind)
 // Walks the boundary between consecutive break points: ellipse arcs on the
 // star go to arc(cc, sc, h, level) (as tau-rule arcs, split when longer than
 // pi, with the starting level of the arc rule); limb arcs are added to S in
-// closed form when `limbs` is set.  Returns the number of ellipse arcs.
+// closed form when `limbs` is set.  Returns the number of ellipse arcs.  Most
+// samples have one piece of each kind: the first ellipse piece and the first
+// limb piece are taken out of the loop over break points, so that all lanes of
+// a wavefront run each kind once together instead of splitting between the two
+// kinds at every break point; further pieces (cluster points, four crossings)
+// follow in the loop.  Either kind is still taken in ascending order.
 template <class ArcFn, class CT>
 GL_HD int boundary_walk(const HardPrep& H, const Frame& F, const double* bp, const int* kind,
                         int nb, Sums& S, bool limbs, ArcFn&& arc, CT& ct)
 {
-    int n_arcs = 0;
+    unsigned more = 0u;  // bit i: piece i is not the first of its kind
+    bool seen_in = false, seen_out = false;
+    double ia = 0.0, ib = 0.0, oa = 0.0, ob = 0.0;  // first ellipse and first limb piece
+    unsigned on = 0u;                                // bit i: piece i lies on the star
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
         if (i >= nb) break;
-        const bool wrap = i + 1 == nb;  // the arc from the last break point back to the first
+        const bool wrap = i + 1 == nb;  // the piece from the last break point back to the first
         const double ta = bp[i], tb = wrap ? bp[0] : bp[i + 1 < 7 ? i + 1 : 0];
         const int ka = kind[i], kb = wrap ? kind[0] : kind[i + 1 < 7 ? i + 1 : 0];
         bool inside;
         if (ka == 1 || kb == 1) inside = true;  // cluster points lie on the star
         else if (!wrap) inside = p4(H.q, 0.5 * (ta + tb)) < 0.0;
-        else inside = H.inf_inside;              // the arc through t = inf
-        if (inside) {
-            TauArc arcs[2];
-            const int na = arc_between(ta, tb, arcs);
-            arc(arcs[0].cc, arcs[0].sc, arcs[0].h, arc_start_level(arcs[0].h));
-            if (na == 2) arc(arcs[1].cc, arcs[1].sc, arcs[1].h, arc_start_level(arcs[1].h));
-            n_arcs += na;
-        } else if (limbs) {
-            double xa, ya, xb, yb;
-            point_at(F, ta, xa, ya);
-            point_at(F, tb, xb, yb);
-            limb_sums(xa, ya, xb, yb, S);
-            ct.limb();
+        else inside = H.inf_inside;              // the piece through t = inf
+        const bool first = inside ? !seen_in : !seen_out;
+        if (inside && first) {
+            ia = ta;
+            ib = tb;
+        }
+        if (!inside && first) {
+            oa = ta;
+            ob = tb;
+        }
+        seen_in = seen_in || inside;
+        seen_out = seen_out || !inside;
+        on |= (inside ? 1u : 0u) << i;
+        more |= (first ? 0u : 1u) << i;
+    }
+    int n_arcs = 0;
+    auto ellipse_piece = [&](double ta, double tb) {
+        TauArc arcs[2];
+        const int na = arc_between(ta, tb, arcs);
+        arc(arcs[0].cc, arcs[0].sc, arcs[0].h, arc_start_level(arcs[0].h));
+        if (na == 2) arc(arcs[1].cc, arcs[1].sc, arcs[1].h, arc_start_level(arcs[1].h));
+        n_arcs += na;
+    };
+    auto limb_piece = [&](double ta, double tb) {
+        double xa, ya, xb, yb;
+        point_at(F, ta, xa, ya);
+        point_at(F, tb, xb, yb);
+        limb_sums(xa, ya, xb, yb, S);
+        ct.limb();
+    };
+    if (seen_in) ellipse_piece(ia, ib);
+    if (more & on) {
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+            if (((more & on) >> i) & 1u) {
+                const bool wrap = i + 1 == nb;
+                ellipse_piece(bp[i], wrap ? bp[0] : bp[i + 1 < 7 ? i + 1 : 0]);
+            }
+        }
+    }
+    if (limbs) {
+        if (seen_out) limb_piece(oa, ob);
+        if (more & ~on) {
+#pragma unroll
+            for (int i = 0; i < 7; ++i) {
+                if (((more & ~on) >> i) & 1u) {
+                    const bool wrap = i + 1 == nb;
+                    limb_piece(bp[i], wrap ? bp[0] : bp[i + 1 < 7 ? i + 1 : 0]);
+                }
+            }
         }
     }
     return n_arcs;
