@@ -541,10 +541,9 @@ k_window(const double* __restrict__ times, int64_t n_sets,
 
 // Classification: one wavefront per group of up to 64 sub-samples of one
 // chunk, classified by the ellipse centre: off the disk (flux 1 now), whole
-// ellipse provably well inside (trapezoid list, written sorted by rule order
-// within the group so that neighbouring lanes of k_trap run the same number
-// of nodes), everything else (hard list).  A group that does not fit the
-// lists sends its chunk to the fused kernel.
+// ellipse provably well inside (trapezoid list with its rule order, in lane
+// order: k_trap sorts its tiles by order), everything else (hard list).  A
+// group that does not fit the lists sends its chunk to the fused kernel.
 template <bool CENSUS>
 __global__ void __launch_bounds__(64)
 k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst* __restrict__ sc,
@@ -606,14 +605,9 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
                 const int64_t slot = tp + lanes_below(mt);
                 if (cls >= 0 && slot < tcap) tl[slot].set = -1;
                 fb = true;
-            } else {
-                int rank = 0;
-#pragma unroll
-                for (int k = 0; k < gl::kTrapOrders; ++k) {
-                    const unsigned long long mk = __ballot(cls == k);
-                    rank += (k < cls) ? __popcll(mk) : (k == cls ? lanes_below(mk) : 0);
-                }
-                if (cls >= 0) tl[tp + rank] = Entry{x0, y0, (int)s, sub | (cls << kSubBits)};
+            } else if (cls >= 0) {
+                // in lane order: the trapezoid stage sorts its tiles by rule order
+                tl[tp + lanes_below(mt)] = Entry{x0, y0, (int)s, sub | (cls << kSubBits)};
             }
         }
         if (mh) {
