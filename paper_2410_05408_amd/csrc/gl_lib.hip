@@ -635,7 +635,7 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
 // Whole ellipses well inside the disk, the trapezoid order chosen by
 // k_classify from the singularity bound.  A workgroup takes kTrapRounds x
 // kTrapThreads consecutive entries, sorts their list slots by rule order in
-// LDS (counting sort from wavefront ballots), then each thread integrates
+// LDS (counting sort, ranks from LDS atomics), then each thread integrates
 // kTrapRounds of them in sorted order, so the lanes of a wavefront mostly run
 // the same number of nodes.
 #ifndef GL_TRAP_THREADS
@@ -647,7 +647,6 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
 constexpr int kTrapThreads = GL_TRAP_THREADS;
 constexpr int kTrapWaves = kTrapThreads / 64;
 constexpr int kTrapRounds = GL_TRAP_ROUNDS;
-static_assert(kTrapRounds * kTrapWaves <= 64, "one wavefront scans the per-(round, wavefront) counts");
 constexpr int kTrapBuckets = gl::kTrapOrders + 1;  // the last bucket holds empty slots
 
 template <bool CENSUS>
@@ -655,13 +654,18 @@ __global__ void __launch_bounds__(kTrapThreads) GL_WAVES(GL_WAVES_TRAP)
 k_trap(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
 {
     __shared__ int lds_slot[kTrapRounds * kTrapThreads];
-    __shared__ int lds_off[kTrapBuckets][kTrapRounds * kTrapWaves];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    __shared__ int lds_cnt[kTrapBuckets];   // entries per rule order, then their first position
+    const int tid = threadIdx.x;
     const int64_t scap = P.scap[L_TRAP];
     const ShardMap m = shard_map(ctr, L_TRAP, scap);
     unsigned long long nodes = 0;
     constexpr int kBlock = kTrapRounds * kTrapThreads;
     for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < m.total; b0 += (int64_t)gridDim.x * kBlock) {
+        if (tid < kTrapBuckets) lds_cnt[tid] = 0;
+        __syncthreads();
+        // counting sort by rule order: an entry's place within its order comes
+        // from an LDS atomic (which thread integrates which entry may change
+        // from run to run; every entry's value does not)
         int bucket[kTrapRounds], rank[kTrapRounds], slot[kTrapRounds];
 #pragma unroll
         for (int r = 0; r < kTrapRounds; ++r) {
@@ -674,34 +678,21 @@ k_trap(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
             }
             bucket[r] = k;
             slot[r] = (int)sl;
-            rank[r] = 0;
-#pragma unroll
-            for (int q = 0; q < kTrapBuckets; ++q) {
-                const unsigned long long mq = __ballot(k == q);
-                if (k == q) rank[r] = lanes_below(mq);
-                if (lane == 0) lds_off[q][r * kTrapWaves + wv] = __popcll(mq);
-            }
+            rank[r] = atomicAdd(&lds_cnt[k], 1);
         }
         __syncthreads();
-        // exclusive offsets, bucket-major then (round, wavefront): one wavefront
-        if (wv == 0) {
+        if (tid == 0) {
             int run = 0;
             for (int q = 0; q < kTrapBuckets; ++q) {
-                const int v = lane < kTrapRounds * kTrapWaves ? lds_off[q][lane] : 0;
-                int incl = v;
-                for (int d = 1; d < 64; d <<= 1) {
-                    const int u = __shfl_up(incl, d);
-                    if (lane >= d) incl += u;
-                }
-                if (lane < kTrapRounds * kTrapWaves) lds_off[q][lane] = run + incl - v;
-                run += __shfl(incl, 63);
+                const int v = lds_cnt[q];
+                lds_cnt[q] = run;
+                run += v;
             }
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < kTrapRounds; ++r)
-            lds_slot[lds_off[bucket[r]][r * kTrapWaves + wv] + rank[r]] = slot[r];
-        const int n_valid = lds_off[gl::kTrapOrders][0];  // start of the empty bucket
+        for (int r = 0; r < kTrapRounds; ++r) lds_slot[lds_cnt[bucket[r]] + rank[r]] = slot[r];
+        const int n_valid = lds_cnt[gl::kTrapOrders];  // start of the empty bucket
         __syncthreads();
         for (int r = 0; r < kTrapRounds; ++r) {
             const int pos = r * kTrapThreads + tid;
