@@ -192,48 +192,55 @@ static constexpr double kAtanInvOdd[16] = {1.0 / 31, 1.0 / 29, 1.0 / 27, 1.0 / 2
                                            1.0 / 7,  1.0 / 5,  1.0 / 3,  1.0};
 
 // atan(z) for |z| <= 1: atan z = pi/6 + atan((z - 1/sqrt 3)/(1 + z/sqrt 3))
-// brings |z| below tan(pi/12); then the Taylor series to z^31.
+// brings |z| below tan(pi/12); then the Taylor series to z^31.  No branches:
+// the reduced argument is always computed and selected, so that the lanes of
+// a wavefront never run the series twice.
 GL_HD double atan_unit(double z)
 {
     const double az = fabs(z);
-    double base = 0.0, u = az;
-    if (az > 0.26794919243112270) {  // tan(pi/12)
-        const double is3 = 0.57735026918962576451;  // 1/sqrt(3)
-        u = (az - is3) / fma(az, is3, 1.0);
-        base = 0.52359877559829887308;               // pi/6
-    }
+    const bool red = az > 0.26794919243112270;      // tan(pi/12)
+    const double is3 = 0.57735026918962576451;       // 1/sqrt(3)
+    const double q = (az - is3) / fma(az, is3, 1.0);
+    const double u = red ? q : az;
+    const double base = red ? 0.52359877559829887308 : 0.0;  // pi/6
     const double u2 = u * u;
-    // coefficients read per term from a table in a loop that is not unrolled:
-    // unrolled, the compiler keeps the 15 doubles in registers across a
-    // caller's whole sample loop (and spills them)
+    // coefficients read from a table, five per pass of a loop that is not
+    // unrolled: unrolled, the compiler keeps the 15 doubles in registers
+    // across a caller's whole sample loop (and spills them)
     double p = kAtanInvOdd[0];
 #pragma unroll 1
-    for (int i = 1; i < 16; ++i) p = fma(p, -u2, kAtanInvOdd[i]);
+    for (int i = 1; i < 16; i += 5) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) p = fma(p, -u2, kAtanInvOdd[i + j]);
+    }
     const double r = base + u * p;
     return z < 0.0 ? -r : r;
 }
 
-// atan2(y, x) in (-pi, pi] from atan_unit.
+// atan2(y, x) in (-pi, pi] from atan_unit, one call per argument pair.
 GL_HD double atan2_d(double y, double x)
 {
     const double ay = fabs(y), ax = fabs(x);
-    double a;
-    if (ay <= ax) {
-        a = (ax > 0.0) ? atan_unit(ay / ax) : 0.0;
-    } else {
-        a = 1.57079632679489661923 - atan_unit(ax / ay);
-    }
+    const bool steep = ay > ax;
+    const double num = steep ? ax : ay, den = steep ? ay : ax;  // num <= den
+    const double t = atan_unit(num / (den > 0.0 ? den : 1.0));  // 0 when x = y = 0
+    double a = steep ? 1.57079632679489661923 - t : t;
     if (x < 0.0) a = 3.14159265358979323846 - a;
     return (y < 0.0) ? -a : a;
 }
+
+// a reduced to [-pi, pi] for sincos_pi (the angles of a parameter block may lie
+// outside it): a - 2 pi rint(a / 2 pi).
+GL_HD double wrap_pi(double a) { return fma(-kTwoPi, rint(a * (1.0 / kTwoPi)), a); }
 
 // The paper's rotation R(zeta=0, eta, xi) = Ry(eta) Rz(xi) entries r1..r9 and
 // eqs. dx, dy1, dy2 with polar semi-axis a = k(1-f) (body x') and b = c = k.
 GL_HD void projected_ellipse(double k, double f, double theta, double phi,
                              double& A, double& B, double& C)
 {
-    const double eta = 0.5 * kPi - theta;
-    const double ce = cos(eta), se = sin(eta), cx = cos(phi), sx = sin(phi);
+    double se, ce, sx, cx;
+    sincos_pi(wrap_pi(0.5 * kPi - theta), se, ce);  // eta = pi/2 - theta
+    sincos_pi(wrap_pi(phi), sx, cx);
     // R = Ry(eta) Rz(xi)
     const double r1 = ce * cx, r2 = -ce * sx, r3 = se;
     const double r4 = sx, r5 = cx, r6 = 0.0;
@@ -261,8 +268,12 @@ GL_HD bool make_set_const(const double* p, double t_exp, int n_ss, SetConst& s)
     s.t_exp = t_exp;
     if (!ok) return false;
     projected_ellipse(k, f, theta, phi, s.A, s.B, s.C);
-    s.sx = cos(phi);
-    s.sy = -sin(phi);
+    {
+        double sp, cp;
+        sincos_pi(wrap_pi(phi), sp, cp);
+        s.sx = cp;
+        s.sy = -sp;
+    }
     s.AC = s.A * s.C;
     s.M2 = s.A * s.A + s.B * s.B + s.C * s.C;
     s.K3 = 0.5 * (s.A * s.A + s.B * s.B - s.C * s.C);
