@@ -1,0 +1,86 @@
+"""CPU checks of the kernels' own per-sample arithmetic, built for the host
+from the same source (tests/host/gl_host_check.cpp includes gl_device.h; the
+host build takes IEEE division and square root where the device takes the
+hardware estimates, everything else is shared with the kernels).
+
+* the own sine/cosine, arctangent and angle reduction against the C library;
+* instantaneous fluxes of the host build against the oracle, at the exact
+  path's bar (1e-9), on hard shapes and grazing geometries and on MCMC-walker
+  draws around the transit.
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2410_05408_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HIP_INC = "/opt/rocm/include"
+
+
+@pytest.fixture(scope="session")
+def host_check(tmp_path_factory):
+    cxx = shutil.which("g++")
+    if cxx is None or not os.path.exists(os.path.join(HIP_INC, "hip", "hip_runtime.h")):
+        pytest.skip("needs g++ and the HIP headers")
+    exe = str(tmp_path_factory.mktemp("host") / "gl_host_check")
+    subprocess.run([cxx, "-O2", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I", HIP_INC,
+                    "-I", os.path.join(ROOT, "paper_2410_05408_amd", "csrc"), "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "host", "gl_host_check.cpp"), "-o", exe], check=True)
+    return exe
+
+
+def host_flux(exe, tmp_path, params, times):
+    pf, tf, of = (str(tmp_path / n) for n in ("p.bin", "t.bin", "o.bin"))
+    np.ascontiguousarray(params, dtype=np.float64).tofile(pf)
+    np.ascontiguousarray(times, dtype=np.float64).tofile(tf)
+    subprocess.run([exe, "flux", pf, tf, of], check=True)
+    return np.fromfile(of)
+
+
+def oracle_flux(oracle, params, times):
+    n = times.size
+    return oracle.flux_batch(params, times, offsets=np.arange(n + 1), n_ss=np.ones(n, np.int32),
+                             t_exp=np.zeros(n))
+
+
+def test_own_trigonometry_against_libm(host_check):
+    out = subprocess.run([host_check, "math"], check=True, capture_output=True, text=True).stdout.split()
+    es, ec, ea, ew, rw = (float(v) for v in out)
+    assert es <= 4.5e-16 and ec <= 4.5e-16      # sincos_pi on [-pi, pi]
+    assert ea <= 9e-16                           # atan2_d, including the axes and the origin
+    assert ew <= 2e-14 and rw <= math.pi + 1e-15  # angle reduction for |a| <= 40 pi
+
+
+def test_host_flux_matches_oracle_on_hard_shapes(host_check, oracle, tmp_path):
+    w = W.adversarial_batch(60)
+    rng = np.random.default_rng(5)
+    cols, ts = [], []
+    for s in range(w.n_sets):
+        a, b = int(w.offsets[s]), int(w.offsets[s + 1])
+        pick = rng.choice(np.arange(a, b), size=min(24, b - a), replace=False)
+        cols += [s] * pick.size
+        ts.append(w.times[pick])
+    params = w.params[:, cols]
+    times = np.concatenate(ts)
+    got = host_flux(host_check, tmp_path, params, times)
+    ref = oracle_flux(oracle, params, times)
+    assert np.all(np.isfinite(got))
+    assert np.sum(got < 1.0) > times.size // 3   # most samples occult something
+    assert np.max(np.abs(got - ref)) <= 1e-9
+
+
+def test_host_flux_matches_oracle_on_walker_draws(host_check, oracle, tmp_path):
+    rng = np.random.default_rng(11)
+    n = 3000
+    params = W.draw_params(rng, n)
+    t14 = W.full_duration(params[W.K], params[W.B], params[W.ARS], params[W.P])
+    times = rng.uniform(-0.6, 0.6, n) * t14
+    got = host_flux(host_check, tmp_path, params, times)
+    ref = oracle_flux(oracle, params, times)
+    assert np.sum(got < 1.0) > n // 2
+    assert np.max(np.abs(got - ref)) <= 1e-9
