@@ -455,15 +455,33 @@ GL_HD void solve_quartic_inl(const Poly4& q, QuarticRoots& out, CT& ct)
             if (m > 0.0 && m < 1e300) dq[i] = sqrt_nn(m);
         }
     }
+    // the brackets with a sign change are solved in a loop over the lane's own
+    // brackets (one Newton loop per root of the lane, not per bracket slot:
+    // the lanes of a wavefront mostly have their two roots in different slots)
     out.n_roots = 0;
+    unsigned todo = 0u;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const double lo = pt[i], hi = pt[i + 1];
-        const double flo = fq[i], fhi = fq[i + 1];
-        out.rv[i] = (flo < 0.0) != (fhi < 0.0) && flo != 0.0 && fhi != 0.0;
-        const double start = dq[i] <= dq[i + 1] ? lo + dq[i] : hi - dq[i + 1];  // from the nearer model
-        out.r[i] = out.rv[i] ? bracket_root<0>(q, lo, hi, flo, fhi, ct, start) : 0.0;
+        out.rv[i] = (fq[i] < 0.0) != (fq[i + 1] < 0.0) && fq[i] != 0.0 && fq[i + 1] != 0.0;
+        out.r[i] = 0.0;
         out.n_roots += out.rv[i] ? 1 : 0;
+        todo |= (out.rv[i] ? 1u : 0u) << i;
+    }
+    while (todo) {
+        const int i = __builtin_ctz(todo);
+        todo &= todo - 1u;
+        // bracket i by selects (the slots stay in registers)
+        const double lo = i == 0 ? pt[0] : i == 1 ? pt[1] : i == 2 ? pt[2] : pt[3];
+        const double hi = i == 0 ? pt[1] : i == 1 ? pt[2] : i == 2 ? pt[3] : pt[4];
+        const double flo = i == 0 ? fq[0] : i == 1 ? fq[1] : i == 2 ? fq[2] : fq[3];
+        const double fhi = i == 0 ? fq[1] : i == 1 ? fq[2] : i == 2 ? fq[3] : fq[4];
+        const double dlo = i == 0 ? dq[0] : i == 1 ? dq[1] : i == 2 ? dq[2] : dq[3];
+        const double dhi = i == 0 ? dq[1] : i == 1 ? dq[2] : i == 2 ? dq[3] : dq[4];
+        const double start = dlo <= dhi ? lo + dlo : hi - dhi;  // from the nearer model
+        const double x = bracket_root<0>(q, lo, hi, flo, fhi, ct, start);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k == i) out.r[k] = x;
     }
 }
 
