@@ -149,6 +149,44 @@ def stage_flop_split(census, per):
     }
 
 
+# launches that carry a stage's work: the arc stage is two level kernels of
+# about equal length (and a short tail launch), every other FP64 stage is one
+STAGE_LAUNCHES = {"arcs": 2}
+
+
+def rooflines(stage_ms, census, per, n_out, n_in_window_out, n_times):
+    """(roofline of the dominant kernel, rooflines of the other stages).  The
+    dominant kernel is the FP64 kernel with the longest launch: a stage's time
+    divided by the launches that carry its work."""
+    flops = sum(census[k] * per[k] for k in census)
+    stage_flops = stage_flop_split(census, per)
+    dom = max(FLOP_STAGES, key=lambda k: stage_ms[k] / STAGE_LAUNCHES.get(k, 1))
+    kern_ms = sum(v for k, v in stage_ms.items() if k != "setup")
+
+    def alu_roof(stage):
+        a = stage_flops[stage] / (stage_ms[stage] * 1e-3) / 1e12
+        return {"bound": "alu", "kernel": STAGE_KERNELS[stage], "achieved": a,
+                "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": a / FP64_VECTOR_PEAK_TFLOPS,
+                "traffic": measured_traffic(STAGE_KERNELS[stage]),
+                "algorithmic_flop_per_launch": stage_flops[stage], "kernel_ms": stage_ms[stage]}
+
+    # the fill and store phase against HBM: every output out of the transit
+    # window is written once (8 B) by the window kernel, which also reads the
+    # shared time grid once
+    fill_bytes = 8 * (n_out - n_in_window_out) + 8 * n_times
+    fill_gbs = fill_bytes / (stage_ms["window"] * 1e-3) / 1e9
+    roof = dict(alu_roof(dom), whole_pipeline={
+        "algorithmic_flop": flops, "compute_ms": kern_ms,
+        "achieved": flops / (kern_ms * 1e-3) / 1e12})
+    stages = {
+        **{k: alu_roof(k) for k in FLOP_STAGES if k != dom},
+        "window": {"bound": "hbm", "kernel": STAGE_KERNELS["window"], "achieved": fill_gbs,
+                   "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fill_gbs / HBM_PEAK_GBS,
+                   "traffic": measured_traffic(STAGE_KERNELS["window"]),
+                   "algorithmic_bytes_per_launch": fill_bytes, "kernel_ms": stage_ms["window"]}}
+    return roof, stages
+
+
 def copy_calibration(n_bytes=1 << 30, reps=3):
     """A plain device-to-device copy of known size: the HBM byte counters read
     for it (per dispatch) give the scale applied to the compute kernel's."""
@@ -232,28 +270,8 @@ def main():
                           t_exp=d["t_exp"], stream=stream)
     wpc = gl.gl_ctx_get_plan(ctx.handle)
     per = gl.gl_flop_model()
-    flops = sum(census[k] * per[k] for k in census)
-    stage_flops = stage_flop_split(census, per)
-    # dominant kernel: the FP64 stage that takes longest (each is one kernel,
-    # except the arc rule's level launches)
-    dom = max(FLOP_STAGES, key=lambda k: stage_ms[k])
-    dom_ms = stage_ms[dom]
-    achieved = stage_flops[dom] / (dom_ms * 1e-3) / 1e12
-    kern_ms = sum(v for k, v in stage_ms.items() if k != "setup")
-
-    def alu_roof(stage):
-        a = stage_flops[stage] / (stage_ms[stage] * 1e-3) / 1e12
-        return {"bound": "alu", "kernel": STAGE_KERNELS[stage], "achieved": a,
-                "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": a / FP64_VECTOR_PEAK_TFLOPS,
-                "traffic": measured_traffic(STAGE_KERNELS[stage]),
-                "algorithmic_flop_per_launch": stage_flops[stage], "kernel_ms": stage_ms[stage]}
-
-    # the fill and store phase against HBM: every output out of the transit
-    # window is written once (8 B) by the window kernel, which also reads the
-    # shared time grid once
-    n_in_window_out = census["sub_in_window"] // int(w.n_ss[0])
-    fill_bytes = 8 * (w.n_out - n_in_window_out) + 8 * int(w.times.size)
-    fill_gbs = fill_bytes / (stage_ms["window"] * 1e-3) / 1e9
+    roof, roof_stages = rooflines(stage_ms, census, per, w.n_out,
+                                  census["sub_in_window"] // int(w.n_ss[0]), int(w.times.size))
 
     got = out.cpu().numpy().reshape(w.n_sets, -1)
     in_transit = int(np.sum(got < 1.0))
@@ -275,15 +293,8 @@ def main():
         "config": {"workload": "walker_batch", "path": "exact", "n_sets": w.n_sets,
                    "n_times": int(w.times.size), "n_ss": int(w.n_ss[0]),
                    "cadence_min": 29.4, "seed": 2},
-        "roofline": dict(alu_roof(dom), whole_pipeline={
-            "algorithmic_flop": flops, "compute_ms": kern_ms,
-            "achieved": flops / (kern_ms * 1e-3) / 1e12}),
-        "roofline_stages": {
-            **{k: alu_roof(k) for k in FLOP_STAGES if k != dom},
-            "window": {"bound": "hbm", "kernel": STAGE_KERNELS["window"], "achieved": fill_gbs,
-                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fill_gbs / HBM_PEAK_GBS,
-                       "traffic": measured_traffic(STAGE_KERNELS["window"]),
-                       "algorithmic_bytes_per_launch": fill_bytes, "kernel_ms": stage_ms["window"]}},
+        "roofline": roof,
+        "roofline_stages": roof_stages,
         "stage_ms": stage_ms,
         "sub_samples_per_s": w.n_sub / (ms_per_step * 1e-3),
         "in_transit_points_per_s": in_transit / (ms_per_step * 1e-3),
