@@ -390,8 +390,12 @@ GL_HD double bracket_root(const Poly4& q, double lo, double hi, double flo, doub
         // a Newton step below 1e-8 leaves an error of its square (quadratic
         // convergence); near a double root, where convergence is linear, an
         // error of 1e-8 in t moves the region boundary by a sliver of area
-        // O(1e-16) (the limb closes the contour radially there)
-        if (fabs(xn - x) <= 1e-8 * fmax(1.0, ax) || hi - lo <= 2e-16 * fmax(1.0, ax)) return xn;
+        // O(1e-16) (the limb closes the contour radially there).  A critical
+        // point only brackets roots and places a cluster break point (the
+        // integral does not depend on where an arc is split): a step below
+        // 1e-4 (an error near 1e-8) is enough there
+        constexpr double step_tol = Deriv == 0 ? 1e-8 : 1e-4;
+        if (fabs(xn - x) <= step_tol * fmax(1.0, ax) || hi - lo <= 2e-16 * fmax(1.0, ax)) return xn;
         x = xn;
     }
     return x;
