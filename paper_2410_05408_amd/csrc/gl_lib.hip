@@ -363,6 +363,36 @@ __device__ __forceinline__ int64_t shard_slot(const ShardMap& m, int64_t g, int6
     return (int64_t)j * scap + (g - (j > 0 ? prev : 0));
 }
 
+// lane k's value v for a wave-uniform k (no LDS round trip)
+__device__ __forceinline__ int64_t readlane64(int64_t v, int k)
+{
+    const unsigned int lo = __builtin_amdgcn_readlane((unsigned int)(v & 0xffffffffll), k);
+    const unsigned int hi = __builtin_amdgcn_readlane((unsigned int)((uint64_t)v >> 32), k);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// shard_slot for a wavefront whose lanes that matter hold indices in the
+// uniform range [g_first, g_last] (consecutive entries of the list): when the
+// range lies in one shard (nearly always: a shard holds thousands of entries),
+// every lane's slot follows from that shard's first index, found once for the
+// wavefront; otherwise the per-lane search.  Lanes outside the range get a
+// slot in bounds that they must not use.
+__device__ __forceinline__ int64_t shard_slot_run(const ShardMap& m, int64_t g, int64_t g_first, int64_t g_last,
+                                                  int64_t scap)
+{
+    g_first = uniform64(g_first);
+    g_last = uniform64(g_last);
+    int j = 0;  // wave-uniform: the shard holding g_first
+#pragma unroll
+    for (int step = kShards / 2; step >= 1; step >>= 1)
+        if (readlane64(m.incl, j + step - 1) <= g_first) j += step;
+    if (g_last < readlane64(m.incl, j)) {
+        const int64_t o = g - (j > 0 ? readlane64(m.incl, j - 1) : 0);
+        return (o >= 0 && o < scap) ? (int64_t)j * scap + o : 0;
+    }
+    return shard_slot(m, g, scap);
+}
+
 // Queues chunk c for the fused kernel once (the first caller wins).
 __device__ __forceinline__ void to_fused(Counters* ctr, const Pipe& P, int* chunk_fb, int64_t c)
 {
@@ -656,6 +686,7 @@ k_trap(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
     __shared__ int lds_slot[kTrapRounds * kTrapThreads];
     __shared__ int lds_cnt[kTrapBuckets];   // entries per rule order, then their first position
     const int tid = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t scap = P.scap[L_TRAP];
     const ShardMap m = shard_map(ctr, L_TRAP, scap);
     unsigned long long nodes = 0;
@@ -670,7 +701,8 @@ k_trap(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
 #pragma unroll
         for (int r = 0; r < kTrapRounds; ++r) {
             const int64_t g = b0 + r * kTrapThreads + tid;
-            const int64_t sl = shard_slot(m, g < m.total ? g : 0, scap);
+            const int64_t gw = b0 + r * kTrapThreads + 64 * wv;  // the wavefront's first entry
+            const int64_t sl = shard_slot_run(m, g < m.total ? g : 0, gw, std::min(gw + 63, m.total - 1), scap);
             int k = gl::kTrapOrders;
             if (g < m.total) {
                 const Entry& e = P.trap[sl];
