@@ -13,15 +13,17 @@
 //               group entry per 64 sub-samples.
 //   k_classify  one wavefront per group: each sub-sample is classified by its
 //               ellipse centre: off the disk (flux 1 now), whole ellipse well
-//               inside (trapezoid list, sorted by rule order), hard (hard list).
-//   k_trap      one thread per trapezoid entry: mu integral of the whole ellipse.
+//               inside (trapezoid list, with its rule order), hard (hard list).
+//   k_trap      one thread per trapezoid entry (tiles counting-sorted by rule
+//               order in LDS): mu integral of the whole ellipse.
 //   k_hard      one thread per hard entry: intersection quartic, break points,
 //               limb arcs in closed form, ellipse arcs appended to an arc list;
 //               whole ellipses near the limb go to the nested-trapezoid list.
 //   k_nested    one thread per nested entry: nested periodic trapezoid.
-//   k_gk<L>     level L = 0..4 of the self-checking arc rule: one thread per
+//   k_gk<L>     level L = 0, 1 of the self-checking arc rule: one thread per
 //               Gauss-Kronrod piece (2^L pieces per arc, summed across lanes);
 //               arcs whose error estimate is too large go on to level L + 1.
+//   k_gk_tail   the few arcs that reach level 2: the rule from there on, per lane.
 //   k_combine   one thread per hard entry: limb sums + its arcs -> flux.
 //   k_average   one wavefront per listed chunk: box average of each output's
 //               sub-samples in a fixed order (deterministic).
