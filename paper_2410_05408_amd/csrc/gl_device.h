@@ -357,8 +357,9 @@ GL_HD double ddp4(const Poly4& q, double t)
 
 // Root of a function that is monotone on [lo, hi] with values flo, fhi of
 // opposite sign at the ends: Newton from the regula-falsi point, with
-// bisection whenever a step leaves the bracket; stops when the step is at
-// rounding level or |f| is below the rounding noise of its own evaluation.
+// bisection whenever a step leaves the bracket; stops when the step is below
+// its tolerance or the bracket at rounding level, or (a root of q) when |f| is
+// below the rounding noise of its own evaluation.
 template <int Deriv, class CT>
 GL_HD double bracket_root(const Poly4& q, double lo, double hi, double flo, double fhi, CT& ct,
                           double start = __builtin_nan(""))
@@ -371,18 +372,19 @@ GL_HD double bracket_root(const Poly4& q, double lo, double hi, double flo, doub
     if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
     for (int it = 0; it < 100; ++it) {
         ct.iter();
-        double f, df, noise;
+        double f, df;
         const double ax = fabs(x);
         if (Deriv == 0) {
             f = p4(q, x);
             df = dp4(q, x);
-            noise = fma(fma(fma(fma(a4, ax, a3), ax, a2), ax, a1), ax, a0);
+            // a root of q may stop at the rounding noise of its evaluation; a
+            // critical point stops on its step alone (the 1e-4 tolerance below)
+            const double noise = fma(fma(fma(fma(a4, ax, a3), ax, a2), ax, a1), ax, a0);
+            if (fabs(f) <= 8e-16 * noise) return x;
         } else {
             f = dp4(q, x);
             df = ddp4(q, x);
-            noise = fma(fma(fma(4.0 * a4, ax, 3.0 * a3), ax, 2.0 * a2), ax, a1);
         }
-        if (fabs(f) <= 8e-16 * noise) return x;
         if ((f < 0.0) == (flo < 0.0)) lo = x;
         else hi = x;
         double xn = x - f * rcp(df);
