@@ -122,6 +122,11 @@ static void rule_pair(glo_fn f, const void *ctx, double a, double b,
 
 #define MAXPANEL 6000
 
+/* integrals that stopped at MAXPANEL panels (or at panels too narrow to
+ * split) with their error estimate still above the target; reported by
+ * glo_unconverged so that a test can require none */
+static long glo_n_unconverged = 0;
+
 static double adapt(glo_fn f, const void *ctx, double a, double b, double tol)
 {
     if (!(b > a)) return 0.0;
@@ -137,9 +142,16 @@ static double adapt(glo_fn f, const void *ctx, double a, double b, double tol)
             etot += P[i].err;
             if (P[i].err > P[worst].err) worst = i;
         }
-        if (etot <= tol || n + 1 >= MAXPANEL) break;
+        if (etot <= tol) break;
         double pa = P[worst].a, pb = P[worst].b, pm = 0.5 * (pa + pb);
-        if (!(pm > pa && pm < pb)) break; /* panel cannot be split further */
+        if (n + 1 >= MAXPANEL || !(pm > pa && pm < pb)) {
+            /* out of panels, or the worst panel cannot be split further */
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+            glo_n_unconverged++;
+            break;
+        }
         P[worst].b = pm;
         rule_pair(f, ctx, pa, pm, &P[worst].val, &P[worst].err);
         P[n].a = pm;
@@ -343,8 +355,11 @@ static int kink_values(const occ_ctx *c, double psi, double e[4])
     double w = c->k * sin(psi);
     double half = c->kq * cos(psi);
     double hh = c->cu + w;
-    if (!(fabs(hh) < 1.0)) return 0;
-    double R = sqrt((1.0 - hh) * (1.0 + hh));
+    /* the disk chord exists for |hh| <= 1; a point at the disk's vertical
+     * tangent (a scan abscissa there, up to its rounding) has R = 0 */
+    if (!(fabs(hh) <= 1.0 + 1e-12)) return 0;
+    double r2 = (1.0 - hh) * (1.0 + hh);
+    double R = r2 > 0.0 ? sqrt(r2) : 0.0;
     double eU = c->cs + half, eL = c->cs - half;
     e[0] = eU - R;
     e[1] = eL + R;
@@ -361,6 +376,49 @@ static int cmp_double(const void *a, const void *b)
 
 #define NGRID 1024
 #define MAXBRK 64
+
+/* zero of limit-crossing function j in [a, b], where it changes sign (fa: its
+ * value at a), by bisection */
+static double kink_bisect(const occ_ctx *c, int j, double a, double b, double fa)
+{
+    for (int it = 0; it < 80; it++) {
+        double m = 0.5 * (a + b), em[4];
+        if (!kink_values(c, m, em)) break;
+        if ((em[j] < 0.0) == (fa < 0.0)) {
+            a = m;
+            fa = em[j];
+        } else {
+            b = m;
+        }
+    }
+    return 0.5 * (a + b);
+}
+
+/* golden-section search on [a, b] for the point where dir * (function j) is
+ * smallest (dir = +1: its minimum, -1: its maximum) */
+static double kink_extremum(const occ_ctx *c, int j, double a, double b, double dir)
+{
+    const double g = 0.6180339887498949; /* (sqrt(5) - 1)/2 */
+    double x1 = b - g * (b - a), x2 = a + g * (b - a), e1[4], e2[4];
+    double f1 = kink_values(c, x1, e1) ? dir * e1[j] : HUGE_VAL;
+    double f2 = kink_values(c, x2, e2) ? dir * e2[j] : HUGE_VAL;
+    for (int it = 0; it < 90; it++) {
+        if (f1 < f2) {
+            b = x2;
+            x2 = x1;
+            f2 = f1;
+            x1 = b - g * (b - a);
+            f1 = kink_values(c, x1, e1) ? dir * e1[j] : HUGE_VAL;
+        } else {
+            a = x1;
+            x1 = x2;
+            f1 = f2;
+            x2 = a + g * (b - a);
+            f2 = kink_values(c, x2, e2) ? dir * e2[j] : HUGE_VAL;
+        }
+    }
+    return 0.5 * (a + b);
+}
 
 double glo_occulted(double cx, double cy, double ux, double uy, double k,
                     double q, double u1, double u2, double tol, int mode)
@@ -388,30 +446,46 @@ double glo_occulted(double cx, double cy, double ux, double uy, double k,
         double sv = (sgn - c.cu) / k;
         if (sv > -1.0 && sv < 1.0) brk[nb++] = asin(sv);
     }
-    double prev_psi = 0.0, prev_e[4];
-    int prev_ok = 0;
-    for (int i = 0; i <= NGRID && nb < MAXBRK - 4; i++) {
-        double psi = -0.5 * M_PI + M_PI * (double)i / NGRID;
+    /* sign scan of the four limit-crossing functions on a grid; a sign change
+     * in a cell is refined by bisection.  Two zeros inside one cell (a
+     * near-tangency) leave no sign change, so wherever a function has a
+     * local extremum between three grid points without a sign change there,
+     * the extremum is located and, if it lies across zero, both zeros are
+     * refined. */
+    /* scan abscissae: the uniform grid and the disk's vertical tangents (the
+     * ends of the range where the disk chord exists), so that a zero between
+     * the last grid point and such an end is seen as a sign change */
+    double scan[NGRID + 3];
+    int ns = 0;
+    for (int i = 0; i <= NGRID; i++) scan[ns++] = -0.5 * M_PI + M_PI * (double)i / NGRID;
+    for (int i = 2; i < nb; i++) scan[ns++] = brk[i];
+    qsort(scan, (size_t)ns, sizeof(double), cmp_double);
+    double pp_psi = 0.0, prev_psi = 0.0, pp_e[4], prev_e[4];
+    int pp_ok = 0, prev_ok = 0;
+    for (int i = 0; i < ns && nb < MAXBRK - 8; i++) {
+        double psi = scan[i];
         double e[4];
         int ok = kink_values(&c, psi, e);
         if (ok && prev_ok) {
-            for (int j = 0; j < 4 && nb < MAXBRK; j++) {
+            for (int j = 0; j < 4 && nb < MAXBRK - 4; j++) {
                 if ((prev_e[j] < 0.0) != (e[j] < 0.0)) {
-                    double a = prev_psi, b = psi, fa = prev_e[j];
-                    for (int it = 0; it < 80; it++) {
-                        double m = 0.5 * (a + b), em[4];
-                        if (!kink_values(&c, m, em)) break;
-                        if ((em[j] < 0.0) == (fa < 0.0)) {
-                            a = m;
-                            fa = em[j];
-                        } else {
-                            b = m;
-                        }
+                    brk[nb++] = kink_bisect(&c, j, prev_psi, psi, prev_e[j]);
+                } else if (pp_ok && (pp_e[j] < 0.0) == (prev_e[j] < 0.0) &&
+                           (prev_e[j] - pp_e[j]) * (e[j] - prev_e[j]) < 0.0) {
+                    /* extremum near prev_psi: pull it toward zero */
+                    double dir = (prev_e[j] < 0.0) ? -1.0 : 1.0;
+                    double ps = kink_extremum(&c, j, pp_psi, psi, dir);
+                    double es[4];
+                    if (kink_values(&c, ps, es) && (es[j] < 0.0) != (prev_e[j] < 0.0)) {
+                        brk[nb++] = kink_bisect(&c, j, pp_psi, ps, pp_e[j]);
+                        brk[nb++] = kink_bisect(&c, j, ps, psi, es[j]);
                     }
-                    brk[nb++] = 0.5 * (a + b);
                 }
             }
         }
+        pp_ok = prev_ok;
+        pp_psi = prev_psi;
+        if (prev_ok) memcpy(pp_e, prev_e, sizeof(e));
         prev_ok = ok;
         prev_psi = psi;
         if (ok) memcpy(prev_e, e, sizeof(e));
@@ -541,6 +615,16 @@ int64_t glo_flux_batch(const double *params, int64_t n_sets,
         }
     }
     return nerr;
+}
+
+long glo_unconverged(void)
+{
+    long n;
+#ifdef _OPENMP
+#pragma omp atomic read
+#endif
+    n = glo_n_unconverged;
+    return n;
 }
 
 int glo_max_threads(void)

@@ -91,6 +91,11 @@ int64_t glo_flux_select(const double *params, int64_t n_sets,
                         const double *t_exp, double tol, const int64_t *sel,
                         int64_t n_sel, double *out_sel, int nthreads);
 
+/* Number of adaptive integrals, since the library was loaded, that stopped
+ * with their error estimate above the target (out of panels, or a panel too
+ * narrow to split).  The tests require it to stay 0. */
+long glo_unconverged(void);
+
 /* Number of OpenMP threads a batch call with nthreads <= 0 would use. */
 int glo_max_threads(void);
 

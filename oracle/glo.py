@@ -60,6 +60,8 @@ def lib():
         L.glo_flux_select.argtypes = [dp, i64, dp, i64p, i64, i32p, dp, d,
                                       i64p, i64, dp, i]
         L.glo_flux_select.restype = i64
+        L.glo_unconverged.argtypes = []
+        L.glo_unconverged.restype = ctypes.c_long
         L.glo_max_threads.argtypes = []
         L.glo_max_threads.restype = i
         _lib = L
@@ -147,6 +149,11 @@ def flux_select(params, times, sel, offsets=None, n_ss=None, t_exp=None,
                           sel.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                           sel.shape[0], _dp(out), int(nthreads))
     return out
+
+
+def unconverged() -> int:
+    """Adaptive integrals that stopped above their error target so far."""
+    return int(lib().glo_unconverged())
 
 
 def max_threads() -> int:
