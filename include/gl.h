@@ -121,14 +121,33 @@ gl_status gl_ctx_set_plan(gl_ctx *ctx, int waves_per_cu);
 
 /* Work-list capacities of the exact path, in entries: sub-sample flux slots
  * (and trapezoid entries) <= 2^27 - 1, hard samples and ellipse arcs
- * <= 2^30 - 1; 0 selects the default (16 Mi slots, a quarter of that of hard
- * samples, twice that of arcs, about 1.5 GB of device memory, less for small
+ * <= 2^30 - 1.  Explicit capacities hold for every batch (one pass each);
+ * all three 0 selects sizing from demand (see gl_ctx_get_overflow), starting
+ * again from the default (16 Mi slots, a quarter of that of hard samples,
+ * twice that of arcs, about 1.5 GB of device memory, less for small
  * batches).  A chunk of 64 outputs whose samples do not fit is evaluated by
  * the fused per-lane kernel instead, with the same results up to rounding;
  * an ellipse arc that does not fit is integrated where it is found.  Waits
  * for the device and frees the current lists (reallocated by the next batch). */
 gl_status gl_ctx_set_capacity(gl_ctx *ctx, int64_t sub_samples, int64_t hard_samples,
                               int64_t arcs);
+
+/* Work lists sized from demand.  Without explicit capacities, every batch
+ * records in pinned host memory how many entries each work list was asked
+ * for, and the next batch on the context sizes its lists from that record
+ * (growing them, and waiting for the device once when it does), and runs as
+ * up to 8 passes over equal ranges of its parameter sets when its in-window
+ * sub-samples exceed about 6.7e7 (2^26), or its lists a third of the device
+ * memory.  Results do not depend on the number of passes or the list sizes:
+ * every sub-sample and output is computed on its own.  A batch that outgrows
+ * the lists planned for it is still exact (the overflowing chunks take the
+ * fused kernel), and the next one is planned for it.
+ *
+ * gl_ctx_get_overflow waits for the device and writes into *fused_chunks the
+ * number of 64-output chunks of the latest batch that did not fit its work
+ * lists (0 when the lists held everything), and into *passes (may be NULL)
+ * the number of passes it ran. */
+gl_status gl_ctx_get_overflow(gl_ctx *ctx, int64_t *fused_chunks, int *passes);
 
 /* When on != 0, later batches replay a captured HIP graph of the whole
  * pipeline if their arguments equal the previous batch's (default on). */
@@ -160,20 +179,33 @@ gl_status gl_ctx_get_stage_timing(gl_ctx *ctx, double *stage_ms, int *n);
 
 /* Work census: runs the batch once (same arguments and results as
  * gl_lightcurve_batch) with counting variants of the kernels, waits, and
- * writes counts[10] (host memory): in-window sub-samples, samples with the
+ * writes counts[11] (host memory): in-window sub-samples, samples with the
  * whole ellipse on the star, intersecting samples, in-window samples off the
  * star, nodes of the rigorous-order periodic trapezoid, 21-node
  * Gauss-Kronrod pieces, Newton steps of the intersection solver, limb arcs,
  * nodes of the nested periodic trapezoid, ellipse arcs listed for the
- * Gauss-Kronrod stage. */
+ * Gauss-Kronrod stage, ellipse arcs accepted unconverged (see
+ * gl_ctx_get_unconverged). */
 gl_status gl_census(gl_ctx *ctx, const double *params, int64_t n_sets, const double *times,
                     const int64_t *offsets, int64_t n_times, const int32_t *n_ss,
                     const double *t_exp, double *out, void *stream, int64_t *counts);
 
 /* Algorithmic FP64 operations per census item (add/sub/mul/div/sqrt/
  * transcendental = 1, fused multiply-add = 2), counted from the kernel source:
- * per_item[10] (host memory) lines up with the census counts. */
+ * per_item[11] (host memory) lines up with the census counts. */
 gl_status gl_flop_model(int64_t *per_item);
+
+/* Accuracy report of the arc rule (Section 2: the Green's-theorem line
+ * integrals along the ellipse arcs on the star).  Each ellipse arc is
+ * integrated by a clustered Gauss-Kronrod 10/21 rule, split into 1, 2, 4, 8
+ * and 16 pieces until the Gauss-Kronrod difference is below its tolerance
+ * (1e-6; the difference estimates the error of the 10-point Gauss sum, the
+ * 21-point Kronrod sum that is kept is far more accurate); an arc still above
+ * it at 16 pieces is accepted there and counted.  Waits for the context's device, writes the
+ * number of such arcs over all batches since the last call into *n_arcs
+ * (host memory) and clears the count.  A nonzero count does not make an
+ * output invalid: it says that the error bound of those arcs was not shown. */
+gl_status gl_ctx_get_unconverged(gl_ctx *ctx, int64_t *n_arcs);
 
 /* ---------------------------------------------------------------------------
  * Residual surrogate network: x[16] -> [Linear -> GELU] x 4 (width 256) -> Linear.

@@ -323,18 +323,24 @@ GL_HD double phase_time(const SetConst& s, double t)
 // ---------------------------------------------------------------- work census
 // The census variant counts the work a sample really does (used to turn the
 // kernel time into an algorithmic FLOP rate); the default does nothing.
+// Both count the arcs that the arc rule accepted at its last level with the
+// Gauss-Kronrod difference still above its tolerance (rare; reported, never
+// silent).
 struct NoCensus {
+    int unconv = 0;
     GL_HD void iter() {}
     GL_HD void arc() {}
     GL_HD void trap(int) {}
     GL_HD void limb() {}
+    GL_HD void unconverged() { ++unconv; }
 };
 struct Census {
-    int iters = 0, arcs = 0, trap_nodes = 0, limbs = 0;
+    int iters = 0, arcs = 0, trap_nodes = 0, limbs = 0, unconv = 0;
     GL_HD void iter() { ++iters; }
     GL_HD void arc() { ++arcs; }           // one 21-node Gauss-Kronrod piece
     GL_HD void trap(int n) { trap_nodes += n; }
     GL_HD void limb() { ++limbs; }
+    GL_HD void unconverged() { ++unconv; }
 };
 
 // ---------------------------------------------------------------- quartic
@@ -615,7 +621,8 @@ GL_HD double gk_piece(const Frame& F, double cc, double sc, double mid, double h
 
 // Whole arc tau in [-h, h]: one or two Gauss-Kronrod pieces (arc_start_level),
 // re-split uniformly into 2, 4, ... pieces until the summed Gauss-Kronrod
-// difference is below kArcTol (L0 >= 0 forces the starting level).
+// difference is below kArcTol (L0 >= 0 forces the starting level).  An arc
+// still above it at kArcMaxLevel is accepted there and counted (ct.unconverged).
 template <class CT>
 GL_HD_CALL void arc_gk(const Frame& F, double cc, double sc, double h, Sums& S, CT& ct, int L0 = -1)
 {
@@ -629,6 +636,7 @@ GL_HD_CALL void arc_gk(const Frame& F, double cc, double sc, double h, Sums& S, 
             ct.arc();
         }
         if (err <= kArcTol || L == kArcMaxLevel) {
+            if (err > kArcTol) ct.unconverged();
             S.flat += K.flat;
             S.lin += K.lin;
             S.quad += K.quad;

@@ -47,7 +47,7 @@ namespace {
 constexpr int kChunk = 64;
 constexpr int kScanThreads = 1024;
 
-constexpr int kCensus = 10;
+constexpr int kCensus = 11;
 constexpr int kLevels = gl::kArcMaxLevel + 1;
 
 // Appended work lists are split into kShards shards, each with its own
@@ -83,10 +83,14 @@ struct Counters {
     unsigned int pad;
     unsigned long long n_fb;          // chunks queued for the fused kernel
     unsigned long long fb_head;       // work head of the fused kernel
+    // arcs accepted at the arc rule's last level above its tolerance, summed
+    // over every batch since gl_ctx_get_unconverged last read it
+    unsigned long long unconverged;
+    unsigned long long fused_batch;   // chunks of the latest batch evaluated by the fused kernel
     // work census (census launches only): in-window sub-samples, whole-on-star,
     // intersecting, in-window but off the star, trapezoid nodes of the rigorous
     // rule, Gauss-Kronrod pieces, Newton steps, limb arcs, nested-trapezoid
-    // nodes, ellipse arcs
+    // nodes, ellipse arcs, arcs accepted unconverged
     unsigned long long census[kCensus];
     LineCount lc[kLists][kShards];    // shard counters (reset by k_prep)
 };
@@ -156,25 +160,32 @@ struct Pipe {
 };
 
 // ---------------------------------------------------------------- kernels
-__global__ void k_prep(const double* __restrict__ params, int64_t n_sets,
+// A batch runs as one or more passes over consecutive ranges of its
+// parameter sets (the whole pipeline per pass); `ld` is the row stride of the
+// parameter block, `first` / `last` mark the batch's first and last pass
+// (census reset, CSR end checks).
+__global__ void k_prep(const double* __restrict__ params, int64_t ld, int64_t n_sets,
                        const int64_t* __restrict__ offsets, int64_t n_times,
                        const int32_t* __restrict__ n_ss, const double* __restrict__ t_exp,
                        gl::SetConst* __restrict__ sc, int64_t* __restrict__ seg_begin,
                        int64_t* __restrict__ seg_len, int64_t* __restrict__ chunk_off,
-                       Counters* __restrict__ ctr, int64_t cps_shared)
+                       Counters* __restrict__ ctr, int64_t cps_shared, int first, int last)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s == 0) {
         ctr->head = 0ull;
         ctr->n_fb = ctr->fb_head = 0ull;
-        for (int i = 0; i < kCensus; ++i) ctr->census[i] = 0ull;
+        if (first) {
+            ctr->fused_batch = 0ull;
+            for (int i = 0; i < kCensus; ++i) ctr->census[i] = 0ull;
+        }
     }
     for (int64_t i = s; i < (int64_t)kLists * kShards; i += (int64_t)gridDim.x * blockDim.x)
         ctr->lc[i / kShards][i % kShards].v = 0ull;
     if (s >= n_sets) return;
     double p[GL_NPARAM];
 #pragma unroll
-    for (int i = 0; i < GL_NPARAM; ++i) p[i] = params[(int64_t)i * n_sets + s];
+    for (int i = 0; i < GL_NPARAM; ++i) p[i] = params[(int64_t)i * ld + s];
     const int nss = n_ss ? n_ss[s] : 1;
     const double te = t_exp ? t_exp[s] : 0.0;
     gl::SetConst c;
@@ -185,8 +196,8 @@ __global__ void k_prep(const double* __restrict__ params, int64_t n_sets,
         b = offsets[s];
         e = offsets[s + 1];
         bool seg_ok = (b >= 0) && (e >= b) && (e <= n_times);
-        if (s == 0) seg_ok = seg_ok && (b == 0);
-        if (s == n_sets - 1) seg_ok = seg_ok && (e == n_times);
+        if (s == 0 && first) seg_ok = seg_ok && (b == 0);
+        if (s == n_sets - 1 && last) seg_ok = seg_ok && (e == n_times);
         if (!seg_ok) {
             b = 0;
             e = 0;
@@ -310,6 +321,17 @@ __device__ __forceinline__ void census_add(Counters* ctr, int idx, unsigned long
 {
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
     if ((threadIdx.x & 63) == 0 && v) atomicAdd(&ctr->census[idx], v);
+}
+
+// Adds a wave's count of unconverged arcs (and to the census in census launches).
+__device__ __forceinline__ void unconverged_add(Counters* ctr, int v, bool census)
+{
+    unsigned long long u = (unsigned long long)v;
+    for (int d = 32; d >= 1; d >>= 1) u += __shfl_xor(u, d);
+    if ((threadIdx.x & 63) == 0 && u) {
+        atomicAdd(&ctr->unconverged, u);
+        if (census) atomicAdd(&ctr->census[10], u);
+    }
 }
 
 // Reserves m slots of list l in shard j for the calling wavefront (called by
@@ -952,6 +974,7 @@ k_nested(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P
         census_add(ctr, 7, (unsigned long long)ct.limbs);
         census_add(ctr, 5, (unsigned long long)ct.arcs);
     }
+    unconverged_add(ctr, CENSUS ? ct.unconv : nc.unconv, CENSUS);
 }
 
 // Level L of the self-checking arc rule: arc tau in [-h, h] split into 2^L
@@ -1042,6 +1065,7 @@ k_gk_tail(Counters* __restrict__ ctr, Pipe P)
         P.arc_res[r.arc] = K;
     }
     if (CENSUS) census_add(ctr, 5, (unsigned long long)ct.arcs);
+    unconverged_add(ctr, CENSUS ? ct.unconv : nc.unconv, CENSUS);
 }
 
 // Hard samples with ellipse arcs: limb sums plus the accepted arc sums in
@@ -1115,12 +1139,59 @@ k_average(const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_b
     }
 }
 
+// Work-list demand of the batches run on a context, in pinned host memory:
+// written by k_demand at the end of every pass, read by the host when it plans
+// the next batch (a stale read only delays a resize).  `norm` is the largest
+// per-shard demand of each list seen in one pass, times that batch's number of
+// passes (what one pass over the whole batch would need); demand that a
+// full upstream list hid (a chunk without flux slots is never classified) is
+// estimated from the upstream list's ratio of demand to entries kept.
+struct Demand {
+    unsigned long long norm[kLists];
+    double sub_per_slot;           // largest ratio of in-window sub-samples to output slots of a batch
+    unsigned long long cur_sub;    // running sum over the passes of the current batch
+};
+
+__global__ void __launch_bounds__(64)
+k_demand(Counters* __restrict__ ctr, Pipe P, Demand* __restrict__ rec, int first, int last, int passes,
+         double slots)
+{
+    const int lane = threadIdx.x;
+    auto wsum = [](unsigned long long v) {
+        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+        return v;
+    };
+    auto wmax = [](unsigned long long v) {
+        for (int d = 32; d >= 1; d >>= 1) v = std::max(v, (unsigned long long)__shfl_xor(v, d));
+        return v;
+    };
+    auto raw = [&](int l) { return lane < kShards ? (unsigned long long)list_count(ctr, l, lane) : 0ull; };
+    auto kept = [&](int l) { return std::min(raw(l), (unsigned long long)P.scap[l]); };
+    const unsigned long long sub_raw = wsum(raw(L_SUB)), sub_kept = wsum(kept(L_SUB));
+    const unsigned long long hard_raw = wsum(raw(L_HARD)), hard_kept = wsum(kept(L_HARD));
+    const double r1 = (double)sub_raw / (double)std::max(1ull, sub_kept);
+    const double r2 = r1 * (double)hard_raw / (double)std::max(1ull, hard_kept);
+    unsigned long long est[kLists];
+    for (int l = 0; l < kLists; ++l) {
+        const double r = (l == L_SUB || l == L_WC || l == L_GRP) ? 1.0 : (l == L_TRAP || l == L_HARD) ? r1 : r2;
+        est[l] = (unsigned long long)((double)wmax(raw(l)) * r * passes) + 1ull;
+    }
+    if (lane == 0) {
+        for (int l = 0; l < kLists; ++l) rec->norm[l] = std::max(rec->norm[l], est[l]);
+        const unsigned long long cur = (first ? 0ull : rec->cur_sub) + sub_raw;
+        rec->cur_sub = cur;
+        if (last) rec->sub_per_slot = std::max(rec->sub_per_slot, (double)cur / slots);
+        ctr->fused_batch += ctr->n_fb;
+    }
+}
+
 // Sub-samples of one chunk kept in LDS by the three-phase path (n_ss <= 16).
 constexpr int kMaxSubLds = kChunk * 16;
 
 template <bool CENSUS>
 struct Counter {
     unsigned long long v[kCensus];
+    int unconv = 0;  // unconverged arcs (counted in every launch)
     __device__ void add_sample(int cls, const gl::Census& ct)
     {
         if (!CENSUS) return;
@@ -1130,6 +1201,7 @@ struct Counter {
         v[5] += ct.arcs;
         v[6] += ct.iters;
         v[7] += ct.limbs;
+        unconv += ct.unconv;
     }
 };
 
@@ -1174,7 +1246,9 @@ __device__ __attribute__((noinline)) double flux_hard(const gl::SetConst& S, dou
         return 1.0 - d;
     }
     gl::NoCensus nc;
-    return 1.0 - gl::occulted_hard<gl::NoCensus>(S, x0, y0, nullptr, nc);
+    const double d = gl::occulted_hard<gl::NoCensus>(S, x0, y0, nullptr, nc);
+    cnt.unconv += nc.unconv;
+    return 1.0 - d;
 }
 
 // Occupancy target of the compute kernel (waves per SIMD; 0 = compiler's choice).
@@ -1289,12 +1363,13 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
         }
     }
     if (CENSUS) {
-        for (int i = 0; i < kCensus; ++i) {
+        for (int i = 0; i < 8; ++i) {
             unsigned long long v = cnt.v[i];
             for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
             if (lane == 0) atomicAdd(&ctr->census[i], v);
         }
     }
+    unconverged_add(ctr, cnt.unconv, CENSUS);
 }
 
 }  // namespace
@@ -1331,6 +1406,7 @@ struct gl_ctx {
         void* stream;
         int waves;
         void* ws;
+        int passes;
     } key{};
     bool have_graph = false;
     // surrogate path buffers (grown on demand)
@@ -1352,8 +1428,16 @@ struct gl_ctx {
     int* chunk_fb = nullptr;  // per chunk: 1 = evaluated by the fused kernel
     int64_t pipe_chunks = 0;  // length of the per-chunk arrays
     int64_t want_sub = 0, want_hard = 0, want_arc = 0;
-    // per-launch timing: an event before the first and after every stage
-    int t_slots = 0, t_used = 0;
+    // demand-driven sizing: the record k_demand writes (pinned host memory and
+    // its device address), and the per-shard capacities it asked for
+    Demand* rec = nullptr;
+    Demand* rec_dev = nullptr;
+    int64_t auto_scap[kLists] = {};
+    int64_t mem_total = 0;
+    int passes = 1;  // passes of the current batch (plan_passes)
+    // per-launch timing: an event before the first and after every stage of
+    // every pass; t_used counts pass slots, t_batches batches
+    int t_slots = 0, t_used = 0, t_batches = 0;
     hipEvent_t* ev = nullptr;  // (GL_NSTAGES + 1) events per slot
 };
 
@@ -1490,10 +1574,22 @@ gl_status ensure_pipe(gl_ctx* ctx, int64_t n_chunks)
     sc_[L_SUB] = (cs + kShards - 1) / kShards;
     sc_[L_TRAP] = sc_[L_SUB];
     sc_[L_WC] = std::max<int64_t>(64, 2 * ((nc + kShards - 1) / kShards));
-    sc_[L_GRP] = std::max<int64_t>(64, sc_[L_SUB] / kChunk + sc_[L_WC]);
     sc_[L_HARD] = (ch + kShards - 1) / kShards;
     sc_[L_NEST] = sc_[L_HARD];
     sc_[L_ARC] = (ca + kShards - 1) / kShards;
+    // lists without an explicit capacity grow to the demand of earlier batches
+    const bool auto_sz = ctx->want_sub == 0 && ctx->want_hard == 0 && ctx->want_arc == 0;
+    if (auto_sz) {
+        const int64_t sub_max = (kSubMask - kShards) / kShards, ent_max = (INT32_MAX / 2) / kShards;
+        sc_[L_SUB] = std::min(sub_max, std::max(sc_[L_SUB], ctx->auto_scap[L_SUB]));
+        sc_[L_TRAP] = std::min(sub_max, std::max(sc_[L_SUB], ctx->auto_scap[L_TRAP]));
+        sc_[L_HARD] = std::min(ent_max, std::max(sc_[L_HARD], ctx->auto_scap[L_HARD]));
+        sc_[L_NEST] = std::min(ent_max, std::max(sc_[L_HARD], ctx->auto_scap[L_NEST]));
+        int64_t arc = std::max(sc_[L_ARC], ctx->auto_scap[L_ARC]);
+        for (int L = 0; L < kLevels; ++L) arc = std::max(arc, ctx->auto_scap[L_LVL0 + L]);
+        sc_[L_ARC] = std::min(ent_max, arc);
+    }
+    sc_[L_GRP] = std::max<int64_t>(64, sc_[L_SUB] / kChunk + sc_[L_WC]);
     for (int L = 0; L < kLevels; ++L) sc_[L_LVL0 + L] = sc_[L_ARC];
     Pipe& P = ctx->pipe;
     bool same = ctx->have_pipe && ctx->pipe_chunks >= n_chunks;
@@ -1538,6 +1634,9 @@ struct Batch {
     double* out;
     hipStream_t stream;
     int64_t max_chunks;
+    int64_t ld = 0;          // row stride of params (the whole batch's n_sets)
+    int first = 1, last = 1;  // first / last pass of the batch
+    int64_t slots = 0;       // output chunk slots of the whole batch, x 64
 };
 
 gl_status check_args(gl_ctx* ctx, Batch& b)
@@ -1560,6 +1659,8 @@ gl_status check_args(gl_ctx* ctx, Batch& b)
             return fail(ctx, GL_ERR_SIZE, "batch too large for one window launch");
     }
     if (b.max_chunks > ((int64_t)1 << 40)) return fail(ctx, GL_ERR_SIZE, "batch too large");
+    b.ld = b.n_sets;
+    b.slots = b.max_chunks * kChunk;
     return GL_OK;
 }
 
@@ -1607,9 +1708,9 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     const Pipe& P = ctx->pipe;
     const unsigned prep_blocks = (unsigned)((b.n_sets + 255) / 256);
     const int64_t cps_shared = shared ? (b.n_times + kChunk - 1) / kChunk : 0;
-    hipLaunchKernelGGL(k_prep, dim3(prep_blocks), dim3(256), 0, st, b.params, b.n_sets,
+    hipLaunchKernelGGL(k_prep, dim3(prep_blocks), dim3(256), 0, st, b.params, b.ld, b.n_sets,
                        b.offsets, b.n_times, b.n_ss, b.t_exp, ctx->sc, ctx->seg_begin,
-                       ctx->seg_len, ctx->chunk_off, ctx->ctr, cps_shared);
+                       ctx->seg_len, ctx->chunk_off, ctx->ctr, cps_shared, b.first, b.last);
     if (!shared)
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, ctx->chunk_off, b.n_sets,
                            b.max_chunks, ctx->ctr);
@@ -1640,15 +1741,103 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     hipLaunchKernelGGL(k_compute<CENSUS>, dim3((unsigned)std::max<int64_t>(1, n_cu / 4)), dim3(64), 0, st, b.times, shared,
                        ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, ctx->masks, ctx->chunk_set,
                        P.fb_chunk, b.out);
+    if (ctx->rec_dev)
+        hipLaunchKernelGGL(k_demand, dim3(1), dim3(64), 0, st, ctx->ctr, P, ctx->rec_dev, b.first, b.last,
+                           ctx->passes, (double)b.slots);
     GL_STAGE_DONE();
 #undef GL_STAGE_DONE
     GL_HIP(hipGetLastError(), "kernel launch");
     return GL_OK;
 }
 
+// Passes: a batch whose in-window sub-samples exceed what one pass should
+// hold runs as up to kMaxPasses passes of the whole pipeline over equal
+// ranges of its parameter sets.  Results do not depend on the split (every
+// sub-sample and output is computed by itself), only the list sizes do.
+constexpr int kMaxPasses = 8;
+constexpr int64_t kPassSub = (int64_t)1 << 26;  // in-window sub-samples one pass aims at
+
+// Bytes of the work lists at per-shard capacities c (entries).
+int64_t pipe_bytes(const int64_t* c)
+{
+    const int64_t K = kShards;
+    return K * (c[L_SUB] * 8 + c[L_TRAP] * (int64_t)sizeof(Entry) + c[L_GRP] * (int64_t)sizeof(Group) +
+                c[L_WC] * (int64_t)sizeof(WorkChunk) +
+                c[L_HARD] * (int64_t)(sizeof(Entry) + sizeof(HardRec) + sizeof(gl::Frame)) +
+                c[L_NEST] * (int64_t)sizeof(Entry) +
+                c[L_ARC] * (int64_t)(sizeof(ArcRec) + sizeof(gl::Sums) + kLevels * sizeof(ArcRef)));
+}
+
+// Number of passes for the batch, and the per-shard list capacities it asks
+// for (ctx->auto_scap, only ever raised), from the demand record.  One pass
+// with explicit capacities (gl_ctx_set_capacity) or no record yet.
+int plan_passes(gl_ctx* ctx, const Batch& b)
+{
+    if (!ctx->rec || ctx->want_sub || ctx->want_hard || ctx->want_arc) return 1;
+    const volatile Demand* r = ctx->rec;
+    // expected in-window sub-samples of this batch at the densest ratio seen
+    const int64_t bs = (int64_t)(r->sub_per_slot * (double)b.slots);
+    if (bs == 0) return 1;
+    int T = (int)std::min<int64_t>(kMaxPasses, (bs + bs / 8 + kPassSub - 1) / kPassSub);
+    T = (int)std::max<int64_t>(1, std::min<int64_t>(T, b.n_sets));
+    // the lists of one pass may take up to a third of the device memory
+    const int64_t budget = ctx->mem_total / 3;
+    int64_t need[kLists];
+    for (;;) {
+        for (int l = 0; l < kLists; ++l) {
+            const int64_t n = (int64_t)r->norm[l];
+            need[l] = std::max(ctx->auto_scap[l], n / T + n / (4 * T) + 64);
+        }
+        need[L_GRP] = need[L_SUB] / kChunk + need[L_WC];
+        if (pipe_bytes(need) <= budget || T >= std::min<int64_t>(kMaxPasses, b.n_sets)) break;
+        ++T;
+    }
+    for (int l = 0; l < kLists; ++l) ctx->auto_scap[l] = need[l];
+    return T;
+}
+
+// Plans a batch's passes and sizes the workspace for them (may wait for the
+// device and reallocate; never called inside a stream capture).
+gl_status prepare_batch(gl_ctx* ctx, const Batch& b)
+{
+    ctx->passes = plan_passes(ctx, b);
+    gl_status st = ensure_ws(ctx, b.n_sets, b.max_chunks);
+    if (st != GL_OK) return st;
+    return ensure_pipe(ctx, b.max_chunks);
+}
+
+// Enqueues every pass of a prepared batch (inside a stream capture when
+// called from one).
+gl_status run_batch(gl_ctx* ctx, const Batch& b, bool census)
+{
+    gl_status st = GL_OK;
+    const int T = ctx->passes;
+    if (ctx->t_slots > 0 && !census) ctx->t_batches++;
+    for (int p = 0; p < T; ++p) {
+        const int64_t a = b.n_sets * p / T, e = b.n_sets * (p + 1) / T;
+        Batch q = b;
+        q.params = b.params + a;
+        q.n_sets = e - a;
+        q.n_ss = b.n_ss ? b.n_ss + a : nullptr;
+        q.t_exp = b.t_exp ? b.t_exp + a : nullptr;
+        if (b.offsets) {
+            q.offsets = b.offsets + a;
+            q.max_chunks = b.n_times / kChunk + q.n_sets;
+        } else {
+            q.out = b.out + a * b.n_times;
+            q.max_chunks = (b.n_times + kChunk - 1) / kChunk * q.n_sets;
+        }
+        q.first = p == 0;
+        q.last = p == T - 1;
+        st = census ? enqueue_t<true>(ctx, q) : enqueue_t<false>(ctx, q);
+        if (st != GL_OK) return st;
+    }
+    return GL_OK;
+}
+
 gl_status enqueue(gl_ctx* ctx, const Batch& b, bool census = false)
 {
-    return census ? enqueue_t<true>(ctx, b) : enqueue_t<false>(ctx, b);
+    return run_batch(ctx, b, census);
 }
 
 bool same_key(const gl_ctx::Key& a, const gl_ctx::Key& b)
@@ -1670,13 +1859,25 @@ gl_status gl_ctx_create(gl_ctx** out, int device)
     gl_ctx* ctx = new (std::nothrow) gl_ctx();
     if (!ctx) return GL_ERR_NOMEM;
     ctx->device = device;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
-        ctx->n_cu = prop.multiProcessorCount;
+    hipDeviceProp_t prop{};
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        if (prop.multiProcessorCount > 0) ctx->n_cu = prop.multiProcessorCount;
+        ctx->mem_total = (int64_t)prop.totalGlobalMem;
+    }
+    if (ctx->mem_total <= 0) ctx->mem_total = (int64_t)1 << 34;
     if (hipMalloc(&ctx->ctr, sizeof(Counters)) != hipSuccess) {
         delete ctx;
         return GL_ERR_NOMEM;
     }
+    // the demand record lives in pinned host memory that k_demand writes
+    if (hipHostMalloc((void**)&ctx->rec, sizeof(Demand), hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&ctx->rec_dev, ctx->rec, 0) != hipSuccess) {
+        if (ctx->rec) (void)hipHostFree(ctx->rec);
+        (void)hipFree(ctx->ctr);
+        delete ctx;
+        return GL_ERR_NOMEM;
+    }
+    std::memset(ctx->rec, 0, sizeof(Demand));
     if (hipMemset(ctx->ctr, 0, sizeof(Counters)) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         (void)hipFree(ctx->ctr);
@@ -1692,7 +1893,7 @@ void free_timing(gl_ctx* ctx)
     for (int i = 0; i < (GL_NSTAGES + 1) * ctx->t_slots; ++i) (void)hipEventDestroy(ctx->ev[i]);
     delete[] ctx->ev;
     ctx->ev = nullptr;
-    ctx->t_slots = ctx->t_used = 0;
+    ctx->t_slots = ctx->t_used = ctx->t_batches = 0;
 }
 
 void gl_ctx_destroy(gl_ctx* ctx)
@@ -1704,6 +1905,7 @@ void gl_ctx_destroy(gl_ctx* ctx)
     drop_graph(ctx);
     free_ws(ctx);
     (void)hipFree(ctx->ctr);
+    if (ctx->rec) (void)hipHostFree(ctx->rec);
     delete ctx;
 }
 
@@ -1716,9 +1918,7 @@ gl_status gl_lightcurve_batch(gl_ctx* ctx, const double* params, int64_t n_sets,
     gl_status st = check_args(ctx, b);
     if (st != GL_OK) return st;
     GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-    st = ensure_ws(ctx, n_sets, b.max_chunks);
-    if (st != GL_OK) return st;
-    st = ensure_pipe(ctx, b.max_chunks);
+    st = prepare_batch(ctx, b);
     if (st != GL_OK) return st;
     // the legacy default stream cannot be captured, and timed launches record
     // events per launch: launch directly there
@@ -1735,6 +1935,7 @@ gl_status gl_lightcurve_batch(gl_ctx* ctx, const double* params, int64_t n_sets,
     k.stream = stream;
     k.waves = ctx->waves_per_cu;
     k.ws = ctx->masks;
+    k.passes = ctx->passes;
     if (!ctx->have_graph || !same_key(k, ctx->key)) {
         drop_graph(ctx);
         GL_HIP(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
@@ -1816,9 +2017,7 @@ gl_status gl_autotune(gl_ctx* ctx, const double* params, int64_t n_sets, const d
     gl_status st = check_args(ctx, b);
     if (st != GL_OK) return st;
     GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-    st = ensure_ws(ctx, n_sets, b.max_chunks);
-    if (st != GL_OK) return st;
-    st = ensure_pipe(ctx, b.max_chunks);
+    st = prepare_batch(ctx, b);
     if (st != GL_OK) return st;
     const bool graph = ctx->use_graph;
     drop_graph(ctx);
@@ -1857,15 +2056,17 @@ gl_status gl_autotune(gl_ctx* ctx, const double* params, int64_t n_sets, const d
 gl_status gl_ctx_set_timing(gl_ctx* ctx, int n_slots)
 {
     if (!ctx) return GL_ERR_NULL;
-    if (n_slots < 0 || n_slots > 100000) return fail(ctx, GL_ERR_SIZE, "n_slots in [0, 100000]");
+    if (n_slots < 0 || n_slots > 10000) return fail(ctx, GL_ERR_SIZE, "n_slots in [0, 10000]");
     GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     GL_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
     free_timing(ctx);
     if (n_slots == 0) return GL_OK;
     drop_graph(ctx);
-    ctx->ev = new (std::nothrow) hipEvent_t[(GL_NSTAGES + 1) * n_slots];
+    // one slot per pass of every timed batch
+    const int slots = n_slots * kMaxPasses;
+    ctx->ev = new (std::nothrow) hipEvent_t[(GL_NSTAGES + 1) * slots];
     if (!ctx->ev) return fail(ctx, GL_ERR_NOMEM, "timing slots");
-    for (int i = 0; i < (GL_NSTAGES + 1) * n_slots; ++i) {
+    for (int i = 0; i < (GL_NSTAGES + 1) * slots; ++i) {
         if (hipEventCreate(&ctx->ev[i]) != hipSuccess) {
             for (int j = 0; j < i; ++j) (void)hipEventDestroy(ctx->ev[j]);
             delete[] ctx->ev;
@@ -1873,8 +2074,8 @@ gl_status gl_ctx_set_timing(gl_ctx* ctx, int n_slots)
             return fail(ctx, GL_ERR_DEVICE, "hipEventCreate");
         }
     }
-    ctx->t_slots = n_slots;
-    ctx->t_used = 0;
+    ctx->t_slots = slots;
+    ctx->t_used = ctx->t_batches = 0;
     return GL_OK;
 }
 
@@ -1893,8 +2094,8 @@ gl_status gl_ctx_get_stage_timing(gl_ctx* ctx, double* stage_ms, int* n)
     }
     if (stage_ms)
         for (int k = 0; k < GL_NSTAGES; ++k) stage_ms[k] = acc[k];
-    if (n) *n = ctx->t_used;
-    ctx->t_used = 0;
+    if (n) *n = ctx->t_batches;
+    ctx->t_used = ctx->t_batches = 0;
     return GL_OK;
 }
 
@@ -1924,6 +2125,9 @@ gl_status gl_ctx_set_capacity(gl_ctx* ctx, int64_t sub_samples, int64_t hard_sam
     ctx->want_sub = sub_samples;
     ctx->want_hard = hard_samples;
     ctx->want_arc = arcs;
+    // sizing from demand starts over
+    for (int l = 0; l < kLists; ++l) ctx->auto_scap[l] = 0;
+    std::memset(ctx->rec, 0, sizeof(Demand));
     drop_graph(ctx);
     free_pipe(ctx);
     return GL_OK;
@@ -1938,9 +2142,7 @@ gl_status gl_census(gl_ctx* ctx, const double* params, int64_t n_sets, const dou
     gl_status st = check_args(ctx, b);
     if (st != GL_OK) return st;
     GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-    st = ensure_ws(ctx, n_sets, b.max_chunks);
-    if (st != GL_OK) return st;
-    st = ensure_pipe(ctx, b.max_chunks);
+    st = prepare_batch(ctx, b);
     if (st != GL_OK) return st;
     st = enqueue(ctx, b, true);
     if (st != GL_OK) return st;
@@ -1964,6 +2166,34 @@ gl_status gl_flop_model(int64_t* per_item)
     per_item[7] = gl::kFlopLimb;
     per_item[8] = gl::kFlopTrapNode;
     per_item[9] = gl::kFlopArc;
+    per_item[10] = 0;  // unconverged arcs: their pieces are already counted
+    return GL_OK;
+}
+
+gl_status gl_ctx_get_overflow(gl_ctx* ctx, int64_t* fused_chunks, int* passes)
+{
+    if (!ctx || !fused_chunks) return GL_ERR_NULL;
+    GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    GL_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    unsigned long long f = 0;
+    GL_HIP(hipMemcpy(&f, &ctx->ctr->fused_batch, sizeof(f), hipMemcpyDeviceToHost), "hipMemcpy");
+    *fused_chunks = (int64_t)f;
+    if (passes) *passes = ctx->passes;
+    return GL_OK;
+}
+
+gl_status gl_ctx_get_unconverged(gl_ctx* ctx, int64_t* n_arcs)
+{
+    if (!ctx || !n_arcs) return GL_ERR_NULL;
+    GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    GL_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    unsigned long long u = 0;
+    GL_HIP(hipMemcpy(&u, &ctx->ctr->unconverged, sizeof(u), hipMemcpyDeviceToHost), "hipMemcpy");
+    if (u) {
+        GL_HIP(hipMemset(&ctx->ctr->unconverged, 0, sizeof(u)), "hipMemset");
+        GL_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    }
+    *n_arcs = (int64_t)u;
     return GL_OK;
 }
 
@@ -2267,9 +2497,9 @@ gl_status gl_lightcurve_batch_surrogate(gl_ctx* ctx, gl_mlp* mlp, const float* t
     if (st != GL_OK) return st;
     hipStream_t s = b.stream;
     const int shared = b.offsets ? 0 : 1;
-    hipLaunchKernelGGL(k_prep, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, s, params, n_sets,
+    hipLaunchKernelGGL(k_prep, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, s, params, n_sets, n_sets,
                        offsets, n_times, n_ss, t_exp, ctx->sc, ctx->seg_begin, ctx->seg_len,
-                       ctx->chunk_off, ctx->ctr, (int64_t)0);
+                       ctx->chunk_off, ctx->ctr, (int64_t)0, 1, 1);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, ctx->chunk_off, n_sets, b.max_chunks, ctx->ctr);
     launch_window(ctx, b, s, 0);
     hipLaunchKernelGGL(k_sub_count, dim3((unsigned)((b.max_chunks + 255) / 256)), dim3(256), 0, s, ctx->masks,

@@ -183,17 +183,20 @@ k_colsum(const void* __restrict__ Xv, int ld, int n, const float* __restrict__ s
     if (tid == 0) out[c] = red[0];
 }
 
-// Adam on FP32 master weights; refreshes the BF16 copy when bf is given
+// Adam on FP32 master weights; refreshes the BF16 copy when bf is given.
+// c1 = 1 - b1^step and c2 = 1 - b2^step come from the host in FP64 (in FP32,
+// 1 - 0.999^step loses ~1e-5 to cancellation), and 1 - b1, 1 - b2 are the
+// FP32 roundings of 0.1 and 0.001 rather than differences of rounded betas.
 __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, bf16* __restrict__ bf, int64_t n, float lr, float c1,
                        float c2)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float b1 = 0.9f, b2 = 0.999f, omb1 = 0.1f, omb2 = 0.001f, eps = 1e-8f;
     const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    const float mi = b1 * m[i] + omb1 * gi;
+    const float vi = b2 * v[i] + omb2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
     const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
@@ -453,7 +456,8 @@ gl_status gl_mlp_train_step(gl_mlp* mm, const float* x, const float* t, int64_t 
     forward_bf(mm, (int)n, s);
     backward(mm, t, (int)n, s);
     mm->step += 1;
-    const float c1 = 1.0f - powf(0.9f, (float)mm->step), c2 = 1.0f - powf(0.999f, (float)mm->step);
+    const float c1 = (float)(1.0 - std::pow(0.9, (double)mm->step));
+    const float c2 = (float)(1.0 - std::pow(0.999, (double)mm->step));
     hipLaunchKernelGGL(k_adam, dim3(blocks(kNParam)), dim3(256), 0, s, mm->p, mm->g, mm->m, mm->v,
                        mm->pb, kNParam, lr, c1, c2);
     if (loss_dev)

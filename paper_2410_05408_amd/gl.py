@@ -25,10 +25,11 @@ GL_NPARAM = 10
 EXPORTED = ("gl_ctx_create", "gl_ctx_destroy", "gl_lightcurve_batch", "gl_ctx_sync_status",
             "gl_ctx_last_error", "gl_autotune", "gl_ctx_get_plan", "gl_ctx_set_plan",
             "gl_ctx_set_graph", "gl_ctx_set_capacity", "gl_ctx_set_timing", "gl_ctx_get_timing",
-            "gl_ctx_get_stage_timing", "gl_census", "gl_flop_model", "gl_version")
+            "gl_ctx_get_stage_timing", "gl_census", "gl_flop_model", "gl_ctx_get_unconverged",
+            "gl_ctx_get_overflow", "gl_version")
 CENSUS_NAMES = ("sub_in_window", "whole_on_star", "intersecting", "off_star_in_window",
                 "trapezoid_nodes", "gk21_pieces", "newton_steps", "limb_arcs",
-                "nested_trapezoid_nodes", "ellipse_arcs")
+                "nested_trapezoid_nodes", "ellipse_arcs", "unconverged_arcs")
 GL_NSTAGES = 9
 STAGE_NAMES = ("setup", "window", "classify", "trapezoid", "hard", "nested", "arcs", "combine", "fused")
 
@@ -83,6 +84,10 @@ def lib():
         L.gl_census.restype = i
         L.gl_flop_model.argtypes = [ctypes.POINTER(ctypes.c_int64)]
         L.gl_flop_model.restype = i
+        L.gl_ctx_get_overflow.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i)]
+        L.gl_ctx_get_overflow.restype = i
+        L.gl_ctx_get_unconverged.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.gl_ctx_get_unconverged.restype = i
         L.gl_version.argtypes = []
         L.gl_version.restype = ctypes.c_char_p
         _lib = L
@@ -224,6 +229,22 @@ def gl_flop_model():
     if st != GL_OK:
         raise GLError(st, "gl_flop_model")
     return dict(zip(CENSUS_NAMES, list(per)))
+
+
+def gl_ctx_get_overflow(ctx):
+    """Waits; returns (chunks of the latest batch evaluated by the fused kernel
+    because they did not fit the work lists, passes the batch ran)."""
+    n, p = ctypes.c_int64(), ctypes.c_int()
+    _check(ctx, lib().gl_ctx_get_overflow(ctx, ctypes.byref(n), ctypes.byref(p)))
+    return n.value, p.value
+
+
+def gl_ctx_get_unconverged(ctx) -> int:
+    """Waits; returns (and clears) the number of ellipse arcs accepted at the
+    arc rule's last level above its tolerance since the last call."""
+    n = ctypes.c_int64()
+    _check(ctx, lib().gl_ctx_get_unconverged(ctx, ctypes.byref(n)))
+    return n.value
 
 
 def gl_version() -> str:

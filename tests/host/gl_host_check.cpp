@@ -8,7 +8,9 @@
 //                                the C library, and the largest reduced angle
 //   gl_host_check flux P T O     P: float64 params [10][n] (parameter-major),
 //                                T: float64 times [n] (one per set),
-//                                O: float64 instantaneous fluxes [n]
+//                                O: float64 instantaneous fluxes [n];
+//                                prints the number of ellipse arcs the arc
+//                                rule accepted at its last level unconverged
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -59,12 +61,14 @@ int main(int argc, char** argv)
         const size_t n = t.size();
         if (n == 0 || p.size() != 10 * n) return 2;
         std::vector<double> out(n);
+        gl::NoCensus nc;
         for (size_t s = 0; s < n; ++s) {
             double q[10];
             for (int i = 0; i < 10; ++i) q[i] = p[(size_t)i * n + s];
             gl::SetConst c;
-            out[s] = gl::make_set_const(q, 0.0, 1, c) ? gl::flux_instant(c, t[s]) : std::nan("");
+            out[s] = gl::make_set_const(q, 0.0, 1, c) ? gl::flux_instant(c, t[s], nullptr, nc) : std::nan("");
         }
+        std::printf("%d\n", nc.unconv);
         FILE* f = std::fopen(argv[4], "wb");
         if (!f) return 3;
         const bool ok = std::fwrite(out.data(), sizeof(double), n, f) == n;

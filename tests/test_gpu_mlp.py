@@ -69,7 +69,48 @@ def test_gradients_match_reference(setup):
             rel = np.linalg.norm(a - r) / np.linalg.norm(r)
             cos = float(np.dot(a.ravel(), r.ravel()) / (np.linalg.norm(a) * np.linalg.norm(r)))
             say(f"  layer {li} {name}: rel {rel:.2e} cos {cos:.6f}")
-            assert rel < 3e-2 and cos > 0.999
+            # BF16 operands, FP32 accumulation: relative error per tensor below
+            # 1e-2 and cosine similarity above 0.999
+            assert rel < 1e-2 and cos > 0.999
+
+
+def test_adam_matches_reference(gpu_lib):
+    """Adam on the FP32 master weights: over several steps, each update of the
+    GPU equals the reference recurrence (FP64) fed the same GPU gradient and
+    the GPU's weights before the step, to 1e-6 relative on the weights."""
+    import torch
+    gl = gpu_lib
+    say("case: Adam steps vs FP64 reference recurrence")
+    rng = np.random.default_rng(13)
+    params = R.init(rng, 16)
+    params = [(W, rng.normal(0, 0.05, b.shape)) for W, b in params]
+    net = gl.MLP(0, max_batch=512)
+    net.set_weights(gl.pack_params(params))
+    x = rng.uniform(-1, 1, (512, 16))
+    t = np.cos(3 * x[:, 0]) * 0.2 + 0.1 * x[:, 1]
+    xd = torch.tensor(x, dtype=torch.float32, device="cuda")
+    td = torch.tensor(t, dtype=torch.float32, device="cuda")
+    lr = 2e-3
+    w_prev = net.get_weights().astype(np.float64)
+    state = R.adam_state(gl.unpack_params(w_prev))
+    try:
+        for step in range(1, 9):
+            g, _ = net.grads(xd, td)      # the gradient the step will use (deterministic)
+            net.train_step(xd, td, lr)
+            torch.cuda.synchronize()
+            w_gpu = net.get_weights().astype(np.float64)
+            ref = R.adam_step(gl.unpack_params(w_prev), gl.unpack_params(g.astype(np.float64)), state,
+                              lr=lr, step=step)
+            w_ref = np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in ref])
+            d_gpu, d_ref = w_gpu - w_prev, w_ref - w_prev
+            rel_w = np.max(np.abs(w_gpu - w_ref) / np.maximum(np.abs(w_ref), lr))
+            rel_u = np.linalg.norm(d_gpu - d_ref) / np.linalg.norm(d_ref)
+            say(f"  step {step}: max rel weight err {rel_w:.2e}, update rel err {rel_u:.2e}")
+            assert rel_w <= 1e-6
+            assert rel_u <= 1e-4
+            w_prev = w_gpu
+    finally:
+        net.close()
 
 
 def test_training_reduces_loss(gpu_lib):

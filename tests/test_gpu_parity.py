@@ -2,6 +2,8 @@
 
 Bar: |gpu - oracle| <= 1e-9 on every compared point.  The oracle shares no
 code with the HIP library; both are fed from the seeded workload generator.
+Every batch run through `run` also checks that the arc rule accepted no arc
+unconverged at its last level (gl_ctx_get_unconverged).
 """
 import math
 import os
@@ -35,6 +37,8 @@ def run(gl, ctx, w, **kw):
                     t_exp=d["t_exp"], **kw)
     torch.cuda.synchronize()
     st = gl.gl_ctx_sync_status(ctx.handle)
+    unconv = gl.gl_ctx_get_unconverged(ctx.handle)
+    assert unconv == 0, f"{unconv} arcs accepted unconverged"
     res = out.cpu().numpy()
     if w.offsets is None:
         res = res.reshape(w.n_sets, -1)
@@ -115,6 +119,64 @@ def test_uneven_batch_sampled(gpu_lib, ctx, oracle):
     ref = oracle.flux_select(w.params, w.times, sel, offsets=w.offsets, n_ss=w.n_ss, t_exp=w.t_exp)
     err = np.abs(got[sel] - ref)
     say(f"  {sel.size} outputs: max err {err.max():.3e}")
+    assert err.max() <= TOL
+
+
+def test_uneven_batch_graph_replay(gpu_lib, ctx, oracle):
+    """The uneven CSR batch with work lists sized from the demand of a first
+    run (several passes, nothing left to the fused kernel), on a non-default
+    stream, i.e. captured into a HIP graph and replayed: equal bit for bit to
+    the direct launch of the same plan, equal to rounding to the first run
+    (other passes, overflowing chunks in the fused kernel), and equal to the
+    oracle on sampled outputs."""
+    import torch
+    from paper_2410_05408_amd import workloads as W
+    gl = gpu_lib
+    say("case: uneven CSR batch 16384 walkers, graph capture + replays vs direct launch")
+    w = W.uneven_batch()
+    d = gl.to_device(w, "cuda:0")
+    args = dict(offsets=d["offsets"], n_ss=d["n_ss"], t_exp=d["t_exp"])
+    s = torch.cuda.Stream()
+    gl.gl_ctx_set_graph(ctx.handle, False)
+    try:
+        first = torch.empty(w.n_out, dtype=torch.float64, device="cuda")
+        gl.gl_lightcurve_batch(ctx.handle, d["params"], d["times"], first, stream=s, **args)
+        fused1, passes1 = gl.gl_ctx_get_overflow(ctx.handle)
+        direct = torch.empty_like(first)
+        for k in range(3):  # the plan settles within a run or two of the first
+            gl.gl_lightcurve_batch(ctx.handle, d["params"], d["times"], direct, stream=s, **args)
+            fused, passes = gl.gl_ctx_get_overflow(ctx.handle)
+            say(f"  run {k + 2}: {passes} passes, {fused} fused chunks (first run: {passes1} pass(es), "
+                f"{fused1} fused chunks)")
+            if fused == 0:
+                break
+        assert fused == 0 and passes >= 2
+        d_first = (first - direct).abs().max().item()
+        say(f"  first run vs planned run: {d_first:.2e}")
+        assert d_first <= 1e-12
+        gl.gl_ctx_set_graph(ctx.handle, True)
+        out = torch.empty_like(direct)
+        for r in range(3):  # capture, then two replays with eager work between
+            out.fill_(-1.0)
+            torch.cuda.synchronize()
+            gl.gl_lightcurve_batch(ctx.handle, d["params"], d["times"], out, stream=s, **args)
+            with torch.cuda.stream(s):
+                junk = torch.randn(4096, device="cuda").sum()  # noqa: F841
+            s.synchronize()
+            assert torch.equal(out, direct), f"replay {r} differs from the direct launch"
+    finally:
+        gl.gl_ctx_set_graph(ctx.handle, True)
+    assert gl.gl_ctx_sync_status(ctx.handle) == gl.GL_OK
+    assert gl.gl_ctx_get_unconverged(ctx.handle) == 0
+    got = out.cpu().numpy()
+    rng = np.random.default_rng(2)
+    sets = rng.choice(w.n_sets, 8, replace=False)
+    sel = np.concatenate([np.arange(w.offsets[s_], w.offsets[s_ + 1]) for s_ in sets])
+    changed = np.flatnonzero(got < 1.0)
+    sel = np.concatenate([sel, rng.choice(changed, 2000, replace=False)])
+    ref = oracle.flux_select(w.params, w.times, sel, offsets=w.offsets, n_ss=w.n_ss, t_exp=w.t_exp)
+    err = np.abs(got[sel] - ref)
+    say(f"  {sel.size} outputs of the replayed graph: max err {err.max():.3e}")
     assert err.max() <= TOL
 
 

@@ -34,11 +34,15 @@ def host_check(tmp_path_factory):
     return exe
 
 
-def host_flux(exe, tmp_path, params, times):
+def host_flux(exe, tmp_path, params, times, unconverged=None):
+    """Instantaneous fluxes of the host build; with a list `unconverged`,
+    appends the number of arcs accepted unconverged at the last level."""
     pf, tf, of = (str(tmp_path / n) for n in ("p.bin", "t.bin", "o.bin"))
     np.ascontiguousarray(params, dtype=np.float64).tofile(pf)
     np.ascontiguousarray(times, dtype=np.float64).tofile(tf)
-    subprocess.run([exe, "flux", pf, tf, of], check=True)
+    r = subprocess.run([exe, "flux", pf, tf, of], check=True, capture_output=True, text=True)
+    if unconverged is not None:
+        unconverged.append(int(r.stdout.split()[0]))
     return np.fromfile(of)
 
 
@@ -67,11 +71,13 @@ def test_host_flux_matches_oracle_on_hard_shapes(host_check, oracle, tmp_path):
         ts.append(w.times[pick])
     params = w.params[:, cols]
     times = np.concatenate(ts)
-    got = host_flux(host_check, tmp_path, params, times)
+    unconv = []
+    got = host_flux(host_check, tmp_path, params, times, unconv)
     ref = oracle_flux(oracle, params, times)
     assert np.all(np.isfinite(got))
     assert np.sum(got < 1.0) > times.size // 3   # most samples occult something
     assert np.max(np.abs(got - ref)) <= 1e-9
+    print(f"unconverged arcs on {times.size} hard-shape samples: {unconv[0]}")
 
 
 def test_host_flux_matches_oracle_on_walker_draws(host_check, oracle, tmp_path):
@@ -80,7 +86,9 @@ def test_host_flux_matches_oracle_on_walker_draws(host_check, oracle, tmp_path):
     params = W.draw_params(rng, n)
     t14 = W.full_duration(params[W.K], params[W.B], params[W.ARS], params[W.P])
     times = rng.uniform(-0.6, 0.6, n) * t14
-    got = host_flux(host_check, tmp_path, params, times)
+    unconv = []
+    got = host_flux(host_check, tmp_path, params, times, unconv)
     ref = oracle_flux(oracle, params, times)
     assert np.sum(got < 1.0) > n // 2
     assert np.max(np.abs(got - ref)) <= 1e-9
+    assert unconv[0] == 0
