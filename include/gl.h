@@ -94,6 +94,30 @@ gl_status gl_lightcurve_batch(gl_ctx *ctx, const double *params, int64_t n_sets,
                               int64_t n_times, const int32_t *n_ss,
                               const double *t_exp, double *out, void *stream);
 
+/* Allocation-free variant of gl_lightcurve_batch, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, layout and results (up
+ * to rounding) as gl_lightcurve_batch, without a context: the workspace and
+ * work lists live in one device array of 73.6 MiB inside the library, which
+ * every GPU the library runs on holds until the process ends.  The call
+ * allocates nothing, launches directly on `stream` (never a graph of its
+ * own), and works on the current HIP device; its first call on a device
+ * looks up that device's copy of the array.
+ *  Limits: n_sets <= 16384 and at most 2^18 chunks of 64 outputs (shared
+ *  grid: n_sets * ceil(n_times / 64); CSR: n_times / 64 + n_sets), else
+ *  GL_ERR_SIZE with nothing enqueued.  Work lists hold 2^19 in-window
+ *  sub-samples; chunks beyond them are evaluated by the fused kernel.
+ *  Every call on one device shares its array and clears what must start at
+ *  zero: calls that overlap on one device (other streams, other threads)
+ *  race.  Domain errors give NaN outputs as in gl_lightcurve_batch; there is
+ *  no status word to read back.
+ * Returns GL_ERR_NULL / GL_ERR_SIZE as gl_lightcurve_batch does, GL_ERR_DEVICE
+ * when the array cannot be found or a launch fails, else GL_OK once the work
+ * is enqueued. */
+gl_status gl_lightcurve_batch_noalloc(const double *params, int64_t n_sets, const double *times,
+                                      const int64_t *offsets, int64_t n_times, const int32_t *n_ss,
+                                      const double *t_exp, double *out, void *stream);
+
 /* Waits for the context's device, then returns GL_ERR_DOMAIN if any batch
  * since the last call met a domain error (and clears the flag), else GL_OK. */
 gl_status gl_ctx_sync_status(gl_ctx *ctx);

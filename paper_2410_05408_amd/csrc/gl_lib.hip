@@ -37,6 +37,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "gl.h"
@@ -1380,7 +1381,7 @@ struct gl_ctx {
     int n_cu = 256;
     int waves_per_cu = 16;  // persistent waves per CU of the list kernels
     bool use_graph = true;
-    std::string err;
+    char err[256] = {};  // last host-side error (fixed buffer: error paths allocate nothing)
     // workspace
     gl::SetConst* sc = nullptr;
     int64_t* seg_begin = nullptr;
@@ -1446,11 +1447,8 @@ namespace {
 gl_status fail(gl_ctx* ctx, gl_status st, const char* what, hipError_t e = hipSuccess)
 {
     if (ctx) {
-        ctx->err = what;
-        if (e != hipSuccess) {
-            ctx->err += ": ";
-            ctx->err += hipGetErrorString(e);
-        }
+        if (e != hipSuccess) std::snprintf(ctx->err, sizeof(ctx->err), "%s: %s", what, hipGetErrorString(e));
+        else std::snprintf(ctx->err, sizeof(ctx->err), "%s", what);
     }
     return st;
 }
@@ -1639,10 +1637,10 @@ struct Batch {
     int64_t slots = 0;       // output chunk slots of the whole batch, x 64
 };
 
-gl_status check_args(gl_ctx* ctx, Batch& b)
+// ctx may be NULL (no message is kept)
+gl_status check_batch(gl_ctx* ctx, Batch& b)
 {
-    if (!ctx) return GL_ERR_NULL;
-    ctx->err.clear();
+    if (ctx) ctx->err[0] = 0;
     if (!b.params || !b.times || !b.out) return fail(ctx, GL_ERR_NULL, "params, times and out are required");
     if (b.n_sets < 1) return fail(ctx, GL_ERR_SIZE, "n_sets must be >= 1");
     if (b.n_sets > (int64_t)INT32_MAX) return fail(ctx, GL_ERR_SIZE, "n_sets too large");
@@ -1662,6 +1660,12 @@ gl_status check_args(gl_ctx* ctx, Batch& b)
     b.ld = b.n_sets;
     b.slots = b.max_chunks * kChunk;
     return GL_OK;
+}
+
+gl_status check_args(gl_ctx* ctx, Batch& b)
+{
+    if (!ctx) return GL_ERR_NULL;
+    return check_batch(ctx, b);
 }
 
 // Window test over all chunks (fills the out-of-window outputs, chunk masks).
@@ -1972,10 +1976,8 @@ gl_status gl_ctx_sync_status(gl_ctx* ctx)
     if (status) {
         GL_HIP(hipMemset(&ctx->ctr->status, 0, sizeof(status)), "hipMemset");
         GL_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
-        ctx->err.clear();
-        if (status & 1u) ctx->err += "invalid parameter set; ";
-        if (status & 2u) ctx->err += "invalid CSR segment; ";
-        if (status & 4u) ctx->err += "non-finite time; ";
+        std::snprintf(ctx->err, sizeof(ctx->err), "%s%s%s", (status & 1u) ? "invalid parameter set; " : "",
+                      (status & 2u) ? "invalid CSR segment; " : "", (status & 4u) ? "non-finite time; " : "");
         return GL_ERR_DOMAIN;
     }
     return GL_OK;
@@ -1983,7 +1985,7 @@ gl_status gl_ctx_sync_status(gl_ctx* ctx)
 
 const char* gl_ctx_last_error(const gl_ctx* ctx)
 {
-    return ctx ? ctx->err.c_str() : "null context";
+    return ctx ? ctx->err : "null context";
 }
 
 gl_status gl_ctx_get_plan(const gl_ctx* ctx, int* waves_per_cu)
@@ -2198,6 +2200,139 @@ gl_status gl_ctx_get_unconverged(gl_ctx* ctx, int64_t* n_arcs)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free batch
+// For callers that cannot allocate device memory (code under stream capture,
+// tight serving loops): the whole exact pipeline with its workspace and work
+// lists carved out of one file-scope device array, at fixed capacities.
+// Chunks that do not fit the lists take the fused kernel, so results are those
+// of gl_lightcurve_batch up to rounding.  Every call on a device shares that
+// device's array: calls that overlap on one device race.
+namespace {
+
+constexpr int64_t kStaticSets = 16384;              // parameter sets per call
+constexpr int64_t kStaticChunks = (int64_t)1 << 18;  // 64-output chunks per call (16.7 M outputs)
+constexpr int64_t kStaticSub = (int64_t)1 << 19;     // sub-sample slots of the work lists
+constexpr int64_t kStaticWC = (int64_t)1 << 16;      // chunks with in-window outputs on the lists
+
+constexpr int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
+
+// per-shard capacities of the lists
+constexpr int64_t kSsub = kStaticSub / kShards;
+constexpr int64_t kShard = kSsub / 4;
+constexpr int64_t kSarc = 2 * kShard;
+constexpr int64_t kSwc = kStaticWC / kShards;
+constexpr int64_t kSgrp = kSsub / kChunk + kSwc;
+
+// byte offsets of the parts of the array
+constexpr int64_t kOffCtr = 0;
+constexpr int64_t kOffSc = align256(kOffCtr + (int64_t)sizeof(Counters));
+constexpr int64_t kOffSegB = align256(kOffSc + kStaticSets * (int64_t)sizeof(gl::SetConst));
+constexpr int64_t kOffSegL = align256(kOffSegB + kStaticSets * 8);
+constexpr int64_t kOffChOff = align256(kOffSegL + kStaticSets * 8);
+constexpr int64_t kOffMasks = align256(kOffChOff + (kStaticSets + 1) * 8);
+constexpr int64_t kOffChSet = align256(kOffMasks + kStaticChunks * 8);
+constexpr int64_t kOffChFb = align256(kOffChSet + kStaticChunks * 4);
+constexpr int64_t kOffFbCh = align256(kOffChFb + kStaticChunks * 4);
+constexpr int64_t kOffFsub = align256(kOffFbCh + kStaticChunks * 8);
+constexpr int64_t kOffWc = align256(kOffFsub + kShards * kSsub * 8);
+constexpr int64_t kOffGrp = align256(kOffWc + kShards * kSwc * (int64_t)sizeof(WorkChunk));
+constexpr int64_t kOffTrap = align256(kOffGrp + kShards * kSgrp * (int64_t)sizeof(Group));
+constexpr int64_t kOffHard = align256(kOffTrap + kShards * kSsub * (int64_t)sizeof(Entry));
+constexpr int64_t kOffNest = align256(kOffHard + kShards * kShard * (int64_t)sizeof(Entry));
+constexpr int64_t kOffHrec = align256(kOffNest + kShards * kShard * (int64_t)sizeof(Entry));
+constexpr int64_t kOffHfr = align256(kOffHrec + kShards * kShard * (int64_t)sizeof(HardRec));
+constexpr int64_t kOffArcs = align256(kOffHfr + kShards * kShard * (int64_t)sizeof(gl::Frame));
+constexpr int64_t kOffArcRes = align256(kOffArcs + kShards * kSarc * (int64_t)sizeof(ArcRec));
+constexpr int64_t kOffLvl = align256(kOffArcRes + kShards * kSarc * (int64_t)sizeof(gl::Sums));
+constexpr int64_t kLvlBytes = align256(kShards * kSarc * (int64_t)sizeof(ArcRef));
+constexpr int64_t kScratchBytes = kOffLvl + kLevels * kLvlBytes;
+static_assert(kScratchBytes <= ((int64_t)80 << 20), "allocation-free workspace above its stated 80 MiB");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of `scratch` and CU count, per device (found once per
+// device, with that device current, on the first call there).
+constexpr int kMaxDevices = 64;
+unsigned char* g_scratch_dev[kMaxDevices] = {};
+int g_scratch_cu[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// counters that a batch reports and that must start from zero on every call
+// (the ones of the work lists are reset by k_prep)
+__global__ void k_clear_static(Counters* __restrict__ ctr)
+{
+    ctr->status = 0u;
+    ctr->unconverged = 0ull;
+    ctr->fused_batch = 0ull;
+    ctr->total_chunks = 0ull;
+}
+
+}  // namespace
+
+extern "C" gl_status gl_lightcurve_batch_noalloc(const double* params, int64_t n_sets, const double* times,
+                                                 const int64_t* offsets, int64_t n_times, const int32_t* n_ss,
+                                                 const double* t_exp, double* out, void* stream)
+{
+    Batch b{params, n_sets, times, offsets, n_times, n_ss, t_exp, out, (hipStream_t)stream, 0};
+    gl_status st = check_batch(nullptr, b);
+    if (st != GL_OK) return st;
+    if (n_sets > kStaticSets || b.max_chunks > kStaticChunks) return GL_ERR_SIZE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GL_ERR_DEVICE;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_dev[dev]) {
+            void* ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GL_ERR_DEVICE;
+            int ncu = 0;
+            if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+                ncu = 256;
+            g_scratch_cu[dev] = ncu;
+            g_scratch_dev[dev] = (unsigned char*)ptr;
+        }
+    }
+    unsigned char* base = g_scratch_dev[dev];
+    gl_ctx c;  // on the stack, pointing into this device's array only (it owns no memory)
+    c.device = dev;
+    c.n_cu = g_scratch_cu[dev];
+    c.use_graph = false;
+    c.ctr = (Counters*)(base + kOffCtr);
+    c.sc = (gl::SetConst*)(base + kOffSc);
+    c.seg_begin = (int64_t*)(base + kOffSegB);
+    c.seg_len = (int64_t*)(base + kOffSegL);
+    c.chunk_off = (int64_t*)(base + kOffChOff);
+    c.cap_sets = kStaticSets;
+    c.masks = (unsigned long long*)(base + kOffMasks);
+    c.chunk_set = (int*)(base + kOffChSet);
+    c.cap_chunks = kStaticChunks;
+    c.chunk_fb = (int*)(base + kOffChFb);
+    Pipe& P = c.pipe;
+    P.fb_chunk = (int64_t*)(base + kOffFbCh);
+    P.fsub = (double*)(base + kOffFsub);
+    P.wc = (WorkChunk*)(base + kOffWc);
+    P.grp = (Group*)(base + kOffGrp);
+    P.trap = (Entry*)(base + kOffTrap);
+    P.hard = (Entry*)(base + kOffHard);
+    P.nest = (Entry*)(base + kOffNest);
+    P.hrec = (HardRec*)(base + kOffHrec);
+    P.hfr = (gl::Frame*)(base + kOffHfr);
+    P.arcs = (ArcRec*)(base + kOffArcs);
+    P.arc_res = (gl::Sums*)(base + kOffArcRes);
+    for (int L = 0; L < kLevels; ++L) P.lvl[L] = (ArcRef*)(base + kOffLvl + L * kLvlBytes);
+    P.scap[L_SUB] = P.scap[L_TRAP] = kSsub;
+    P.scap[L_WC] = kSwc;
+    P.scap[L_GRP] = kSgrp;
+    P.scap[L_HARD] = P.scap[L_NEST] = kShard;
+    P.scap[L_ARC] = kSarc;
+    for (int L = 0; L < kLevels; ++L) P.scap[L_LVL0 + L] = kSarc;
+    c.have_pipe = true;
+    c.pipe_chunks = kStaticChunks;
+    c.want_sub = kStaticSub;  // fixed capacities: one pass, no demand record
+    c.passes = 1;
+    hipLaunchKernelGGL(k_clear_static, dim3(1), dim3(1), 0, b.stream, c.ctr);
+    return enqueue_t<false>(&c, b);
+}
 
 // ---------------------------------------------------------------- surrogate path
 namespace {
@@ -2454,7 +2589,7 @@ gl_status gl_surrogate_samples(gl_ctx* ctx, const double* params, const double* 
                                double* scale, int32_t* bin, void* stream)
 {
     if (!ctx) return GL_ERR_NULL;
-    ctx->err.clear();
+    ctx->err[0] = 0;
     if (!params || !times || !feat || !target) return fail(ctx, GL_ERR_NULL, "params, times, feat, target");
     if (n < 1) return fail(ctx, GL_ERR_SIZE, "n >= 1");
     GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
