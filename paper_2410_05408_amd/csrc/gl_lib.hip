@@ -42,6 +42,7 @@
 
 #include "gl.h"
 #include "gl_device.h"
+#include "gl_index.h"
 
 namespace {
 
@@ -264,17 +265,6 @@ k_scan(int64_t* __restrict__ chunk_off, int64_t n, int64_t max_chunks, Counters*
 
 __global__ void k_reset_head(Counters* __restrict__ ctr) { ctr->head = 0ull; }
 
-__device__ __forceinline__ int64_t set_of_chunk(const int64_t* __restrict__ chunk_off,
-                                                int64_t n_sets, int64_t c)
-{
-    int64_t lo = 0, hi = n_sets;  // chunk_off[lo] <= c < chunk_off[hi]
-    while (hi - lo > 1) {
-        const int64_t m = (lo + hi) >> 1;
-        if (chunk_off[m] <= c) lo = m;
-        else hi = m;
-    }
-    return lo;
-}
 
 __device__ __forceinline__ int64_t uniform64(int64_t v)
 {
@@ -475,7 +465,7 @@ __device__ __forceinline__ void window_lists(Counters* ctr, const Pipe& P, int* 
 // major);
 // every time load is issued before the first test, and lane k keeps chunk k's
 // mask for one store of all of them.
-constexpr int kWinGrid = 16;
+constexpr int kWinGrid = gl::kWinGridChunks;
 
 __global__ void __launch_bounds__(64)
 k_window_grid(const double* __restrict__ times, int64_t n_times, int64_t cps,
@@ -484,11 +474,10 @@ k_window_grid(const double* __restrict__ times, int64_t n_times, int64_t cps,
               double* __restrict__ out, int lists, Pipe P, int* __restrict__ chunk_fb)
 {
     const int lane = threadIdx.x;
-    const int64_t bx = (cps + kWinGrid - 1) / kWinGrid;
-    const int64_t s = (int64_t)blockIdx.x / bx;
-    const int64_t lc0 = ((int64_t)blockIdx.x - s * bx) * kWinGrid;  // first chunk, within the set
-    const int nk = (int)std::min<int64_t>(kWinGrid, cps - lc0);
-    const int64_t ob = s * n_times;  // the set's first output
+    int64_t s, lc0;  // the set and its first chunk here
+    int nk;
+    gl::window_grid_block(blockIdx.x, cps, kWinGrid, s, lc0, nk);
+    const int64_t ob = s * n_times;  // the set's first output (its segment start)
     const gl::SetConst& S = sc[s];
     double t[kWinGrid];
 #pragma unroll
@@ -525,15 +514,15 @@ k_window_grid(const double* __restrict__ times, int64_t n_times, int64_t cps,
     }
     if (!lists || !any) return;
     const int cnt = lane < nk ? __popcll(my_mask) * S.n_ss : 0;
-    const int64_t tb = (lc0 + lane) * kChunk;
+    const gl::ChunkPos cp = gl::chunk_pos(true, ob, lc0 + lane);
     const int shard = (int)(blockIdx.x % kShards);
-    window_lists(ctr, P, chunk_fb, shard, c, cnt, my_mask, ob + tb, tb, S.n_ss, (int)s);
+    window_lists(ctr, P, chunk_fb, shard, c, cnt, my_mask, cp.out0, cp.time0, S.n_ss, (int)s);
 }
 
 // CSR segments: one wavefront per group of kWinChunks consecutive chunks (their
 // memory operations overlap), the set of the first chunk found by binary
 // search and stepped along from there.
-constexpr int kWinChunks = 4;
+constexpr int kWinChunks = gl::kWinCsrChunks;
 
 __global__ void __launch_bounds__(256)
 k_window(const double* __restrict__ times, int64_t n_sets,
@@ -549,11 +538,11 @@ k_window(const double* __restrict__ times, int64_t n_sets,
     const int64_t g = (int64_t)blockIdx.x * 4 + wv;
     const int64_t c_first = g * kWinChunks;
     int64_t s = 0;
-    if (c_first < total) s = uniform64(set_of_chunk(chunk_off, n_sets, c_first));
+    if (c_first < total) s = uniform64(gl::set_of_chunk(chunk_off, n_sets, c_first));
     // lane k (k < kWinChunks) collects chunk k's description for the lists
     int cnt_l = 0, nss_l = 0, set_l = 0;
     unsigned long long mask_l = 0ull, any = 0ull;
-    int64_t i0_l = 0;
+    int64_t i0_l = 0, t0_l = 0;
 #pragma unroll
     for (int k = 0; k < kWinChunks; ++k) {
         const int64_t c = c_first + k;
@@ -586,11 +575,13 @@ k_window(const double* __restrict__ times, int64_t n_sets,
             cnt_l = __popcll(m) * S.n_ss;
             nss_l = S.n_ss;
             set_l = (int)s;
-            i0_l = seg_begin[s] + (c - chunk_off[s]) * kChunk;
+            const gl::ChunkPos cp = gl::chunk_pos(false, seg_begin[s], c - chunk_off[s]);
+            i0_l = cp.out0;
+            t0_l = cp.time0;
         }
     }
     if (!lists || !any) return;
-    window_lists(ctr, P, chunk_fb, (int)(g % kShards), c_first + lane, cnt_l, mask_l, i0_l, i0_l, nss_l,
+    window_lists(ctr, P, chunk_fb, (int)(g % kShards), c_first + lane, cnt_l, mask_l, i0_l, t0_l, nss_l,
                  set_l);
 }
 
@@ -1288,8 +1279,8 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
             const int64_t s = uniform64(chunk_set[c]);
             const gl::SetConst S = sc[s];
             const int64_t lc = c - chunk_off[s];
-            const int64_t i0 = seg_begin[s] + lc * kChunk;
-            const int64_t tb = shared_grid ? lc * kChunk : i0;
+            const gl::ChunkPos cp = gl::chunk_pos(shared_grid != 0, seg_begin[s], lc);
+            const int64_t i0 = cp.out0, tb = cp.time0;
             // compact the chunk's working lanes
             if ((M >> lane) & 1ull) lds_idx[__popcll(M & ((1ull << lane) - 1ull))] = lane;
             __syncthreads();
@@ -2444,7 +2435,7 @@ k_sur_enum(const double* __restrict__ times, int shared_grid, const gl::SetConst
     const int64_t s = uniform64(chunk_set[c]);
     const gl::SetConst S = sc[s];
     const int64_t lc = c - chunk_off[s];
-    const int64_t tb = shared_grid ? lc * kChunk : seg_begin[s] + lc * kChunk;
+    const int64_t tb = gl::chunk_pos(shared_grid != 0, seg_begin[s], lc).time0;
     if ((M >> lane) & 1ull) lds_idx[__popcll(M & ((1ull << lane) - 1ull))] = lane;
     __syncthreads();
     const int nss = S.n_ss;
@@ -2530,7 +2521,7 @@ k_sur_reduce(const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ se
     if (!M) return;
     const int64_t s = uniform64(chunk_set[c]);
     const int nss = sc[s].n_ss;
-    const int64_t i0 = seg_begin[s] + (c - chunk_off[s]) * kChunk;
+    const int64_t i0 = gl::chunk_pos(false, seg_begin[s], c - chunk_off[s]).out0;  // outputs: same either way
     if ((M >> lane) & 1ull) lds_idx[__popcll(M & ((1ull << lane) - 1ull))] = lane;
     __syncthreads();
     const int n_in = __popcll(M);
