@@ -48,6 +48,7 @@ def cpu_baseline(w, gpu_out, target_s=10.0):
     pts = ref.size
     err = float(np.max(np.abs(gpu_out[sets] - ref)))
     return {"value": pts / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
+            "per_core": pts / dt / threads, "cpu_model": cpu_model(),
             "sample": f"first {n} walkers of the batch, all {w.times.size} outputs each "
                       f"({pts} outputs, {pts * int(w.n_ss[0])} sub-samples), {dt:.1f} s wall",
             "max_abs_err_gpu_vs_oracle": err}
@@ -154,26 +155,33 @@ def stage_flop_split(census, per):
 STAGE_LAUNCHES = {"arcs": 2}
 
 
-def rooflines(stage_ms, census, per, n_out, n_in_window_out, n_times):
+def rooflines(stage_ms, census, per, n_out, n_in_window_out, n_times, csr=False, passes=1):
     """(roofline of the dominant kernel, rooflines of the other stages).  The
     dominant kernel is the FP64 kernel with the longest launch: a stage's time
-    divided by the launches that carry its work."""
+    divided by the launches that carry its work (one per pass, the arc stage
+    two level launches per pass)."""
     flops = sum(census[k] * per[k] for k in census)
     stage_flops = stage_flop_split(census, per)
-    dom = max(FLOP_STAGES, key=lambda k: stage_ms[k] / STAGE_LAUNCHES.get(k, 1))
+    dom = max(FLOP_STAGES, key=lambda k: stage_ms[k] / (STAGE_LAUNCHES.get(k, 1) * passes))
     kern_ms = sum(v for k, v in stage_ms.items() if k != "setup")
 
     def alu_roof(stage):
         a = stage_flops[stage] / (stage_ms[stage] * 1e-3) / 1e12
+        launches = STAGE_LAUNCHES.get(stage, 1) * passes
         return {"bound": "alu", "kernel": STAGE_KERNELS[stage], "achieved": a,
                 "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": a / FP64_VECTOR_PEAK_TFLOPS,
-                "traffic": measured_traffic(STAGE_KERNELS[stage]),
-                "algorithmic_flop_per_launch": stage_flops[stage], "kernel_ms": stage_ms[stage]}
+                "traffic": measured_traffic(STAGE_KERNELS[stage]) if passes == 1 and not csr else None,
+                "algorithmic_flop_per_launch": stage_flops[stage] / launches,
+                "kernel_ms": stage_ms[stage] / launches, "launches_per_step": launches}
 
     # the fill and store phase against HBM: every output out of the transit
     # window is written once (8 B) by the window kernel, which also reads the
-    # shared time grid once
-    fill_bytes = 8 * (n_out - n_in_window_out) + 8 * n_times
+    # times (a shared grid once, CSR one time per output).  With CSR and mixed
+    # supersampling the census does not give the in-window outputs; the
+    # outputs that stay at 1.0 are then all counted as written by the window
+    # (an upper bound of its bytes, so a lower bound of its rate)
+    time_bytes = 8 * (n_out if csr else n_times)
+    fill_bytes = 8 * (n_out - n_in_window_out) + time_bytes
     fill_gbs = fill_bytes / (stage_ms["window"] * 1e-3) / 1e9
     roof = dict(alu_roof(dom), whole_pipeline={
         "algorithmic_flop": flops, "compute_ms": kern_ms,
@@ -200,6 +208,116 @@ def copy_calibration(n_bytes=1 << 30, reps=3):
                                            "dispatches": reps}}), flush=True)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_sample(w, got, n_sets=4, n_changed=2000, seed=0):
+    """Max |gpu - oracle| on the outputs of a few whole walkers and on a
+    random sample of the outputs that differ from 1 (flat output indices)."""
+    from oracle import glo
+    rng = np.random.default_rng(seed)
+    flat = got.ravel()
+    sets = rng.choice(w.n_sets, min(n_sets, w.n_sets), replace=False)
+    if w.offsets is None:
+        sel = np.concatenate([np.arange(s * w.times.size, (s + 1) * w.times.size) for s in sets])
+    else:
+        sel = np.concatenate([np.arange(w.offsets[s], w.offsets[s + 1]) for s in sets])
+    changed = np.flatnonzero(flat < 1.0)
+    sel = np.concatenate([sel, rng.choice(changed, min(n_changed, changed.size), replace=False)])
+    ref = glo.flux_select(w.params, w.times, sel, offsets=w.offsets, n_ss=w.n_ss, t_exp=w.t_exp,
+                          nthreads=glo.max_threads())
+    return {"outputs_compared": int(sel.size), "max_abs_err": float(np.max(np.abs(flat[sel] - ref)))}
+
+
+def exact_leg(gl, w, steps, warmup, trials=10, autotune=False, check_oracle=True, dev="cuda:0"):
+    """One workload through gl_lightcurve_batch on its own context: warm-up
+    (the first batch sizes the work lists from its demand), optional
+    autotuning before the graph is captured, `steps` graph-replayed steps
+    bracketed by synchronisations, `trials` single steps timed by HIP events
+    on the launch stream (median), a stage-timing pass, the work census, and
+    the rooflines of its stages."""
+    import torch
+    d = gl.to_device(w, dev)
+    out = torch.empty(w.n_out, dtype=torch.float64, device=dev)
+    ctx = gl.Context(0)
+    stream = torch.cuda.Stream()
+    args = dict(offsets=d["offsets"], n_ss=d["n_ss"], t_exp=d["t_exp"])
+
+    def step():
+        gl.gl_lightcurve_batch(ctx.handle, d["params"], d["times"], out, stream=stream, **args)
+
+    step()  # sizes the work lists from this batch's demand
+    stream.synchronize()
+    if autotune:
+        log(f"  autotune on {w.name}")
+        gl.gl_autotune(ctx.handle, d["params"], d["times"], out, stream=stream, **args)
+    for _ in range(warmup):
+        step()
+    stream.synchronize()
+    torch.cuda.synchronize()
+    if gl.gl_ctx_sync_status(ctx.handle) != gl.GL_OK:
+        raise RuntimeError(gl.gl_ctx_last_error(ctx.handle))
+    fused, passes = gl.gl_ctx_get_overflow(ctx.handle)
+
+    log(f"  timed region: {steps} steps (graph replay)")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    stream.synchronize()
+    torch.cuda.synchronize()
+    ms_per_step = 1e3 * (time.perf_counter() - t0) / steps
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(trials)]
+    for a, b in ev:
+        a.record(stream)
+        step()
+        b.record(stream)
+    stream.synchronize()
+    trial_ms = sorted(a.elapsed_time(b) for a, b in ev)
+
+    gl.gl_ctx_set_timing(ctx.handle, steps)
+    for _ in range(steps):
+        step()
+    stage_sum, n_timed = gl.gl_ctx_get_stage_timing(ctx.handle)
+    gl.gl_ctx_set_timing(ctx.handle, 0)
+    stage_ms = {k: v / n_timed for k, v in stage_sum.items()}
+    census = gl.gl_census(ctx.handle, d["params"], d["times"], out, stream=stream, **args)
+    unconv = gl.gl_ctx_get_unconverged(ctx.handle)
+    per = gl.gl_flop_model()
+    got = out.cpu().numpy()
+    in_transit = int(np.sum(got < 1.0))
+    n_in_window_out = in_transit if w.offsets is not None else census["sub_in_window"] // int(w.n_ss[0])
+    roof, roof_stages = rooflines(stage_ms, census, per, w.n_out, n_in_window_out, w.times.size,
+                                  csr=w.offsets is not None, passes=passes)
+    res = {
+        "value": w.n_out / (ms_per_step * 1e-3), "unit": "points/s", "ms_per_step": ms_per_step,
+        "trials_ms": {"n": trials, "median": float(np.median(trial_ms)), "min": trial_ms[0],
+                      "max": trial_ms[-1]},
+        "points_per_s_median": w.n_out / (float(np.median(trial_ms)) * 1e-3),
+        "sub_samples_per_s": w.n_sub / (ms_per_step * 1e-3),
+        "in_transit_points_per_s": in_transit / (ms_per_step * 1e-3),
+        "in_transit_points": in_transit, "outputs": w.n_out, "sub_samples": w.n_sub,
+        "roofline": roof, "roofline_stages": roof_stages, "stage_ms": stage_ms,
+        "pipeline_ms_direct_launch": sum(stage_ms.values()),
+        "plan": {"waves_per_cu": gl.gl_ctx_get_plan(ctx.handle), "passes": passes,
+                 "fused_chunks": fused, "autotuned": autotune},
+        "census": census, "unconverged_arcs": unconv,
+    }
+    if check_oracle:
+        res["oracle_check"] = oracle_sample(w, got)
+    ctx.close()
+    return res, got
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +325,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-extra-configs", action="store_true",
+                    help="skip the high-cadence and uneven-batch legs")
+    ap.add_argument("--only", choices=("walker_batch", "high_cadence", "uneven_batch"),
+                    help="run one exact leg only (profiling)")
     ap.add_argument("--sur-train", type=int, default=20_000_000)
     ap.add_argument("--sur-cal", type=int, default=1_000_000)
     ap.add_argument("--sur-epochs", type=int, default=4)
@@ -226,65 +348,25 @@ def main():
 
     from paper_2410_05408_amd import gl, workloads
 
-    log("building workload")
+    if args.only and args.only != "walker_batch":
+        w = workloads.by_name(args.only)
+        log(f"{args.only}: {w.n_out} outputs")
+        res, _ = exact_leg(gl, w, args.steps, args.warmup, autotune=args.only == "uneven_batch",
+                           check_oracle=False)
+        print(json.dumps({"workload": args.only, **res}), flush=True)
+        return
+
+    log("walker batch (4096 sets x 3000 shared times x 15 sub-samples)")
     w = workloads.walker_batch()
-    dev = "cuda:0"
-    d = gl.to_device(w, dev)
-    out = torch.empty(w.n_out, dtype=torch.float64, device=dev)
-    ctx = gl.Context(0)
-    stream = torch.cuda.Stream()
-
-    def step():
-        gl.gl_lightcurve_batch(ctx.handle, d["params"], d["times"], out, n_ss=d["n_ss"],
-                               t_exp=d["t_exp"], stream=stream)
-
-    log(f"warmup {args.warmup}")
-    for _ in range(args.warmup):
-        step()
-    stream.synchronize()
-    torch.cuda.synchronize()
-    if gl.gl_ctx_sync_status(ctx.handle) != gl.GL_OK:
-        raise RuntimeError(gl.gl_ctx_last_error(ctx.handle))
-
-    log(f"timed region: {args.steps} steps (graph replay)")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    stream.synchronize()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = 1e3 * elapsed / args.steps
-
-    log("stage timing pass (HIP events on the launch stream)")
-    gl.gl_ctx_set_timing(ctx.handle, args.steps)
-    for _ in range(args.steps):
-        step()
-    stage_sum, n_timed = gl.gl_ctx_get_stage_timing(ctx.handle)
-    gl.gl_ctx_set_timing(ctx.handle, 0)
-    stage_ms = {k: v / n_timed for k, v in stage_sum.items()}
-    pipe_ms = sum(stage_ms.values())
-
-    log("work census")
-    census = gl.gl_census(ctx.handle, d["params"], d["times"], out, n_ss=d["n_ss"],
-                          t_exp=d["t_exp"], stream=stream)
-    wpc = gl.gl_ctx_get_plan(ctx.handle)
-    per = gl.gl_flop_model()
-    roof, roof_stages = rooflines(stage_ms, census, per, w.n_out,
-                                  census["sub_in_window"] // int(w.n_ss[0]), int(w.times.size))
-
-    got = out.cpu().numpy().reshape(w.n_sets, -1)
-    in_transit = int(np.sum(got < 1.0))
-    value = w.n_out / (ms_per_step * 1e-3)
-
+    head, got = exact_leg(gl, w, args.steps, args.warmup, check_oracle=False)
     res = {
         "metric": "light-curve points/sec on 1 MI355X: exact (≤1e-9) vs surrogate+fallback (≤1 ppm)",
-        "value": value,
-        "unit": "points/s",
+        "value": head.pop("value"),
+        "unit": head.pop("unit"),
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -293,23 +375,34 @@ def main():
         "config": {"workload": "walker_batch", "path": "exact", "n_sets": w.n_sets,
                    "n_times": int(w.times.size), "n_ss": int(w.n_ss[0]),
                    "cadence_min": 29.4, "seed": 2},
-        "roofline": roof,
-        "roofline_stages": roof_stages,
-        "stage_ms": stage_ms,
-        "sub_samples_per_s": w.n_sub / (ms_per_step * 1e-3),
-        "in_transit_points_per_s": in_transit / (ms_per_step * 1e-3),
-        "in_transit_points": in_transit,
-        "pipeline_ms_direct_launch": pipe_ms,
-        "plan": {"waves_per_cu": wpc},
-        "census": census,
+        "roofline": head.pop("roofline"),
+        **head,
     }
-    if not args.no_surrogate:
+    if not args.no_extra_configs and not args.only:
+        res["configs"] = {}
+        log("high-cadence batch (512 sets x 65536 shared times, no supersampling)")
+        hc, _ = exact_leg(gl, workloads.high_cadence(), args.steps, args.warmup)
+        res["configs"]["high_cadence"] = {"config": {"n_sets": 512, "n_times": 65536, "n_ss": 1,
+                                                     "cadence_s": 60, "seed": 3}, **hc}
+        log("uneven CSR batch (16384 walkers, own grids of 200..20000 times, n_ss in {1,5,15})")
+        ub, _ = exact_leg(gl, workloads.uneven_batch(), max(3, args.steps // 4), args.warmup, autotune=True)
+        res["configs"]["uneven_batch"] = {"config": {"n_sets": 16384, "grid_len": "log-uniform [200, 20000]",
+                                                     "n_ss": "{1, 5, 15}", "layout": "CSR", "seed": 4}, **ub}
+        torch.cuda.synchronize()
+    if not args.no_surrogate and not args.only:
         log("surrogate leg: data, training, calibration, gated evaluation")
-        res["surrogate"] = surrogate_leg(ctx, d, out, ms_per_step, w.n_out, args)
-    if not args.no_cpu_baseline:
+        d = gl.to_device(w, "cuda:0")
+        exact_out = torch.from_numpy(got).to("cuda:0")
+        ctx = gl.Context(0)
+        res["surrogate"] = surrogate_leg(ctx, d, exact_out, res["ms_per_step"], w.n_out, args)
+        ctx.close()
+    if not args.no_cpu_baseline and not args.only:
         log("cpu baseline (oracle on the host cores)")
-        res["cpu_baseline"] = cpu_baseline(w, got)
-    ctx.close()
+        res["cpu_baseline"] = cpu_baseline(w, got.reshape(w.n_sets, -1))
+    res["paper_context"] = {
+        "note": "the paper's own code: FP32 limb snapping + Simpson's rule, OpenCL; context, not the target",
+        "per_sample_us": 0.5, "samples_per_s": 2e6, "hardware": "NVIDIA Quadro RTX 5000",
+        "precision": "fp32", "source": "Section 2.2, Code Performance"}
     print(json.dumps(res), flush=True)
 
 

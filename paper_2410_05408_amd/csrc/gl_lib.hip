@@ -28,7 +28,9 @@
 //   k_average   one wavefront per listed chunk: box average of each output's
 //               sub-samples in a fixed order (deterministic).
 //   k_compute   the fused per-lane evaluation, for chunks whose sub-samples
-//               did not fit the work-list capacities.
+//               did not fit the work-list capacities; its first wavefront
+//               records the pass's work-list demand (sizes the next batch).
+// A batch too large for one pass runs the pipeline once per range of sets.
 // Every list is appended through per-shard counters (see kShards).  The
 // launches are captured once into a HIP graph and replayed while the
 // arguments stay the same.
@@ -73,6 +75,17 @@ enum : int {
     kLists = L_LVL0 + gl::kArcMaxLevel + 1
 };
 
+// Work-list demand of the batches run on a context: `norm` is the largest
+// per-shard demand of each list seen in one pass, times that batch's number of
+// passes (what one pass over the whole batch would need); demand that a full
+// upstream list hid (a chunk without flux slots is never classified) is
+// estimated from the upstream list's ratio of demand to entries kept.
+struct Demand {
+    unsigned long long norm[kLists];
+    double sub_per_slot;           // largest ratio of in-window sub-samples to output slots of a batch
+    unsigned long long cur_sub;    // running sum over the passes of the current batch
+};
+
 struct alignas(128) LineCount {
     unsigned long long v;
     unsigned long long pad[15];
@@ -89,6 +102,7 @@ struct Counters {
     // over every batch since gl_ctx_get_unconverged last read it
     unsigned long long unconverged;
     unsigned long long fused_batch;   // chunks of the latest batch evaluated by the fused kernel
+    Demand demand;                    // kept here; k_demand stores a copy to the host's record
     // work census (census launches only): in-window sub-samples, whole-on-star,
     // intersecting, in-window but off the star, trapezoid nodes of the rigorous
     // rule, Gauss-Kronrod pieces, Newton steps, limb arcs, nested-trapezoid
@@ -1131,24 +1145,32 @@ k_average(const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_b
     }
 }
 
-// Work-list demand of the batches run on a context, in pinned host memory:
-// written by k_demand at the end of every pass, read by the host when it plans
-// the next batch (a stale read only delays a resize).  `norm` is the largest
-// per-shard demand of each list seen in one pass, times that batch's number of
-// passes (what one pass over the whole batch would need); demand that a
-// full upstream list hid (a chunk without flux slots is never classified) is
-// estimated from the upstream list's ratio of demand to entries kept.
-struct Demand {
-    unsigned long long norm[kLists];
-    double sub_per_slot;           // largest ratio of in-window sub-samples to output slots of a batch
-    unsigned long long cur_sub;    // running sum over the passes of the current batch
+// Updates the demand record at the end of every pass (in device memory) and
+// stores a copy into the host's pinned record, which the host reads when it
+// plans the next batch (a stale read only delays a resize).  Only stores
+// cross to host memory: a load from there is a bus round trip.  Run by one
+// wavefront of the pass's last launch, once the lists are complete.
+struct DemandArgs {
+    Demand* rec;  // NULL: no record
+    int first, last, passes;
+    double slots;
 };
 
-__global__ void __launch_bounds__(64)
-k_demand(Counters* __restrict__ ctr, Pipe P, Demand* __restrict__ rec, int first, int last, int passes,
-         double slots)
+__device__ void demand_update(Counters* __restrict__ ctr, const Pipe& P, const DemandArgs& a)
 {
-    const int lane = threadIdx.x;
+    Demand* __restrict__ rec = a.rec;
+    const int first = a.first, last = a.last, passes = a.passes;
+    const double slots = a.slots;
+    const int lane = threadIdx.x & 63;
+    // every list's shard count at once (lane j: shard j), then the reductions
+    unsigned long long raw[kLists];
+#pragma unroll
+    for (int l = 0; l < kLists; ++l) raw[l] = lane < kShards ? (unsigned long long)list_count(ctr, l, lane) : 0ull;
+    Demand& D = ctr->demand;
+    const unsigned long long n_fb = ctr->n_fb;
+    const unsigned long long norm_l = lane < kLists ? D.norm[lane] : 0ull;
+    const unsigned long long cur0 = D.cur_sub;
+    const double spo0 = D.sub_per_slot;
     auto wsum = [](unsigned long long v) {
         for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
         return v;
@@ -1157,23 +1179,32 @@ k_demand(Counters* __restrict__ ctr, Pipe P, Demand* __restrict__ rec, int first
         for (int d = 32; d >= 1; d >>= 1) v = std::max(v, (unsigned long long)__shfl_xor(v, d));
         return v;
     };
-    auto raw = [&](int l) { return lane < kShards ? (unsigned long long)list_count(ctr, l, lane) : 0ull; };
-    auto kept = [&](int l) { return std::min(raw(l), (unsigned long long)P.scap[l]); };
-    const unsigned long long sub_raw = wsum(raw(L_SUB)), sub_kept = wsum(kept(L_SUB));
-    const unsigned long long hard_raw = wsum(raw(L_HARD)), hard_kept = wsum(kept(L_HARD));
+    const unsigned long long sub_raw = wsum(raw[L_SUB]);
+    const unsigned long long sub_kept = wsum(std::min(raw[L_SUB], (unsigned long long)P.scap[L_SUB]));
+    const unsigned long long hard_raw = wsum(raw[L_HARD]);
+    const unsigned long long hard_kept = wsum(std::min(raw[L_HARD], (unsigned long long)P.scap[L_HARD]));
     const double r1 = (double)sub_raw / (double)std::max(1ull, sub_kept);
     const double r2 = r1 * (double)hard_raw / (double)std::max(1ull, hard_kept);
-    unsigned long long est[kLists];
+    unsigned long long mine = 0ull;  // lane l: the estimate of list l
+#pragma unroll
     for (int l = 0; l < kLists; ++l) {
         const double r = (l == L_SUB || l == L_WC || l == L_GRP) ? 1.0 : (l == L_TRAP || l == L_HARD) ? r1 : r2;
-        est[l] = (unsigned long long)((double)wmax(raw(l)) * r * passes) + 1ull;
+        const unsigned long long est = (unsigned long long)((double)wmax(raw[l]) * r * passes) + 1ull;
+        if (lane == l) mine = est;
     }
-    if (lane == 0) {
-        for (int l = 0; l < kLists; ++l) rec->norm[l] = std::max(rec->norm[l], est[l]);
-        const unsigned long long cur = (first ? 0ull : rec->cur_sub) + sub_raw;
+    if (lane < kLists) {
+        const unsigned long long nl = std::max(norm_l, mine);
+        D.norm[lane] = nl;
+        rec->norm[lane] = nl;
+    }
+    if (lane == 63) {
+        const unsigned long long cur = (first ? 0ull : cur0) + sub_raw;
+        const double spo = last ? std::max(spo0, (double)cur / slots) : spo0;
+        D.cur_sub = cur;
+        D.sub_per_slot = spo;
         rec->cur_sub = cur;
-        if (last) rec->sub_per_slot = std::max(rec->sub_per_slot, (double)cur / slots);
-        ctr->fused_batch += ctr->n_fb;
+        rec->sub_per_slot = spo;
+        ctr->fused_batch += n_fb;
     }
 }
 
@@ -1258,9 +1289,11 @@ __global__ void GL_COMPUTE_ATTR
 k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst* __restrict__ sc,
           const int64_t* __restrict__ seg_begin, const int64_t* __restrict__ chunk_off,
           Counters* __restrict__ ctr, const unsigned long long* __restrict__ masks,
-          const int* __restrict__ chunk_set, const int64_t* __restrict__ fb_chunk,
-          double* __restrict__ out)
+          const int* __restrict__ chunk_set, Pipe P, DemandArgs dem, double* __restrict__ out)
 {
+    // the pass's lists are complete here: the first wavefront records their demand
+    if (blockIdx.x == 0 && dem.rec) demand_update(ctr, P, dem);
+    const int64_t* __restrict__ fb_chunk = P.fb_chunk;
     __shared__ double lds_f[kMaxSubLds];   // sub-sample fluxes of the chunk
     __shared__ short lds_def[kMaxSubLds];  // deferred (hard) sub-samples
     __shared__ int lds_idx[kChunk];        // chunk lanes with work, compacted
@@ -1733,12 +1766,10 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
                        ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks, ctx->chunk_set,
                        ctx->chunk_fb, b.out);
     GL_STAGE_DONE();
+    const DemandArgs dem{ctx->rec_dev, b.first, b.last, ctx->passes, (double)b.slots};
     hipLaunchKernelGGL(k_compute<CENSUS>, dim3((unsigned)std::max<int64_t>(1, n_cu / 4)), dim3(64), 0, st, b.times, shared,
                        ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, ctx->masks, ctx->chunk_set,
-                       P.fb_chunk, b.out);
-    if (ctx->rec_dev)
-        hipLaunchKernelGGL(k_demand, dim3(1), dim3(64), 0, st, ctx->ctr, P, ctx->rec_dev, b.first, b.last,
-                           ctx->passes, (double)b.slots);
+                       P, dem, b.out);
     GL_STAGE_DONE();
 #undef GL_STAGE_DONE
     GL_HIP(hipGetLastError(), "kernel launch");
@@ -2120,6 +2151,8 @@ gl_status gl_ctx_set_capacity(gl_ctx* ctx, int64_t sub_samples, int64_t hard_sam
     ctx->want_arc = arcs;
     // sizing from demand starts over
     for (int l = 0; l < kLists; ++l) ctx->auto_scap[l] = 0;
+    GL_HIP(hipMemset(&ctx->ctr->demand, 0, sizeof(Demand)), "hipMemset");
+    GL_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
     std::memset(ctx->rec, 0, sizeof(Demand));
     drop_graph(ctx);
     free_pipe(ctx);
