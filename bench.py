@@ -55,47 +55,50 @@ def cpu_baseline(w, gpu_out, target_s=10.0):
 
 
 def surrogate_leg(ctx, d, exact_out, exact_ms, n_out, args):
-    """Config-5 style: train on samples from the exact kernels, calibrate,
-    evaluate the walker batch with exact fallback at 1 ppm."""
+    """Learned surrogate: trained and calibrated by the library on samples it
+    draws and evaluates with the exact kernels, then the walker batch through
+    the gate (exact fallback at 1 ppm), timed like the exact path; the same
+    gate around the zero-residual predictor (the sphere alone) beside it."""
     import torch
 
     from paper_2410_05408_amd import surrogate as S
+    cfg = S.config(n_train=args.sur_train, n_calib=args.sur_cal, epochs=args.sur_epochs)
     t0 = time.perf_counter()
-    train = S.Samples(ctx, args.sur_train, seed=5)
-    cal = S.Samples(ctx, args.sur_cal, seed=6)
+    sur = S.Surrogate.train(ctx, cfg)
     torch.cuda.synchronize()
-    t_data = time.perf_counter() - t0
-    sur = S.Surrogate(ctx, max_batch=8192, seed=0)
-    t0 = time.perf_counter()
-    hist = sur.train(train, epochs=args.sur_epochs, log=log)
     t_train = time.perf_counter() - t0
-    sur.calibrate(cal)
-    zero = S.Surrogate(ctx, max_batch=8192, zero=True)
-    zero.calibrate(cal, choose=False)
-    del train, cal
+    zero = S.Surrogate.train(ctx, S.config(n_train=args.sur_train, n_calib=args.sur_cal, epochs=args.sur_epochs,
+                                           zero_predictor=1))
+    _, table, zero_bins, counts = sur.info()
+    stream = torch.cuda.Stream()
     out = torch.empty_like(exact_out)
-    sur.lightcurve(d, out)  # warm-up
+    for _ in range(2):  # warm-up (sizes the lists)
+        sur.lightcurve(d, out, stream=stream, counts=False)
+    stream.synchronize()
+    reps = 20
     torch.cuda.synchronize()
-    reps = 3
     t0 = time.perf_counter()
     for _ in range(reps):
-        n_sub, n_fb = sur.lightcurve(d, out)
-    torch.cuda.synchronize()
+        sur.lightcurve(d, out, stream=stream, counts=False)
+    stream.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / reps
+    n_sub, n_fb = sur.lightcurve(d, out, stream=stream)
     err = float((out - exact_out).abs().max().item())
     out_z = torch.empty_like(exact_out)
-    n_sub_z, n_fb_z = zero.lightcurve(d, out_z)
-    torch.cuda.synchronize()
+    n_sub_z, n_fb_z = zero.lightcurve(d, out_z, stream=stream)
     err_z = float((out_z - exact_out).abs().max().item())
     res = {"value": n_out / (ms * 1e-3), "unit": "points/s", "ms_per_step": ms,
            "speedup_vs_exact": exact_ms / ms, "tol": 1e-6, "max_abs_err_vs_exact": err,
            "sub_samples_in_window": n_sub, "fallback_sub_samples": n_fb,
            "fallback_fraction": n_fb / max(1, n_sub),
-           "zero_residual_predictor": {"fallback_fraction": n_fb_z / max(1, n_sub_z),
+           "zero_residual_predictor": {"fallback_sub_samples": n_fb_z, "fallback_fraction": n_fb_z / max(1, n_sub_z),
                                        "max_abs_err_vs_exact": err_z},
+           "gain_vs_zero_predictor_points": (n_fb_z - n_fb) / max(1, n_sub),
+           "bins_with_network": int(np.sum((zero_bins == 0) & (table >= 0))),
+           "bins_accepting": int(np.sum(table >= 0)), "bins": int(table.size),
            "train_samples": args.sur_train, "calibration_samples": args.sur_cal,
-           "epochs": args.sur_epochs, "train_mse_first_last": [hist[0], hist[-1]],
-           "data_s": t_data, "train_s": t_train, "dtype": "bf16 mfma / f32 acc + f64"}
+           "epochs": args.sur_epochs, "train_mse_per_epoch": sur.history,
+           "train_s": t_train, "dtype": "bf16 mfma / f32 acc + f64"}
     sur.close()
     zero.close()
     return res

@@ -296,49 +296,100 @@ gl_status gl_surrogate_samples(gl_ctx *ctx, const double *params, const double *
 /* Number of calibration bins of the error-bound table. */
 int gl_surrogate_num_bins(void);
 
-/* Calibration: table[bin] = max(table[bin], |pred - target|) over the n
- * samples, the network's largest error in scaled-residual units (rounded up
- * to float; device arrays; table float[gl_surrogate_num_bins()], start from
- * zeros; `scale` is accepted for symmetry with the samples and not used).
- * A bin never seen keeps 0 and must be marked unusable by the caller
- * (negative entries always fall back). */
-gl_status gl_surrogate_bound(gl_ctx *ctx, const float *pred, const float *target, const double *scale,
-                             const int32_t *bin, int64_t n, float *table, void *stream);
+/* A trained surrogate: the network, its optimizer state, the calibrated
+ * per-bin error bound and predictor choice, and the configuration it was
+ * trained with.  Owned by the caller; used by one host thread at a time. */
+typedef struct gl_surrogate gl_surrogate;
+
+typedef struct {
+    int64_t n_train;      /* training samples drawn (default 2e7); those on the star are used */
+    int64_t n_calib;      /* calibration samples (default 1e6) */
+    int epochs;           /* passes over the training samples (default 4) */
+    int batch;            /* rows per Adam step, a multiple of 64 (default 8192) */
+    float lr, lr_final;   /* learning rate, log-linear from lr to lr_final (2e-3 -> 1e-4) */
+    double safety;        /* factor on the calibrated bound in the gate (default 4) */
+    int min_bin_count;    /* calibration samples a bin needs before the gate may accept there (200) */
+    double window;        /* sample times uniform in +-window * T14 (default 0.6) */
+    uint64_t seed;        /* training draws use seed, calibration draws seed + 1, initial weights seed + 2 */
+    int zero_predictor;   /* 1: no network, the residual is taken as 0 (the sphere alone; ablation) */
+} gl_surrogate_config;
+
+void gl_surrogate_config_default(gl_surrogate_config *cfg);
+
+/* Trains a surrogate on the context's device (synchronises `stream`):
+ *  1. draws n_train parameter sets from the walker priors (k ~ U[0.05, 0.12],
+ *     f ~ U[0, 0.9], theta ~ U[0, pi], phi ~ U[0, 2 pi), b ~ U[0, 0.9],
+ *     a/R* ~ U[100, 300], q1, q2 ~ U[0, 1], P = 500 d, t0 = 0) and one time
+ *     each uniform in +-window * T14, with a counter-based generator from the
+ *     seed; their targets come from the exact kernels (gl_surrogate_samples);
+ *  2. trains the network on the samples on the star (Adam, MSE, `epochs`
+ *     passes in a fresh permutation each);
+ *  3. calibrates on n_calib fresh draws: per bin, the largest scaled error of
+ *     the network and of the zero predictor; each bin keeps the smaller (the
+ *     sphere alone where it is smaller), and bins with fewer than
+ *     min_bin_count samples never accept.
+ * loss_history (host float[epochs], may be NULL) receives each epoch's mean
+ * squared error.  *s receives the surrogate (NULL on failure).  Errors:
+ * GL_ERR_NULL, GL_ERR_SIZE (configuration out of range, or fewer samples on
+ * the star than one batch), GL_ERR_NOMEM, GL_ERR_DEVICE. */
+gl_status gl_surrogate_train(gl_ctx *ctx, const gl_surrogate_config *cfg, gl_surrogate **s,
+                             float *loss_history, void *stream);
+
+void gl_surrogate_destroy(gl_surrogate *s);
+
+/* Host copies of a surrogate's packed FP32 parameters (params may be NULL;
+ * n_params = gl_mlp_num_params()), calibrated bound table, per-bin predictor
+ * choice (1 = sphere alone) and calibration counts (each may be NULL;
+ * n_bins = gl_surrogate_num_bins()).  Waits for the device. */
+gl_status gl_surrogate_get(const gl_surrogate *s, float *params, int64_t n_params, float *table,
+                           uint8_t *zero_bins, int32_t *counts, int n_bins);
+
+/* The configuration a surrogate was trained (or loaded) with. */
+gl_status gl_surrogate_config_of(const gl_surrogate *s, gl_surrogate_config *cfg);
+
+/* A surrogate on disk: header (magic, version 2, network widths, counts),
+ * the configuration, the packed FP32 parameters, the Adam moments and step,
+ * the bound table, the predictor choice and the calibration counts
+ * (little-endian), and a 64-bit FNV-1a hash of all of it.  Load creates the
+ * surrogate on the context's device.  Errors: GL_ERR_NULL; GL_ERR_SIZE when
+ * the file was written for other network widths or bin counts; GL_ERR_STATE
+ * when the file cannot be opened, written or read, or its magic, version,
+ * length or hash is wrong. */
+gl_status gl_surrogate_save(const gl_surrogate *s, const char *path);
+gl_status gl_surrogate_load(gl_ctx *ctx, gl_surrogate **s, const char *path);
+
+/* The same file from and into host arrays, with no device call (the file
+ * functions also run without a GPU): cfg, params, m, v float[n_params]
+ * (n_params = gl_mlp_num_params()), step, table float[n_bins], zero_bins
+ * uint8[n_bins], counts int32[n_bins] (n_bins = gl_surrogate_num_bins()).
+ * Errors as for gl_surrogate_save / gl_surrogate_load; on any error the
+ * outputs of the read are untouched. */
+gl_status gl_surrogate_file_write(const char *path, const gl_surrogate_config *cfg, const float *params,
+                                  const float *m, const float *v, int64_t step, int64_t n_params,
+                                  const float *table, const uint8_t *zero_bins, const int32_t *counts,
+                                  int n_bins);
+gl_status gl_surrogate_file_read(const char *path, gl_surrogate_config *cfg, float *params, float *m,
+                                 float *v, int64_t *step, int64_t n_params, float *table,
+                                 uint8_t *zero_bins, int32_t *counts, int n_bins);
 
 /* Light curves through the surrogate: same batch arguments and output as
- * gl_lightcurve_batch.  Every in-window sub-sample on the star gets
- * F = F_sphere + scale * network(features) when
- * safety * table[bin] * scale <= tol (its bin's calibrated error in flux
- * units, with a safety factor), and the exact kernel's value otherwise;
- * outputs are box-averaged in order.  zero_bins (device uint8 per bin, or
- * NULL) marks bins where the prediction is taken as 0, i.e. the equal-area
- * sphere alone (per-bin choice of the better calibrated predictor).
- * Synchronous (it sizes its buffers from the device); *n_sub_out and
- * *n_fallback_out (host, may be NULL) receive the number of in-window
- * sub-samples and of those computed exactly. */
-gl_status gl_lightcurve_batch_surrogate(gl_ctx *ctx, gl_mlp *mlp, const float *table,
-                                        const uint8_t *zero_bins, double safety,
-                                        double tol, const double *params, int64_t n_sets,
-                                        const double *times, const int64_t *offsets, int64_t n_times,
-                                        const int32_t *n_ss, const double *t_exp, double *out,
-                                        void *stream, int64_t *n_sub_out, int64_t *n_fallback_out);
-
-/* A trained surrogate on disk (host memory in and out; no device call, so
- * these also run without a GPU): params float[n_params] in the packed layout
- * of gl_mlp_get_weights, table float[n_bins] (the calibrated bound table of
- * gl_lightcurve_batch_surrogate), zero_bins uint8[n_bins] (may be NULL: saved
- * as all 0, or not returned).  n_params must equal gl_mlp_num_params() and
- * n_bins gl_surrogate_num_bins(), else GL_ERR_SIZE.  The file holds a fixed
- * header (magic, version, network widths, counts), the three arrays
- * (little-endian) and a 64-bit FNV-1a hash of them.  Errors: GL_ERR_NULL for
- * a NULL path, params or table; GL_ERR_SIZE when the counts or widths differ
- * from this library's (or the file's); GL_ERR_STATE when the file cannot be
- * opened, written or read, or its magic, version, length or hash is wrong
- * (the outputs are then untouched). */
-gl_status gl_surrogate_save(const char *path, const float *params, int64_t n_params, const float *table,
-                            const uint8_t *zero_bins, int n_bins);
-gl_status gl_surrogate_load(const char *path, float *params, int64_t n_params, float *table,
-                            uint8_t *zero_bins, int n_bins);
+ * gl_lightcurve_batch.  Every in-window sub-sample whose ellipse reaches the
+ * disk goes to the gate first: it is accepted when
+ * safety * table[bin] * scale <= tol (its bin's calibrated scaled error, in
+ * flux units through its own scale k^2 (1 - q), with the safety factor of the
+ * configuration); then its flux is that of the sphere of equal projected area
+ * (computed exactly, by the same kernels as the oblate flux) plus
+ * scale * network(features), or the sphere alone where the bin takes it.
+ * Every other sub-sample is computed exactly (the exact path's work lists).
+ * Outputs are box-averaged in order.  Asynchronous unless a count is
+ * requested: *n_sub_out and *n_fallback_out (host, may be NULL) then receive,
+ * after waiting for `stream`, the in-window sub-samples and those of them
+ * whose ellipse reaches the disk but that the gate rejected. */
+gl_status gl_lightcurve_batch_surrogate(gl_ctx *ctx, const gl_surrogate *s, double tol,
+                                        const double *params, int64_t n_sets, const double *times,
+                                        const int64_t *offsets, int64_t n_times, const int32_t *n_ss,
+                                        const double *t_exp, double *out, void *stream,
+                                        int64_t *n_sub_out, int64_t *n_fallback_out);
 
 /* Library version, e.g. "0.1.0". */
 const char *gl_version(void);

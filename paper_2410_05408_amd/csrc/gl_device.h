@@ -1281,6 +1281,14 @@ GL_HD SetConst sphere_of(const SetConst& s)
     return c;
 }
 
+// float -> BF16 bits, round to nearest even (the network's input rounding)
+GL_HD unsigned short f2bf_rne(float f)
+{
+    unsigned int u = __builtin_bit_cast(unsigned int, f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
 constexpr int kSurFeat = 16;   // encoded features (zero-padded)
 constexpr int kSurBinsRho = 24;
 constexpr int kSurBinsQ = 8;

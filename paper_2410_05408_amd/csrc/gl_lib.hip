@@ -41,10 +41,12 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "gl.h"
 #include "gl_device.h"
 #include "gl_index.h"
+#include "gl_internal.h"
 
 namespace {
 
@@ -70,6 +72,7 @@ enum : int {
     L_TRAP,      // whole ellipses for the trapezoid stage
     L_HARD,      // hard samples
     L_NEST,      // whole ellipses near the limb for the nested trapezoid
+    L_NET,       // surrogate batches: sub-samples whose residual the network predicts
     L_ARC,       // ellipse arcs (storage)
     L_LVL0,      // indices of the arcs at level 0 .. kArcMaxLevel of the arc rule
     kLists = L_LVL0 + gl::kArcMaxLevel + 1
@@ -102,6 +105,10 @@ struct Counters {
     // over every batch since gl_ctx_get_unconverged last read it
     unsigned long long unconverged;
     unsigned long long fused_batch;   // chunks of the latest batch evaluated by the fused kernel
+    unsigned long long sur_in;        // surrogate batches: in-window sub-samples
+    unsigned long long sur_on;        // of those, with the ellipse reaching the disk
+    unsigned long long sur_acc;       // of those, accepted by the gate
+    unsigned long long net_total;     // rows of the current pass's network batch
     Demand demand;                    // kept here; k_demand stores a copy to the host's record
     // work census (census launches only): in-window sub-samples, whole-on-star,
     // intersecting, in-window but off the star, trapezoid nodes of the rigorous
@@ -173,7 +180,28 @@ struct Pipe {
     gl::Sums* arc_res;     // indexed like `arcs`
     ArcRef* lvl[kLevels];  // arcs evaluated at level L
     int64_t scap[kLists];  // entries per shard
+    // surrogate batches (NULL otherwise): sub-samples the gate accepts are
+    // integrated for the sphere of equal projected area (their entries carry
+    // kSphBit in `set`) and, unless their bin takes the sphere alone, listed
+    // for the network, whose prediction is added to the flux slot
+    Entry* net;                  // L_NET list
+    const gl::SetConst* sph;     // sphere constants per set
+    const float* gate_table;     // calibrated scaled-error bound per bin (< 0: never accept)
+    const uint8_t* gate_zero;    // per bin: 1 = the sphere alone (no network)
+    double gate_k;               // safety / tolerance
+    uint16_t* net_x;             // dense network rows (BF16 features)
+    int64_t* net_slot;           // their flux slots
+    double* net_scale;           // their residual scales
+    float* net_y;                // network outputs
 };
+
+constexpr int kSphBit = 1 << 30;  // Entry::set flag: integrate the equal-area sphere
+
+// set constants of a list entry: the parameter set's, or its sphere's
+__device__ __forceinline__ const gl::SetConst& entry_set(const gl::SetConst* __restrict__ sc, const Pipe& P, int set)
+{
+    return (set & kSphBit) ? P.sph[set & (kSphBit - 1)] : sc[set];
+}
 
 // ---------------------------------------------------------------- kernels
 // A batch runs as one or more passes over consecutive ranges of its
@@ -185,7 +213,8 @@ __global__ void k_prep(const double* __restrict__ params, int64_t ld, int64_t n_
                        const int32_t* __restrict__ n_ss, const double* __restrict__ t_exp,
                        gl::SetConst* __restrict__ sc, int64_t* __restrict__ seg_begin,
                        int64_t* __restrict__ seg_len, int64_t* __restrict__ chunk_off,
-                       Counters* __restrict__ ctr, int64_t cps_shared, int first, int last)
+                       Counters* __restrict__ ctr, int64_t cps_shared, int first, int last,
+                       gl::SetConst* __restrict__ sph)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s == 0) {
@@ -193,6 +222,7 @@ __global__ void k_prep(const double* __restrict__ params, int64_t ld, int64_t n_
         ctr->n_fb = ctr->fb_head = 0ull;
         if (first) {
             ctr->fused_batch = 0ull;
+            ctr->sur_in = ctr->sur_on = ctr->sur_acc = 0ull;
             for (int i = 0; i < kCensus; ++i) ctr->census[i] = 0ull;
         }
     }
@@ -225,6 +255,7 @@ __global__ void k_prep(const double* __restrict__ params, int64_t ld, int64_t n_
     }
     if (flag) atomicOr(&ctr->status, flag);
     sc[s] = c;
+    if (sph) sph[s] = gl::sphere_of(c);
     seg_begin[s] = b;
     seg_len[s] = e - b;
     if (cps_shared > 0) {
@@ -604,7 +635,11 @@ k_window(const double* __restrict__ times, int64_t n_sets,
 // ellipse provably well inside (trapezoid list with its rule order, in lane
 // order: k_trap sorts its tiles by order), everything else (hard list).  A
 // group that does not fit the lists sends its chunk to the fused kernel.
-template <bool CENSUS>
+// SUR (surrogate batches): a sub-sample whose ellipse reaches the disk is
+// first put to the gate; if accepted it is classified and listed for the
+// sphere of equal projected area instead, and listed for the network unless
+// its bin takes the sphere alone.
+template <bool CENSUS, bool SUR>
 __global__ void __launch_bounds__(64)
 k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst* __restrict__ sc,
            const int64_t* __restrict__ seg_begin, const int64_t* __restrict__ chunk_off,
@@ -616,7 +651,7 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
     const int shard = (int)(blockIdx.x % kShards);
     const int64_t gcap = P.scap[L_GRP];
     const ShardMap m = shard_map(ctr, L_GRP, gcap);
-    unsigned long long c_in = 0, c_whole = 0, c_off = 0;
+    unsigned long long c_in = 0, c_whole = 0, c_off = 0, c_sur_in = 0, c_sur_on = 0, c_sur_acc = 0;
     for (int64_t gi = blockIdx.x; gi < m.total; gi += gridDim.x) {
         const Group G = P.grp[shard_slot(m, gi, gcap)];
         const int64_t c = uniform64(G.c);
@@ -635,11 +670,29 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
         const int f = f0 + lane;
         int cls = gl::kOffDisk - 1;  // no sample on this lane
         double x0 = 0.0, y0 = 0.0;
+        int eset = (int)s;           // list entries' set (kSphBit: the sphere)
+        bool to_net = false;
         if (f < cnt) {
             // f / nss for f < 4096, nss <= 64 from a float product (exact floor)
             const int o = (int)(((float)f + 0.5f) * inv_nss_f), j = f - o * nss;
             const double t = lds_t[o] + (((double)j + 0.5) * inv_nss - 0.5) * S.t_exp;
             cls = gl::centre_at(S, t, x0, y0) ? gl::easy_class(S, x0, y0) : gl::kOffDisk;
+            if (SUR) {
+                c_sur_in += 1;
+                float fe[gl::kSurFeat];
+                double scl;
+                int bin;
+                if (cls != gl::kOffDisk && gl::sur_encode(S, x0, y0, fe, scl, bin)) {
+                    c_sur_on += 1;
+                    const float tb = P.gate_table[bin];
+                    if (tb >= 0.f && P.gate_k * (double)tb * scl <= 1.0) {
+                        c_sur_acc += 1;
+                        eset = (int)s | kSphBit;
+                        to_net = P.gate_zero[bin] == 0;
+                        cls = gl::easy_class(P.sph[s], x0, y0);
+                    }
+                }
+            }
             if (cls == gl::kOffDisk) P.fsub[base + f] = 1.0;
             if (CENSUS) {
                 c_in += 1;
@@ -667,7 +720,7 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
                 fb = true;
             } else if (cls >= 0) {
                 // in lane order: the trapezoid stage sorts its tiles by rule order
-                tl[tp + lanes_below(mt)] = Entry{x0, y0, (int)s, sub | (cls << kSubBits)};
+                tl[tp + lanes_below(mt)] = Entry{x0, y0, eset, sub | (cls << kSubBits)};
             }
         }
         if (mh) {
@@ -679,16 +732,44 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
                 if (cls == gl::kHard && slot < hcap) hl[slot].set = -1;
                 fb = true;
             } else if (cls == gl::kHard) {
-                hl[slot] = Entry{x0, y0, (int)s, sub};
+                hl[slot] = Entry{x0, y0, eset, sub};
             }
         }
-        if (fb && lane == 0) to_fused(ctr, P, chunk_fb, c);
+        if (SUR) {
+            // the network's rows, in the shard of this workgroup
+            const unsigned long long mn = __ballot(to_net);
+            if (mn) {
+                const int64_t np = reserve(ctr, L_NET, shard, (unsigned long long)__popcll(mn));
+                const int64_t ncap = P.scap[L_NET];
+                if (np + __popcll(mn) > ncap) {
+                    const int64_t slot = np + lanes_below(mn);
+                    if (to_net && slot < ncap) P.net[(int64_t)shard * ncap + slot].set = -1;
+                    fb = true;
+                } else if (to_net) {
+                    P.net[(int64_t)shard * ncap + np + lanes_below(mn)] = Entry{x0, y0, (int)s, sub};
+                }
+            }
+        }
+        if (__ballot(fb) && lane == 0) to_fused(ctr, P, chunk_fb, c);
         __syncthreads();
     }
     if (CENSUS) {
         census_add(ctr, 0, c_in);
         census_add(ctr, 1, c_whole);
         census_add(ctr, 3, c_off);
+    }
+    if (SUR) {
+        unsigned long long a = c_sur_in, o = c_sur_on, b = c_sur_acc;
+        for (int d = 32; d >= 1; d >>= 1) {
+            a += __shfl_xor(a, d);
+            o += __shfl_xor(o, d);
+            b += __shfl_xor(b, d);
+        }
+        if (lane == 0) {
+            if (a) atomicAdd(&ctr->sur_in, a);
+            if (o) atomicAdd(&ctr->sur_on, o);
+            if (b) atomicAdd(&ctr->sur_acc, b);
+        }
     }
 }
 
@@ -761,7 +842,7 @@ k_trap(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
             if (pos >= n_valid) break;
             const Entry e = P.trap[lds_slot[pos]];
             const int oi = e.sub >> kSubBits, sub = e.sub & kSubMask;
-            const gl::SetConst& S = sc[e.set];
+            const gl::SetConst& S = entry_set(sc, P, e.set);
             const double sl = gl::trap_lin_inl(S, e.x0, e.y0, oi);
             P.fsub[sub] = 1.0 - gl::whole_delta(S, e.x0, e.y0, sl);
             if (CENSUS) nodes += gl::kTrapN[oi];
@@ -811,7 +892,7 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
         bool open = false, to_list = false;
         int flag = 0;
         if (valid) {
-            const gl::SetConst& S = sc[e.set];
+            const gl::SetConst& S = entry_set(sc, P, e.set);
             if (CENSUS) gl::hard_prepare<gl::Census, true>(S, e.x0, e.y0, H, ct);
             else gl::hard_prepare<gl::NoCensus, true>(S, e.x0, e.y0, H, nc);
             const int cls = gl::hard_class(H);
@@ -943,7 +1024,7 @@ k_nested(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P
         const Entry e = P.nest[slot];
         const int sub = e.sub & kSubMask;
         const bool in_place = (e.sub & kInPlace) != 0;
-        const gl::SetConst& S = sc[e.set];
+        const gl::SetConst& S = entry_set(sc, P, e.set);
         if (!in_place) {
             double sl;
             int lev;
@@ -1104,7 +1185,50 @@ k_combine(const gl::SetConst* __restrict__ sc, const Counters* __restrict__ ctr,
                     S.quad += B[k].quad;
                 }
         }
-        P.fsub[R.sub] = 1.0 - gl::sums_delta(sc[R.set], S);
+        P.fsub[R.sub] = 1.0 - gl::sums_delta(sc[R.set & (kSphBit - 1)], S);  // same law for the sphere
+    }
+}
+
+// Surrogate batches: the network's rows in list order, as dense arrays
+// (features in BF16, flux slot, residual scale) and their count.
+__global__ void __launch_bounds__(64)
+k_net_gather(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
+{
+    const int lane = threadIdx.x;
+    const int64_t scap = P.scap[L_NET];
+    const ShardMap m = shard_map(ctr, L_NET, scap);
+    if (blockIdx.x == 0 && lane == 0) ctr->net_total = (unsigned long long)m.total;
+    for (int64_t g0 = (int64_t)blockIdx.x * 64; g0 < m.total; g0 += (int64_t)gridDim.x * 64) {
+        const int64_t g = g0 + lane;
+        const int64_t slot = shard_slot(m, g < m.total ? g : 0, scap);
+        if (g >= m.total) continue;
+        const Entry e = P.net[slot];
+        float fe[gl::kSurFeat];
+        double scl = 0.0;
+        int bin = -1;
+        unsigned int w[gl::kSurFeat / 2];
+        if (e.set >= 0 && gl::sur_encode(sc[e.set], e.x0, e.y0, fe, scl, bin)) {
+            for (int i = 0; i < gl::kSurFeat / 2; ++i)
+                w[i] = (unsigned)gl::f2bf_rne(fe[2 * i]) | ((unsigned)gl::f2bf_rne(fe[2 * i + 1]) << 16);
+        } else {
+            for (int i = 0; i < gl::kSurFeat / 2; ++i) w[i] = 0u;
+            scl = 0.0;  // an emptied slot (its chunk went to the fused kernel) adds nothing
+        }
+        uint4* dst = reinterpret_cast<uint4*>(P.net_x + g * gl::kSurFeat);
+        dst[0] = uint4{w[0], w[1], w[2], w[3]};
+        dst[1] = uint4{w[4], w[5], w[6], w[7]};
+        P.net_slot[g] = e.set >= 0 ? (int64_t)e.sub : -1;
+        P.net_scale[g] = scl;
+    }
+}
+
+// flux slot += scale * predicted scaled residual
+__global__ void k_net_add(const Counters* __restrict__ ctr, Pipe P)
+{
+    const int64_t n = (int64_t)ctr->net_total;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t slot = P.net_slot[g];
+        if (slot >= 0) P.fsub[slot] += P.net_scale[g] * (double)P.net_y[g];
     }
 }
 
@@ -1188,7 +1312,7 @@ __device__ void demand_update(Counters* __restrict__ ctr, const Pipe& P, const D
     unsigned long long mine = 0ull;  // lane l: the estimate of list l
 #pragma unroll
     for (int l = 0; l < kLists; ++l) {
-        const double r = (l == L_SUB || l == L_WC || l == L_GRP) ? 1.0 : (l == L_TRAP || l == L_HARD) ? r1 : r2;
+        const double r = (l == L_SUB || l == L_WC || l == L_GRP) ? 1.0 : (l == L_TRAP || l == L_HARD || l == L_NET) ? r1 : r2;
         const unsigned long long est = (unsigned long long)((double)wmax(raw[l]) * r * passes) + 1ull;
         if (lane == l) mine = est;
     }
@@ -1408,6 +1532,7 @@ struct gl_ctx {
     char err[256] = {};  // last host-side error (fixed buffer: error paths allocate nothing)
     // workspace
     gl::SetConst* sc = nullptr;
+    gl::SetConst* sc_sph = nullptr;  // equal-area spheres (surrogate batches)
     int64_t* seg_begin = nullptr;
     int64_t* seg_len = nullptr;
     int64_t* chunk_off = nullptr;
@@ -1434,25 +1559,13 @@ struct gl_ctx {
         int passes;
     } key{};
     bool have_graph = false;
-    // surrogate path buffers (grown on demand)
-    int64_t* chunk_sub = nullptr;  // sub-sample offset per chunk (+1 total)
-    int64_t cap_sub_chunks = 0;
-    float* s_feat = nullptr;
-    float* s_pred = nullptr;
-    double* s_fsph = nullptr;
-    double* s_scale = nullptr;
-    double* s_t = nullptr;
-    double* s_F = nullptr;
-    int* s_bin = nullptr;
-    int* s_set = nullptr;
-    int64_t* s_fb = nullptr;
-    int64_t cap_sub = 0;
     // work lists of the exact path (capacities in entries; 0 = default)
     Pipe pipe{};
     bool have_pipe = false;
     int* chunk_fb = nullptr;  // per chunk: 1 = evaluated by the fused kernel
     int64_t pipe_chunks = 0;  // length of the per-chunk arrays
     int64_t want_sub = 0, want_hard = 0, want_arc = 0;
+    bool want_net = false;  // lists and buffers of surrogate batches
     // demand-driven sizing: the record k_demand writes (pinned host memory and
     // its device address), and the per-shard capacities it asked for
     Demand* rec = nullptr;
@@ -1492,24 +1605,11 @@ void drop_graph(gl_ctx* ctx)
     ctx->have_graph = false;
 }
 
-void free_sur(gl_ctx* ctx)
-{
-    void* b[] = {ctx->chunk_sub, ctx->s_feat, ctx->s_pred, ctx->s_fsph, ctx->s_scale, ctx->s_t,
-                 ctx->s_F,       ctx->s_bin,  ctx->s_set,  ctx->s_fb};
-    for (void* p : b) (void)hipFree(p);
-    ctx->chunk_sub = nullptr;
-    ctx->s_feat = ctx->s_pred = nullptr;
-    ctx->s_fsph = ctx->s_scale = ctx->s_t = ctx->s_F = nullptr;
-    ctx->s_bin = ctx->s_set = nullptr;
-    ctx->s_fb = nullptr;
-    ctx->cap_sub_chunks = ctx->cap_sub = 0;
-}
-
 void free_pipe(gl_ctx* ctx)
 {
     Pipe& P = ctx->pipe;
     void* b[] = {P.fsub, P.wc, P.grp, P.fb_chunk, P.trap, P.hard, P.nest, P.hrec, P.hfr, P.arcs,
-                 P.arc_res, ctx->chunk_fb};
+                 P.arc_res, ctx->chunk_fb, P.net, P.net_x, P.net_slot, P.net_scale, P.net_y};
     for (void* q : b) (void)hipFree(q);
     ctx->chunk_fb = nullptr;
     for (int L = 0; L < kLevels; ++L) (void)hipFree(P.lvl[L]);
@@ -1521,14 +1621,14 @@ void free_pipe(gl_ctx* ctx)
 void free_ws(gl_ctx* ctx)
 {
     free_pipe(ctx);
-    free_sur(ctx);
     (void)hipFree(ctx->sc);
+    (void)hipFree(ctx->sc_sph);
     (void)hipFree(ctx->seg_begin);
     (void)hipFree(ctx->seg_len);
     (void)hipFree(ctx->chunk_off);
     (void)hipFree(ctx->masks);
     (void)hipFree(ctx->chunk_set);
-    ctx->sc = nullptr;
+    ctx->sc = ctx->sc_sph = nullptr;
     ctx->seg_begin = ctx->seg_len = ctx->chunk_off = nullptr;
     ctx->masks = nullptr;
     ctx->chunk_set = nullptr;
@@ -1541,14 +1641,16 @@ gl_status ensure_ws(gl_ctx* ctx, int64_t n_sets, int64_t n_chunks)
         drop_graph(ctx);
         GL_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
         (void)hipFree(ctx->sc);
+        (void)hipFree(ctx->sc_sph);
         (void)hipFree(ctx->seg_begin);
         (void)hipFree(ctx->seg_len);
         (void)hipFree(ctx->chunk_off);
-        ctx->sc = nullptr;
+        ctx->sc = ctx->sc_sph = nullptr;
         ctx->seg_begin = ctx->seg_len = ctx->chunk_off = nullptr;
         ctx->cap_sets = 0;
         const int64_t cap = std::max<int64_t>(n_sets, 1024);
         if (hipMalloc(&ctx->sc, sizeof(gl::SetConst) * cap) != hipSuccess ||
+            hipMalloc(&ctx->sc_sph, sizeof(gl::SetConst) * cap) != hipSuccess ||
             hipMalloc(&ctx->seg_begin, sizeof(int64_t) * cap) != hipSuccess ||
             hipMalloc(&ctx->seg_len, sizeof(int64_t) * cap) != hipSuccess ||
             hipMalloc(&ctx->chunk_off, sizeof(int64_t) * (cap + 1)) != hipSuccess) {
@@ -1613,6 +1715,7 @@ gl_status ensure_pipe(gl_ctx* ctx, int64_t n_chunks)
     }
     sc_[L_GRP] = std::max<int64_t>(64, sc_[L_SUB] / kChunk + sc_[L_WC]);
     for (int L = 0; L < kLevels; ++L) sc_[L_LVL0 + L] = sc_[L_ARC];
+    sc_[L_NET] = ctx->want_net ? std::max(sc_[L_SUB], auto_sz ? ctx->auto_scap[L_NET] : 0) : 0;
     Pipe& P = ctx->pipe;
     bool same = ctx->have_pipe && ctx->pipe_chunks >= n_chunks;
     for (int l = 0; l < kLists && same; ++l) same = P.scap[l] == sc_[l];
@@ -1635,6 +1738,14 @@ gl_status ensure_pipe(gl_ctx* ctx, int64_t n_chunks)
               hipMalloc(&P.arc_res, sizeof(gl::Sums) * K * sc_[L_ARC]) == hipSuccess;
     for (int L = 0; L < kLevels && ok; ++L)
         ok = hipMalloc(&P.lvl[L], sizeof(ArcRef) * K * sc_[L_ARC]) == hipSuccess;
+    if (ok && sc_[L_NET] > 0) {
+        const int64_t rows = K * sc_[L_NET];
+        ok = hipMalloc(&P.net, sizeof(Entry) * rows) == hipSuccess &&
+             hipMalloc(&P.net_x, sizeof(uint16_t) * gl::kSurFeat * rows) == hipSuccess &&
+             hipMalloc(&P.net_slot, sizeof(int64_t) * rows) == hipSuccess &&
+             hipMalloc(&P.net_scale, sizeof(double) * rows) == hipSuccess &&
+             hipMalloc(&P.net_y, sizeof(float) * rows) == hipSuccess;
+    }
     if (!ok) {
         free_pipe(ctx);
         return fail(ctx, GL_ERR_NOMEM, "work-list allocation");
@@ -1659,6 +1770,11 @@ struct Batch {
     int64_t ld = 0;          // row stride of params (the whole batch's n_sets)
     int first = 1, last = 1;  // first / last pass of the batch
     int64_t slots = 0;       // output chunk slots of the whole batch, x 64
+    // surrogate batches (net != NULL): the gate and the network
+    gl_mlp* net = nullptr;
+    const float* gate_table = nullptr;
+    const uint8_t* gate_zero = nullptr;
+    double gate_k = 0.0;
 };
 
 // ctx may be NULL (no message is kept)
@@ -1693,26 +1809,25 @@ gl_status check_args(gl_ctx* ctx, Batch& b)
 }
 
 // Window test over all chunks (fills the out-of-window outputs, chunk masks).
-void launch_window(gl_ctx* ctx, const Batch& b, hipStream_t st, int lists)
+void launch_window(gl_ctx* ctx, const Batch& b, hipStream_t st, int lists, const Pipe& P)
 {
     if (!b.offsets) {
         const int64_t cps = (b.n_times + kChunk - 1) / kChunk;
         const int64_t bx = (cps + kWinGrid - 1) / kWinGrid;
         hipLaunchKernelGGL(k_window_grid, dim3((unsigned)(bx * b.n_sets)), dim3(64), 0, st, b.times,
                            b.n_times, cps, ctx->sc, ctx->ctr, ctx->masks, ctx->chunk_set, b.out, lists,
-                           ctx->pipe, ctx->chunk_fb);
+                           P, ctx->chunk_fb);
     } else {
         const int64_t groups = (b.max_chunks + kWinChunks - 1) / kWinChunks;
         hipLaunchKernelGGL(k_window, dim3((unsigned)((groups + 3) / 4)), dim3(256), 0, st, b.times,
                            b.n_sets, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off,
-                           ctx->ctr, ctx->masks, ctx->chunk_set, b.out, lists, ctx->pipe, ctx->chunk_fb);
+                           ctx->ctr, ctx->masks, ctx->chunk_set, b.out, lists, P, ctx->chunk_fb);
     }
 }
 
 template <bool CENSUS>
-void launch_arcs(gl_ctx* ctx, hipStream_t st, unsigned grid)
+void launch_arcs(gl_ctx* ctx, hipStream_t st, unsigned grid, const Pipe& P)
 {
-    const Pipe& P = ctx->pipe;
     hipLaunchKernelGGL((k_gk<0, CENSUS>), dim3(grid), dim3(64), 0, st, ctx->ctr, P);
     hipLaunchKernelGGL((k_gk<1, CENSUS>), dim3(grid), dim3(64), 0, st, ctx->ctr, P);
     // few arcs reach the deeper levels: one small launch finishes them per lane
@@ -1733,23 +1848,36 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     }
 #define GL_STAGE_DONE() \
     do { if (ev) GL_HIP(hipEventRecord(ev[e++], st), "hipEventRecord"); } while (0)
-    const Pipe& P = ctx->pipe;
+    Pipe P = ctx->pipe;
+    const bool sur = b.net != nullptr;
+    if (sur) {
+        P.sph = ctx->sc_sph;
+        P.gate_table = b.gate_table;
+        P.gate_zero = b.gate_zero;
+        P.gate_k = b.gate_k;
+    }
     const unsigned prep_blocks = (unsigned)((b.n_sets + 255) / 256);
     const int64_t cps_shared = shared ? (b.n_times + kChunk - 1) / kChunk : 0;
     hipLaunchKernelGGL(k_prep, dim3(prep_blocks), dim3(256), 0, st, b.params, b.ld, b.n_sets,
                        b.offsets, b.n_times, b.n_ss, b.t_exp, ctx->sc, ctx->seg_begin,
-                       ctx->seg_len, ctx->chunk_off, ctx->ctr, cps_shared, b.first, b.last);
+                       ctx->seg_len, ctx->chunk_off, ctx->ctr, cps_shared, b.first, b.last,
+                       sur ? ctx->sc_sph : nullptr);
     if (!shared)
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, ctx->chunk_off, b.n_sets,
                            b.max_chunks, ctx->ctr);
     GL_STAGE_DONE();
     const int64_t n_cu = ctx->n_cu;
-    launch_window(ctx, b, st, 1);
+    launch_window(ctx, b, st, 1, P);
     GL_STAGE_DONE();
     const unsigned waves = (unsigned)std::max<int64_t>(4, n_cu * ctx->waves_per_cu);
-    hipLaunchKernelGGL(k_classify<CENSUS>, dim3((unsigned)(n_cu * GL_CLASSIFY_WAVES_PER_CU)), dim3(64), 0, st, b.times, shared, ctx->sc,
-                       ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks, ctx->chunk_set,
-                       ctx->chunk_fb);
+    if (sur)
+        hipLaunchKernelGGL((k_classify<false, true>), dim3((unsigned)(n_cu * GL_CLASSIFY_WAVES_PER_CU)), dim3(64), 0, st, b.times,
+                           shared, ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks, ctx->chunk_set,
+                           ctx->chunk_fb);
+    else
+        hipLaunchKernelGGL((k_classify<CENSUS, false>), dim3((unsigned)(n_cu * GL_CLASSIFY_WAVES_PER_CU)), dim3(64), 0, st,
+                           b.times, shared, ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks,
+                           ctx->chunk_set, ctx->chunk_fb);
     GL_STAGE_DONE();
     const unsigned twaves = GL_TRAP_WAVES_PER_CU > 0 ? (unsigned)(n_cu * GL_TRAP_WAVES_PER_CU) : waves;
     hipLaunchKernelGGL(k_trap<CENSUS>, dim3((twaves + kTrapWaves - 1) / kTrapWaves), dim3(kTrapThreads), 0, st,
@@ -1759,9 +1887,15 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     GL_STAGE_DONE();
     hipLaunchKernelGGL(k_nested<CENSUS>, dim3((unsigned)(n_cu * 4)), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
     GL_STAGE_DONE();
-    launch_arcs<CENSUS>(ctx, st, GL_GK_WAVES_PER_CU > 0 ? (unsigned)(n_cu * GL_GK_WAVES_PER_CU) : waves);
+    launch_arcs<CENSUS>(ctx, st, GL_GK_WAVES_PER_CU > 0 ? (unsigned)(n_cu * GL_GK_WAVES_PER_CU) : waves, P);
     GL_STAGE_DONE();
     hipLaunchKernelGGL(k_combine, dim3((unsigned)(n_cu * 8)), dim3(256), 0, st, ctx->sc, ctx->ctr, P);
+    if (sur) {
+        // the network's residuals on the accepted sub-samples' sphere fluxes
+        hipLaunchKernelGGL(k_net_gather, dim3((unsigned)(n_cu * 8)), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
+        gl_net::infer(b.net, P.net_x, (int64_t)kShards * P.scap[L_NET], &ctx->ctr->net_total, P.net_y, st);
+        hipLaunchKernelGGL(k_net_add, dim3((unsigned)(n_cu * 8)), dim3(256), 0, st, ctx->ctr, P);
+    }
     hipLaunchKernelGGL(k_average, dim3((unsigned)(n_cu * 32)), dim3(64), 0, st, ctx->sc,
                        ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks, ctx->chunk_set,
                        ctx->chunk_fb, b.out);
@@ -2377,18 +2511,19 @@ __global__ void k_sur_samples(const double* __restrict__ params, int64_t n, cons
     for (int r = 0; r < gl::kSurFeat; ++r) fe[r] = 0.f;
     double Fo = 1.0, Fs = 1.0, sc = 0.0;
     int bin = -1;
+    gl::NoCensus nc;
     if (!gl::make_set_const(p, 0.0, 1, S) || !gl::finite_d(times[i])) {
         atomicOr(&ctr->status, 1u);
         Fo = Fs = __builtin_nan("");
     } else {
         double x0, y0;
         if (gl::centre_at(S, times[i], x0, y0) && gl::sur_encode(S, x0, y0, fe, sc, bin)) {
-            gl::NoCensus nc;
             Fo = 1.0 - gl::occulted<gl::NoCensus>(S, x0, y0, nullptr, nc);
             const gl::SetConst C = gl::sphere_of(S);
             Fs = 1.0 - gl::occulted<gl::NoCensus>(C, x0, y0, nullptr, nc);
         }
     }
+    unconverged_add(ctr, nc.unconv, false);
     for (int r = 0; r < gl::kSurFeat; ++r) feat[i * gl::kSurFeat + r] = fe[r];
     target[i] = bin >= 0 ? (float)((Fo - Fs) / sc) : 0.f;
     if (f_obl) f_obl[i] = Fo;
@@ -2397,37 +2532,63 @@ __global__ void k_sur_samples(const double* __restrict__ params, int64_t n, cons
     if (bin_out) bin_out[i] = bin;
 }
 
-// table[bin] = max over samples of the scaled error |pred - target| (rounded
-// up to float; non-negative floats order like their bit patterns, so an
-// integer max is exact)
-__global__ void k_sur_bound(const float* __restrict__ pred, const float* __restrict__ target,
-                            const double* __restrict__ scale, const int* __restrict__ bin, int64_t n,
-                            float* __restrict__ table)
+// Counter-based uniform draws in [0, 1): SplitMix64 of (seed, sample, column)
+__device__ __forceinline__ double u01(uint64_t seed, int64_t i, int col)
+{
+    uint64_t z = seed ^ ((uint64_t)i * 0xd1342543de82ef95ull) ^ ((uint64_t)(col + 1) * 0x9e3779b97f4a7c15ull);
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * 0x1.0p-53;
+}
+
+// Training / calibration draws from the walker priors: k ~ U[0.05, 0.12],
+// f ~ U[0, 0.9], theta ~ U[0, pi], phi ~ U[0, 2 pi), b ~ U[0, 0.9],
+// a/R* ~ U[100, 300], q1, q2 ~ U[0, 1], P = 500 d, t0 = 0; one time per
+// sample uniform in +-window * T14 (the transit duration of the sphere of
+// radius k, T14 = (P / pi) asin(sqrt((1 + k)^2 - b^2) / (a/R* sin i)),
+// sin i = sqrt(1 - (b / a/R*)^2)).
+__global__ void k_sur_draw(uint64_t seed, int64_t n, double window, double* __restrict__ params,
+                           double* __restrict__ times)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || bin[i] < 0) return;
-    const double ed = fabs((double)pred[i] - (double)target[i]);
-    float e = (float)ed;
-    if ((double)e < ed) e = __uint_as_float(__float_as_uint(e) + 1u);  // round up
-    atomicMax((unsigned int*)&table[bin[i]], __float_as_uint(e));
+    if (i >= n) return;
+    const double k = 0.05 + 0.07 * u01(seed, i, 0);
+    const double f = 0.9 * u01(seed, i, 1);
+    const double th = gl::kPi * u01(seed, i, 2);
+    const double ph = gl::kTwoPi * u01(seed, i, 3);
+    const double b = 0.9 * u01(seed, i, 4);
+    const double ars = 100.0 + 200.0 * u01(seed, i, 5);
+    const double q1 = u01(seed, i, 6), q2 = u01(seed, i, 7);
+    const double P = 500.0;
+    const double sini = sqrt(1.0 - (b / ars) * (b / ars));
+    const double t14 = P / gl::kPi * asin(fmin(1.0, sqrt((1.0 + k) * (1.0 + k) - b * b) / (ars * sini)));
+    const double vals[GL_NPARAM] = {k, f, th, ph, b, ars, P, 0.0, q1, q2};
+    for (int r = 0; r < GL_NPARAM; ++r) params[(int64_t)r * n + i] = vals[r];
+    times[i] = (2.0 * u01(seed, i, 8) - 1.0) * window * t14;
 }
 
-// sub-sample count per chunk: popcount(mask) * n_ss
-__global__ void k_sub_count(const unsigned long long* __restrict__ masks, const int* __restrict__ chunk_set,
-                            const gl::SetConst* __restrict__ sc, const Counters* __restrict__ ctr,
-                            int64_t* __restrict__ cnt)
+constexpr int kKeepBlock = 1024;  // rows per block of the on-star compaction
+
+// rows with bin >= 0 per block of kKeepBlock rows
+__global__ void __launch_bounds__(256) k_keep_count(const int* __restrict__ bin, int64_t n, int64_t* __restrict__ cnt)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= (int64_t)ctr->total_chunks) return;
-    const unsigned long long m = masks[c];
-    cnt[c] = m ? (int64_t)__popcll(m) * sc[chunk_set[c]].n_ss : 0;
+    __shared__ int red[4];
+    const int64_t r0 = (int64_t)blockIdx.x * kKeepBlock;
+    int c = 0;
+    for (int k = threadIdx.x; k < kKeepBlock; k += 256)
+        if (r0 + k < n && bin[r0 + k] >= 0) ++c;
+    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-// exclusive scan of a[0..n) in place with a[n] = total, one workgroup
-__global__ void __launch_bounds__(kScanThreads) k_scan_n(int64_t* __restrict__ a, const Counters* __restrict__ ctr)
+// exclusive scan of a[0..n) in place, a[n] = total (one workgroup)
+__global__ void __launch_bounds__(kScanThreads) k_excl_scan(int64_t* __restrict__ a, int64_t n)
 {
     __shared__ int64_t part[kScanThreads];
-    const int64_t n = (int64_t)ctr->total_chunks;
     const int tid = threadIdx.x;
     const int64_t per = (n + kScanThreads - 1) / kScanThreads;
     const int64_t lo = std::min<int64_t>(n, per * tid), hi = std::min<int64_t>(n, lo + per);
@@ -2450,163 +2611,155 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_n(int64_t* __restrict__ a
     if (tid == kScanThreads - 1) a[n] = part[tid];
 }
 
-// one wavefront per chunk: sub-sample times, features, sphere flux
-__global__ void __launch_bounds__(64)
-k_sur_enum(const double* __restrict__ times, int shared_grid, const gl::SetConst* __restrict__ sc,
-           const int64_t* __restrict__ seg_begin, const int64_t* __restrict__ chunk_off,
-           const Counters* __restrict__ ctr, const unsigned long long* __restrict__ masks,
-           const int* __restrict__ chunk_set, const int64_t* __restrict__ chunk_sub,
-           float* __restrict__ feat, double* __restrict__ fsph, double* __restrict__ scale,
-           double* __restrict__ tsub, double* __restrict__ F, int* __restrict__ bin, int* __restrict__ setid)
+// the rows with bin >= 0, in order, as BF16 features and FP32 targets
+__global__ void __launch_bounds__(256)
+k_keep_write(const float* __restrict__ feat, const float* __restrict__ target, const int* __restrict__ bin, int64_t n,
+             const int64_t* __restrict__ off, uint16_t* __restrict__ X, float* __restrict__ T)
 {
-    __shared__ int lds_idx[kChunk];
-    const int lane = threadIdx.x;
-    const int64_t c = uniform64((int64_t)blockIdx.x);
-    if (c >= (int64_t)ctr->total_chunks) return;
-    const unsigned long long M = (unsigned long long)uniform64((int64_t)masks[c]);
-    if (!M) return;
-    const int64_t s = uniform64(chunk_set[c]);
-    const gl::SetConst S = sc[s];
-    const int64_t lc = c - chunk_off[s];
-    const int64_t tb = gl::chunk_pos(shared_grid != 0, seg_begin[s], lc).time0;
-    if ((M >> lane) & 1ull) lds_idx[__popcll(M & ((1ull << lane) - 1ull))] = lane;
-    __syncthreads();
-    const int nss = S.n_ss;
-    const int N = __popcll(M) * nss;
-    const int64_t g0 = chunk_sub[c];
-    for (int f = lane; f < N; f += kChunk) {
-        const int o = f / nss, j = f - o * nss;
-        const double t = times[tb + lds_idx[o]] + (((double)j + 0.5) / (double)nss - 0.5) * S.t_exp;
-        const int64_t g = g0 + f;
-        float fe[gl::kSurFeat];
-        for (int r = 0; r < gl::kSurFeat; ++r) fe[r] = 0.f;
-        double sc_ = 0.0, fs = 1.0, Fv = 1.0;
-        int b = -1;
-        double x0, y0;
-        if (gl::centre_at(S, t, x0, y0) && gl::sur_encode(S, x0, y0, fe, sc_, b)) {
-            gl::NoCensus nc;
-            const gl::SetConst C = gl::sphere_of(S);
-            fs = 1.0 - gl::occulted<gl::NoCensus>(C, x0, y0, nullptr, nc);
-            Fv = __builtin_nan("");  // decided by the gate
+    __shared__ int wsum[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * kKeepBlock;
+    int64_t base = off[blockIdx.x];
+    for (int k0 = 0; k0 < kKeepBlock; k0 += 256) {
+        const int64_t r = r0 + k0 + threadIdx.x;
+        const bool keep = r < n && bin[r] >= 0;
+        const unsigned long long m = __ballot(keep);
+        if (lane == 0) wsum[wv] = __popcll(m);
+        __syncthreads();
+        int before = 0;
+        for (int w = 0; w < wv; ++w) before += wsum[w];
+        if (keep) {
+            const int64_t o = base + before + lanes_below(m);
+            for (int f = 0; f < gl::kSurFeat; ++f) X[o * gl::kSurFeat + f] = gl::f2bf_rne(feat[r * gl::kSurFeat + f]);
+            T[o] = target[r];
         }
-        for (int r = 0; r < gl::kSurFeat; ++r) feat[g * gl::kSurFeat + r] = fe[r];
-        fsph[g] = fs;
-        scale[g] = sc_;
-        tsub[g] = t;
-        F[g] = Fv;
-        bin[g] = b;
-        setid[g] = (int)s;
+        base += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
     }
 }
 
-// accept F = F_sphere + scale * pred where safety * table[bin] * scale <= tol
-// (the bin's calibrated scaled error carried to this sample's flux units),
-// otherwise queue the sub-sample for the exact kernel; in bins flagged in
-// zero_bins the prediction is 0 (the equal-area sphere alone)
-__global__ void k_sur_gate(const float* __restrict__ pred, const double* __restrict__ fsph,
-                           const double* __restrict__ scale, const int* __restrict__ bin,
-                           const float* __restrict__ table, const uint8_t* __restrict__ zero_bins,
-                           double safety, double tol, int64_t n,
-                           double* __restrict__ F, int64_t* __restrict__ fb, Counters* __restrict__ ctr)
+// Calibration: per bin the largest |prediction - target| of the network and
+// of the zero predictor (float bits of non-negative values order like
+// integers, so an integer maximum is exact and order-independent) and the
+// sample count
+__global__ void k_sur_calib(const float* __restrict__ pred, const float* __restrict__ target,
+                            const int* __restrict__ bin, int64_t n, unsigned int* __restrict__ err_net,
+                            unsigned int* __restrict__ err_zero, int* __restrict__ counts)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool queue = false;
-    if (g < n && bin[g] >= 0) {
-        const int b = bin[g];
-        const float tb = table[b];
-        const double bound = safety * (double)tb * scale[g];
-        const double pr = (zero_bins && zero_bins[b]) ? 0.0 : (double)pred[g];
-        if (tb >= 0.f && bound <= tol && gl::finite_d(bound)) F[g] = fsph[g] + scale[g] * pr;
-        else queue = true;
-    }
-    const unsigned long long qm = __ballot(queue);
-    unsigned long long base = 0;
-    const int lane = threadIdx.x & 63;
-    if (lane == 0 && qm) base = atomicAdd(&ctr->head, (unsigned long long)__popcll(qm));
-    base = (unsigned long long)uniform64((int64_t)base);
-    if (queue) fb[base + __popcll(qm & ((1ull << lane) - 1ull))] = g;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || bin[i] < 0) return;
+    auto up = [](double e) {  // rounded up to float
+        float x = (float)e;
+        if ((double)x < e) x = __uint_as_float(__float_as_uint(x) + 1u);
+        return __float_as_uint(x);
+    };
+    const double t = (double)target[i];
+    atomicMax(&err_net[bin[i]], up(fabs((double)pred[i] - t)));
+    atomicMax(&err_zero[bin[i]], up(fabs(t)));
+    atomicAdd(&counts[bin[i]], 1);
 }
 
-// exact flux for the queued sub-samples (count in ctr->head)
-__global__ void __launch_bounds__(64)
-k_sur_exact(const int64_t* __restrict__ fb, const Counters* __restrict__ ctr, const double* __restrict__ tsub,
-            const int* __restrict__ setid, const gl::SetConst* __restrict__ sc, double* __restrict__ F)
+// table[b] = the smaller calibrated bound of the two predictors (the zero
+// predictor only, with zero_only), -1 where fewer than min_count samples
+// fell; zero[b] = 1 where the sphere alone is taken
+__global__ void k_sur_finalize(const unsigned int* __restrict__ err_net, const unsigned int* __restrict__ err_zero,
+                               const int* __restrict__ counts, int min_count, int zero_only, float* __restrict__ table,
+                               uint8_t* __restrict__ zero)
 {
-    const int64_t nq = (int64_t)ctr->head;
-    for (int64_t k = (int64_t)blockIdx.x * 64 + threadIdx.x; k < nq; k += (int64_t)gridDim.x * 64) {
-        const int64_t g = fb[k];
-        F[g] = gl::flux_instant(sc[setid[g]], tsub[g]);
-    }
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= gl::kSurBins) return;
+    const float en = __uint_as_float(err_net[b]), ez = __uint_as_float(err_zero[b]);
+    const bool z = zero_only || ez <= en;
+    zero[b] = z ? 1 : 0;
+    table[b] = counts[b] >= min_count ? (z ? ez : en) : -1.0f;
 }
 
-// one wavefront per chunk: box average of each output's sub-samples in order
-__global__ void __launch_bounds__(64)
-k_sur_reduce(const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_begin,
-             const int64_t* __restrict__ chunk_off, const Counters* __restrict__ ctr,
-             const unsigned long long* __restrict__ masks, const int* __restrict__ chunk_set,
-             const int64_t* __restrict__ chunk_sub, const double* __restrict__ F, double* __restrict__ out)
+}  // namespace
+
+struct gl_surrogate {
+    int device = 0;
+    gl_mlp* net = nullptr;
+    float* table = nullptr;      // device [kSurBins]
+    uint8_t* zero = nullptr;     // device [kSurBins]
+    int32_t* counts = nullptr;   // device [kSurBins]
+    gl_surrogate_config cfg{};
+};
+
+namespace {
+
+void sur_free(gl_surrogate* s)
 {
-    __shared__ int lds_idx[kChunk];
-    const int lane = threadIdx.x;
-    const int64_t c = uniform64((int64_t)blockIdx.x);
-    if (c >= (int64_t)ctr->total_chunks) return;
-    const unsigned long long M = (unsigned long long)uniform64((int64_t)masks[c]);
-    if (!M) return;
-    const int64_t s = uniform64(chunk_set[c]);
-    const int nss = sc[s].n_ss;
-    const int64_t i0 = gl::chunk_pos(false, seg_begin[s], c - chunk_off[s]).out0;  // outputs: same either way
-    if ((M >> lane) & 1ull) lds_idx[__popcll(M & ((1ull << lane) - 1ull))] = lane;
-    __syncthreads();
-    const int n_in = __popcll(M);
-    const int64_t g0 = chunk_sub[c];
-    for (int o = lane; o < n_in; o += kChunk) {
-        double sum = 0.0;
-        for (int j = 0; j < nss; ++j) sum += F[g0 + (int64_t)o * nss + j];
-        out[i0 + lds_idx[o]] = sum / (double)nss;
-    }
+    if (!s) return;
+    (void)hipSetDevice(s->device);
+    (void)hipDeviceSynchronize();
+    gl_mlp_destroy(s->net);
+    (void)hipFree(s->table);
+    (void)hipFree(s->zero);
+    (void)hipFree(s->counts);
+    delete s;
 }
 
-gl_status ensure_sur(gl_ctx* ctx, int64_t n_chunks, int64_t n_sub)
+gl_status sur_alloc(gl_ctx* ctx, const gl_surrogate_config& cfg, gl_surrogate** out)
 {
-    if (n_chunks + 1 > ctx->cap_sub_chunks) {
-        (void)hipFree(ctx->chunk_sub);
-        ctx->chunk_sub = nullptr;
-        ctx->cap_sub_chunks = 0;
-        if (hipMalloc(&ctx->chunk_sub, sizeof(int64_t) * (n_chunks + 1)) != hipSuccess)
-            return fail(ctx, GL_ERR_NOMEM, "surrogate workspace (chunks)");
-        ctx->cap_sub_chunks = n_chunks + 1;
+    gl_surrogate* s = new (std::nothrow) gl_surrogate();
+    if (!s) return fail(ctx, GL_ERR_NOMEM, "surrogate");
+    s->device = ctx->device;
+    s->cfg = cfg;
+    gl_status st = gl_mlp_create(&s->net, ctx->device, cfg.batch);
+    if (st != GL_OK) {
+        delete s;
+        return fail(ctx, st, "surrogate network");
     }
-    if (n_sub > ctx->cap_sub) {
-        void* b[] = {ctx->s_feat, ctx->s_pred, ctx->s_fsph, ctx->s_scale, ctx->s_t,
-                     ctx->s_F,    ctx->s_bin,  ctx->s_set,  ctx->s_fb};
-        for (void* p : b) (void)hipFree(p);
-        ctx->s_feat = ctx->s_pred = nullptr;
-        ctx->s_fsph = ctx->s_scale = ctx->s_t = ctx->s_F = nullptr;
-        ctx->s_bin = ctx->s_set = nullptr;
-        ctx->s_fb = nullptr;
-        ctx->cap_sub = 0;
-        const int64_t cap = std::max<int64_t>(n_sub, 1 << 16);
-        bool ok = hipMalloc(&ctx->s_feat, sizeof(float) * gl::kSurFeat * cap) == hipSuccess &&
-                  hipMalloc(&ctx->s_pred, sizeof(float) * cap) == hipSuccess &&
-                  hipMalloc(&ctx->s_fsph, sizeof(double) * cap) == hipSuccess &&
-                  hipMalloc(&ctx->s_scale, sizeof(double) * cap) == hipSuccess &&
-                  hipMalloc(&ctx->s_t, sizeof(double) * cap) == hipSuccess &&
-                  hipMalloc(&ctx->s_F, sizeof(double) * cap) == hipSuccess &&
-                  hipMalloc(&ctx->s_bin, sizeof(int) * cap) == hipSuccess &&
-                  hipMalloc(&ctx->s_set, sizeof(int) * cap) == hipSuccess &&
-                  hipMalloc(&ctx->s_fb, sizeof(int64_t) * cap) == hipSuccess;
-        if (!ok) {
-            free_sur(ctx);
-            return fail(ctx, GL_ERR_NOMEM, "surrogate workspace (sub-samples)");
-        }
-        ctx->cap_sub = cap;
+    if (hipMalloc(&s->table, sizeof(float) * gl::kSurBins) != hipSuccess ||
+        hipMalloc(&s->zero, gl::kSurBins) != hipSuccess ||
+        hipMalloc(&s->counts, sizeof(int32_t) * gl::kSurBins) != hipSuccess) {
+        sur_free(s);
+        return fail(ctx, GL_ERR_NOMEM, "surrogate tables");
     }
+    *out = s;
     return GL_OK;
+}
+
+// He-uniform initial weights, zero biases, from a seeded host generator
+void init_weights(uint64_t seed, float* w)
+{
+    uint64_t z = seed * 0x2545f4914f6cdd1dull + 1ull;
+    auto next = [&z]() {
+        z += 0x9e3779b97f4a7c15ull;
+        uint64_t x = z;
+        x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+        x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+        return (double)((x ^ (x >> 31)) >> 11) * 0x1.0p-53;
+    };
+    const int dims[6] = {GL_MLP_DIN, GL_MLP_WIDTH, GL_MLP_WIDTH, GL_MLP_WIDTH, GL_MLP_WIDTH, 1};
+    int64_t o = 0;
+    for (int l = 0; l < 5; ++l) {
+        const int a = dims[l], b = dims[l + 1];
+        const double lim = b != 1 ? std::sqrt(6.0 / a) : std::sqrt(3.0 / a);
+        for (int64_t e = 0; e < (int64_t)a * b; ++e) w[o++] = (float)((2.0 * next() - 1.0) * lim);
+        for (int e = 0; e < b; ++e) w[o++] = 0.0f;
+    }
 }
 
 }  // namespace
 
 extern "C" {
+
+void gl_surrogate_config_default(gl_surrogate_config* c)
+{
+    if (!c) return;
+    c->n_train = 20000000;
+    c->n_calib = 1000000;
+    c->epochs = 4;
+    c->batch = 8192;
+    c->lr = 2e-3f;
+    c->lr_final = 1e-4f;
+    c->safety = 4.0;
+    c->min_bin_count = 200;
+    c->window = 0.6;
+    c->seed = 5;
+    c->zero_predictor = 0;
+}
 
 gl_status gl_surrogate_samples(gl_ctx* ctx, const double* params, const double* times, int64_t n,
                                float* feat, float* target, double* f_obl, double* f_sph,
@@ -2623,80 +2776,222 @@ gl_status gl_surrogate_samples(gl_ctx* ctx, const double* params, const double* 
     return GL_OK;
 }
 
-gl_status gl_surrogate_bound(gl_ctx* ctx, const float* pred, const float* target, const double* scale,
-                             const int32_t* bin, int64_t n, float* table, void* stream)
+int gl_surrogate_num_bins(void) { return gl::kSurBins; }
+
+gl_status gl_surrogate_train(gl_ctx* ctx, const gl_surrogate_config* cfg_in, gl_surrogate** out,
+                             float* loss_history, void* stream)
 {
-    if (!ctx) return GL_ERR_NULL;
-    if (!pred || !target || !scale || !bin || !table) return fail(ctx, GL_ERR_NULL, "null argument");
-    if (n < 1) return fail(ctx, GL_ERR_SIZE, "n >= 1");
+    if (!ctx || !cfg_in || !out) return GL_ERR_NULL;
+    *out = nullptr;
+    ctx->err[0] = 0;
+    const gl_surrogate_config cfg = *cfg_in;
+    if (cfg.batch < 64 || cfg.batch % 64 || cfg.batch > (1 << 20) || cfg.epochs < 1 || cfg.epochs > 1000 ||
+        cfg.n_train < cfg.batch || cfg.n_train > ((int64_t)1 << 31) || cfg.n_calib < 1 ||
+        cfg.n_calib > ((int64_t)1 << 31) || !(cfg.lr > 0.f) || !(cfg.lr_final > 0.f) || !(cfg.safety > 0.0) ||
+        cfg.min_bin_count < 1 || !(cfg.window > 0.0))
+        return fail(ctx, GL_ERR_SIZE, "surrogate configuration out of range");
     GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-    hipLaunchKernelGGL(k_sur_bound, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
-                       pred, target, scale, bin, n, table);
-    GL_HIP(hipGetLastError(), "kernel launch");
+    hipStream_t st = (hipStream_t)stream;
+    gl_surrogate* s = nullptr;
+    gl_status rs = sur_alloc(ctx, cfg, &s);
+    if (rs != GL_OK) return rs;
+    std::vector<float> w0(gl_mlp_num_params());
+    init_weights(cfg.seed + 2, w0.data());
+    if (cfg.zero_predictor) std::fill(w0.begin(), w0.end(), 0.0f);
+    rs = gl_mlp_set_weights(s->net, w0.data(), (int64_t)w0.size());
+    if (rs != GL_OK) {
+        sur_free(s);
+        return fail(ctx, rs, "surrogate weights");
+    }
+    // sample buffers, sized for the larger of the two draws
+    const int64_t nmax = std::max(cfg.n_train, cfg.n_calib);
+    const int64_t nblk = (nmax + kKeepBlock - 1) / kKeepBlock;
+    double *prm = nullptr, *tms = nullptr, *scl = nullptr;
+    float *feat = nullptr, *tgt = nullptr, *Tk = nullptr, *pred = nullptr, *hist = nullptr;
+    int *bin = nullptr;
+    int64_t* koff = nullptr;
+    uint16_t* Xk = nullptr;
+    unsigned int *en = nullptr, *ez = nullptr;
+    bool ok = hipMalloc(&prm, sizeof(double) * GL_NPARAM * nmax) == hipSuccess &&
+              hipMalloc(&tms, sizeof(double) * nmax) == hipSuccess &&
+              hipMalloc(&scl, sizeof(double) * nmax) == hipSuccess &&
+              hipMalloc(&feat, sizeof(float) * gl::kSurFeat * nmax) == hipSuccess &&
+              hipMalloc(&tgt, sizeof(float) * nmax) == hipSuccess && hipMalloc(&Tk, sizeof(float) * nmax) == hipSuccess &&
+              hipMalloc(&pred, sizeof(float) * nmax) == hipSuccess &&
+              hipMalloc(&hist, sizeof(float) * cfg.epochs) == hipSuccess &&
+              hipMalloc(&bin, sizeof(int) * nmax) == hipSuccess &&
+              hipMalloc(&koff, sizeof(int64_t) * (nblk + 1)) == hipSuccess &&
+              hipMalloc(&Xk, sizeof(uint16_t) * gl::kSurFeat * nmax) == hipSuccess &&
+              hipMalloc(&en, sizeof(unsigned int) * gl::kSurBins) == hipSuccess &&
+              hipMalloc(&ez, sizeof(unsigned int) * gl::kSurBins) == hipSuccess;
+    auto release = [&]() {
+        void* b[] = {prm, tms, scl, feat, tgt, Tk, pred, hist, bin, koff, Xk, en, ez};
+        for (void* q : b) (void)hipFree(q);
+    };
+    if (!ok) {
+        release();
+        sur_free(s);
+        return fail(ctx, GL_ERR_NOMEM, "surrogate sample buffers");
+    }
+    auto draw = [&](uint64_t seed, int64_t n) {
+        hipLaunchKernelGGL(k_sur_draw, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, seed, n, cfg.window, prm, tms);
+        hipLaunchKernelGGL(k_sur_samples, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, prm, n, tms, feat, tgt,
+                           nullptr, nullptr, scl, bin, ctx->ctr);
+    };
+    // training: the samples on the star, compacted in order
+    int64_t n_keep = 0;
+    if (!cfg.zero_predictor) {
+        draw(cfg.seed, cfg.n_train);
+        const int64_t nb = (cfg.n_train + kKeepBlock - 1) / kKeepBlock;
+        hipLaunchKernelGGL(k_keep_count, dim3((unsigned)nb), dim3(256), 0, st, bin, cfg.n_train, koff);
+        hipLaunchKernelGGL(k_excl_scan, dim3(1), dim3(kScanThreads), 0, st, koff, nb);
+        hipLaunchKernelGGL(k_keep_write, dim3((unsigned)nb), dim3(256), 0, st, feat, tgt, bin, cfg.n_train, koff, Xk, Tk);
+        ok = hipMemcpyAsync(&n_keep, koff + nb, sizeof(int64_t), hipMemcpyDeviceToHost, st) == hipSuccess &&
+             hipStreamSynchronize(st) == hipSuccess && hipMemsetAsync(hist, 0, sizeof(float) * cfg.epochs, st) == hipSuccess;
+        if (ok && n_keep >= cfg.batch) {
+            rs = gl_net::train_rows(s->net, Xk, Tk, n_keep, cfg.epochs, cfg.batch, cfg.lr, cfg.lr_final, cfg.seed, hist, st);
+            if (rs != GL_OK) ok = false;
+        } else if (ok) {
+            rs = GL_ERR_SIZE;
+            ok = false;
+        }
+    }
+    // calibration on fresh draws: the network's and the zero predictor's
+    // largest scaled error per bin, and the counts
+    if (ok) {
+        draw(cfg.seed + 1, cfg.n_calib);
+        const int64_t nc = cfg.n_calib;
+        ok = hipMemsetAsync(en, 0, sizeof(unsigned int) * gl::kSurBins, st) == hipSuccess &&
+             hipMemsetAsync(ez, 0, sizeof(unsigned int) * gl::kSurBins, st) == hipSuccess &&
+             hipMemsetAsync(s->counts, 0, sizeof(int32_t) * gl::kSurBins, st) == hipSuccess;
+        if (ok) {
+            rs = gl_mlp_forward(s->net, feat, nc, pred, st);
+            if (rs != GL_OK) ok = false;
+        }
+        if (ok) {
+            hipLaunchKernelGGL(k_sur_calib, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, pred, tgt, bin, nc, en, ez,
+                               s->counts);
+            hipLaunchKernelGGL(k_sur_finalize, dim3((gl::kSurBins + 255) / 256), dim3(256), 0, st, en, ez, s->counts,
+                               cfg.min_bin_count, cfg.zero_predictor, s->table, s->zero);
+            ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
+            if (ok && loss_history) {
+                if (cfg.zero_predictor) std::fill(loss_history, loss_history + cfg.epochs, 0.0f);
+                else ok = hipMemcpy(loss_history, hist, sizeof(float) * cfg.epochs, hipMemcpyDeviceToHost) == hipSuccess;
+            }
+        }
+    }
+    release();
+    if (!ok) {
+        sur_free(s);
+        return fail(ctx, rs != GL_OK ? rs : GL_ERR_DEVICE,
+                    rs == GL_ERR_SIZE ? "too few training samples on the star for one batch" : "surrogate training");
+    }
+    *out = s;
     return GL_OK;
 }
 
-int gl_surrogate_num_bins(void) { return gl::kSurBins; }
+void gl_surrogate_destroy(gl_surrogate* s) { sur_free(s); }
 
-gl_status gl_lightcurve_batch_surrogate(gl_ctx* ctx, gl_mlp* mlp, const float* table,
-                                        const uint8_t* zero_bins, double safety,
-                                        double tol, const double* params, int64_t n_sets,
-                                        const double* times, const int64_t* offsets, int64_t n_times,
-                                        const int32_t* n_ss, const double* t_exp, double* out,
-                                        void* stream, int64_t* n_sub_out, int64_t* n_fallback_out)
+gl_status gl_surrogate_get(const gl_surrogate* s, float* params, int64_t n_params, float* table, uint8_t* zero_bins,
+                           int32_t* counts, int n_bins)
+{
+    if (!s) return GL_ERR_NULL;
+    if (n_bins != gl::kSurBins || (params && n_params != gl_mlp_num_params())) return GL_ERR_SIZE;
+    if (hipSetDevice(s->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return GL_ERR_DEVICE;
+    if (params && gl_mlp_get_weights(s->net, params, n_params) != GL_OK) return GL_ERR_DEVICE;
+    if (table && hipMemcpy(table, s->table, sizeof(float) * n_bins, hipMemcpyDeviceToHost) != hipSuccess)
+        return GL_ERR_DEVICE;
+    if (zero_bins && hipMemcpy(zero_bins, s->zero, n_bins, hipMemcpyDeviceToHost) != hipSuccess) return GL_ERR_DEVICE;
+    if (counts && hipMemcpy(counts, s->counts, sizeof(int32_t) * n_bins, hipMemcpyDeviceToHost) != hipSuccess)
+        return GL_ERR_DEVICE;
+    return GL_OK;
+}
+
+gl_status gl_surrogate_config_of(const gl_surrogate* s, gl_surrogate_config* cfg)
+{
+    if (!s || !cfg) return GL_ERR_NULL;
+    *cfg = s->cfg;
+    return GL_OK;
+}
+
+gl_status gl_surrogate_save(const gl_surrogate* s, const char* path)
+{
+    if (!s || !path) return GL_ERR_NULL;
+    const int np = gl_mlp_num_params();
+    std::vector<float> w(np), m(np), v(np), table(gl::kSurBins);
+    std::vector<uint8_t> zero(gl::kSurBins);
+    std::vector<int32_t> counts(gl::kSurBins);
+    int64_t step = 0;
+    gl_status st = gl_surrogate_get(s, w.data(), np, table.data(), zero.data(), counts.data(), gl::kSurBins);
+    if (st != GL_OK) return st;
+    st = gl_net::get_state(s->net, m.data(), v.data(), &step);
+    if (st != GL_OK) return st;
+    return gl_surrogate_file_write(path, &s->cfg, w.data(), m.data(), v.data(), step, np, table.data(), zero.data(),
+                                   counts.data(), gl::kSurBins);
+}
+
+gl_status gl_surrogate_load(gl_ctx* ctx, gl_surrogate** out, const char* path)
+{
+    if (!ctx || !out || !path) return GL_ERR_NULL;
+    *out = nullptr;
+    ctx->err[0] = 0;
+    const int np = gl_mlp_num_params();
+    std::vector<float> w(np), m(np), v(np), table(gl::kSurBins);
+    std::vector<uint8_t> zero(gl::kSurBins);
+    std::vector<int32_t> counts(gl::kSurBins);
+    int64_t step = 0;
+    gl_surrogate_config cfg{};
+    gl_status st = gl_surrogate_file_read(path, &cfg, w.data(), m.data(), v.data(), &step, np, table.data(),
+                                          zero.data(), counts.data(), gl::kSurBins);
+    if (st != GL_OK) return fail(ctx, st, "surrogate file");
+    GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    gl_surrogate* s = nullptr;
+    st = sur_alloc(ctx, cfg, &s);
+    if (st != GL_OK) return st;
+    if (gl_mlp_set_weights(s->net, w.data(), np) != GL_OK || gl_net::set_state(s->net, m.data(), v.data(), step) != GL_OK ||
+        hipMemcpy(s->table, table.data(), sizeof(float) * gl::kSurBins, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->zero, zero.data(), gl::kSurBins, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->counts, counts.data(), sizeof(int32_t) * gl::kSurBins, hipMemcpyHostToDevice) != hipSuccess) {
+        sur_free(s);
+        return fail(ctx, GL_ERR_DEVICE, "surrogate upload");
+    }
+    *out = s;
+    return GL_OK;
+}
+
+gl_status gl_lightcurve_batch_surrogate(gl_ctx* ctx, const gl_surrogate* s, double tol, const double* params,
+                                        int64_t n_sets, const double* times, const int64_t* offsets, int64_t n_times,
+                                        const int32_t* n_ss, const double* t_exp, double* out, void* stream,
+                                        int64_t* n_sub_out, int64_t* n_fallback_out)
 {
     Batch b{params, n_sets, times, offsets, n_times, n_ss, t_exp, out, (hipStream_t)stream, 0};
     gl_status st = check_args(ctx, b);
     if (st != GL_OK) return st;
-    if (!mlp || !table) return fail(ctx, GL_ERR_NULL, "network and bound table are required");
+    if (!s) return fail(ctx, GL_ERR_NULL, "surrogate required");
+    if (!(tol > 0.0)) return fail(ctx, GL_ERR_SIZE, "tol > 0");
+    if (s->device != ctx->device) return fail(ctx, GL_ERR_STATE, "surrogate on another device");
     GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-    st = ensure_ws(ctx, n_sets, b.max_chunks);
-    if (st != GL_OK) return st;
-    st = ensure_sur(ctx, b.max_chunks, 0);
-    if (st != GL_OK) return st;
-    hipStream_t s = b.stream;
-    const int shared = b.offsets ? 0 : 1;
-    hipLaunchKernelGGL(k_prep, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, s, params, n_sets, n_sets,
-                       offsets, n_times, n_ss, t_exp, ctx->sc, ctx->seg_begin, ctx->seg_len,
-                       ctx->chunk_off, ctx->ctr, (int64_t)0, 1, 1);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, ctx->chunk_off, n_sets, b.max_chunks, ctx->ctr);
-    launch_window(ctx, b, s, 0);
-    hipLaunchKernelGGL(k_sub_count, dim3((unsigned)((b.max_chunks + 255) / 256)), dim3(256), 0, s, ctx->masks,
-                       ctx->chunk_set, ctx->sc, ctx->ctr, ctx->chunk_sub);
-    hipLaunchKernelGGL(k_scan_n, dim3(1), dim3(kScanThreads), 0, s, ctx->chunk_sub, ctx->ctr);
-    GL_HIP(hipGetLastError(), "kernel launch");
-    // the sub-sample count sizes the buffers: one synchronisation
-    unsigned long long total_chunks = 0;
-    GL_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
-    GL_HIP(hipMemcpy(&total_chunks, &ctx->ctr->total_chunks, sizeof(total_chunks), hipMemcpyDeviceToHost), "hipMemcpy");
-    int64_t n_sub = 0;
-    GL_HIP(hipMemcpy(&n_sub, ctx->chunk_sub + total_chunks, sizeof(n_sub), hipMemcpyDeviceToHost), "hipMemcpy");
-    st = ensure_sur(ctx, b.max_chunks, n_sub);
-    if (st != GL_OK) return st;
-    if (n_sub > 0) {
-        hipLaunchKernelGGL(k_sur_enum, dim3((unsigned)total_chunks), dim3(64), 0, s, times, shared, ctx->sc,
-                           ctx->seg_begin, ctx->chunk_off, ctx->ctr, ctx->masks, ctx->chunk_set,
-                           ctx->chunk_sub, ctx->s_feat, ctx->s_fsph, ctx->s_scale, ctx->s_t, ctx->s_F,
-                           ctx->s_bin, ctx->s_set);
-        st = gl_mlp_forward(mlp, ctx->s_feat, n_sub, ctx->s_pred, s);
-        if (st != GL_OK) return fail(ctx, st, "surrogate network forward");
-        hipLaunchKernelGGL(k_reset_head, dim3(1), dim3(1), 0, s, ctx->ctr);
-        hipLaunchKernelGGL(k_sur_gate, dim3((unsigned)((n_sub + 255) / 256)), dim3(256), 0, s, ctx->s_pred,
-                           ctx->s_fsph, ctx->s_scale, ctx->s_bin, table, zero_bins, safety, tol, n_sub, ctx->s_F,
-                           ctx->s_fb, ctx->ctr);
-        const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)ctx->n_cu * ctx->waves_per_cu,
-                                                                    (n_sub + 63) / 64));
-        hipLaunchKernelGGL(k_sur_exact, dim3((unsigned)grid), dim3(64), 0, s, ctx->s_fb, ctx->ctr, ctx->s_t,
-                           ctx->s_set, ctx->sc, ctx->s_F);
-        hipLaunchKernelGGL(k_sur_reduce, dim3((unsigned)total_chunks), dim3(64), 0, s, ctx->sc, ctx->seg_begin,
-                           ctx->chunk_off, ctx->ctr, ctx->masks, ctx->chunk_set, ctx->chunk_sub, ctx->s_F, out);
-        GL_HIP(hipGetLastError(), "kernel launch");
+    b.net = s->net;
+    b.gate_table = s->table;
+    b.gate_zero = s->zero;
+    b.gate_k = s->cfg.safety / tol;
+    if (!ctx->want_net) {
+        ctx->want_net = true;
+        drop_graph(ctx);
+        GL_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        free_pipe(ctx);
     }
-    GL_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
-    unsigned long long nfb = 0;
-    if (n_sub > 0) GL_HIP(hipMemcpy(&nfb, &ctx->ctr->head, sizeof(nfb), hipMemcpyDeviceToHost), "hipMemcpy");
-    if (n_sub_out) *n_sub_out = n_sub;
-    if (n_fallback_out) *n_fallback_out = (int64_t)nfb;
+    st = prepare_batch(ctx, b);
+    if (st != GL_OK) return st;
+    st = run_batch(ctx, b, false);
+    if (st != GL_OK) return st;
+    if (n_sub_out || n_fallback_out) {
+        unsigned long long c[3] = {0ull, 0ull, 0ull};  // in window, reaching the disk, accepted
+        GL_HIP(hipStreamSynchronize(b.stream), "hipStreamSynchronize");
+        GL_HIP(hipMemcpy(c, &ctx->ctr->sur_in, sizeof(c), hipMemcpyDeviceToHost), "hipMemcpy");
+        if (n_sub_out) *n_sub_out = (int64_t)c[0];
+        if (n_fallback_out) *n_fallback_out = (int64_t)(c[1] - c[2]);
+    }
     return GL_OK;
 }
 

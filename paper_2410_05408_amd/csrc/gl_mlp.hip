@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "gl.h"
+#include "gl_internal.h"
 
 namespace {
 
@@ -300,6 +301,26 @@ __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float
     const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
     w[i] = wi;
     if (bf) bf[i] = f2bf(wi);
+}
+
+// Training batch: rows perm(step * batch + i) of X / T, where perm(j) =
+// (a j + c) mod n for a coprime to n (a fresh permutation every epoch).
+__global__ void k_gather_rows(const bf16* __restrict__ Xall, const float* __restrict__ Tall, int64_t n,
+                              uint64_t a, uint64_t c, int64_t j0, int batch, bf16* __restrict__ X,
+                              float* __restrict__ T)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)batch * D_IN) return;
+    const int64_t i = e / D_IN, f = e % D_IN;
+    const uint64_t r = ((unsigned __int128)a * (uint64_t)(j0 + i) + c) % (uint64_t)n;
+    X[e] = Xall[r * D_IN + f];
+    if (f == 0) T[i] = Tall[r];
+}
+
+// hist[0] += loss[0] / n (one thread: the epoch's mean squared error)
+__global__ void k_add_loss(const float* __restrict__ loss, float inv_n, float* __restrict__ hist)
+{
+    hist[0] += loss[0] * inv_n;
 }
 
 __global__ void k_refresh_bf16(const float* __restrict__ w, bf16* __restrict__ bf, int64_t n)
@@ -605,7 +626,7 @@ gl_status gl_mlp_create(gl_mlp** out, int device, int max_batch)
     }
     al((void**)&mm->dA, sizeof(bf16) * (size_t)max_batch * W);
     al((void**)&mm->dB, sizeof(bf16) * (size_t)max_batch * W);
-    al((void**)&mm->y, sizeof(float) * max_batch);
+    al((void**)&mm->y, sizeof(float) * 2 * (size_t)max_batch);  // outputs, then a batch's targets
     al((void**)&mm->dy, sizeof(float) * max_batch);
     al((void**)&mm->sq, sizeof(float) * max_batch);
     al((void**)&mm->lossbuf, sizeof(float) * 4);
@@ -736,3 +757,92 @@ gl_status gl_mlp_train_step(gl_mlp* mm, const float* x, const float* t, int64_t 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- internal calls
+namespace gl_net {
+
+namespace {
+uint64_t mix64(uint64_t z)
+{
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+uint64_t gcd64(uint64_t a, uint64_t b)
+{
+    while (b) {
+        const uint64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+}  // namespace
+
+int max_batch(const gl_mlp* mm) { return mm->max_batch; }
+
+gl_status train_rows(gl_mlp* mm, const uint16_t* X, const float* T, int64_t n, int epochs, int batch,
+                     float lr, float lr_final, uint64_t seed, float* hist_dev, hipStream_t s)
+{
+    if (!mm || !X || !T) return GL_ERR_NULL;
+    if (batch < 64 || batch > mm->max_batch || n < batch || epochs < 1) return mfail(mm, GL_ERR_SIZE, "training sizes");
+    GM_HIP(hipSetDevice(mm->device), "hipSetDevice");
+    const int64_t per_epoch = n / batch;
+    const int64_t steps = per_epoch * epochs;
+    int64_t step = 0;
+    for (int ep = 0; ep < epochs; ++ep) {
+        // a fresh permutation j -> (a j + c) mod n
+        uint64_t a = (mix64(seed * 1315423911ull + (uint64_t)ep) % (uint64_t)n) | 1ull;
+        while (gcd64(a, (uint64_t)n) != 1ull) a += 2;
+        const uint64_t c = mix64(seed + 7919ull * (uint64_t)(ep + 1)) % (uint64_t)n;
+        for (int64_t b = 0; b < per_epoch; ++b, ++step) {
+            hipLaunchKernelGGL(k_gather_rows, dim3(blocks((int64_t)batch * D_IN)), dim3(256), 0, s, (const bf16*)X, T, n,
+                               a % (uint64_t)n, c, b * batch, batch, mm->X, mm->y + mm->max_batch);
+            const float lr_s = (float)((double)lr * std::pow((double)lr_final / (double)lr,
+                                                             (double)step / (double)std::max<int64_t>(1, steps - 1)));
+            forward_bf(mm, batch, s);
+            backward(mm, mm->y + mm->max_batch, batch, s);
+            mm->step += 1;
+            const float c1 = (float)(1.0 - std::pow(0.9, (double)mm->step));
+            const float c2 = (float)(1.0 - std::pow(0.999, (double)mm->step));
+            hipLaunchKernelGGL(k_adam, dim3(blocks(kNParam)), dim3(256), 0, s, mm->p, mm->g, mm->m, mm->v, mm->pb,
+                               kNParam, lr_s, c1, c2);
+            if (hist_dev)
+                hipLaunchKernelGGL(k_add_loss, dim3(1), dim3(1), 0, s, mm->lossbuf, 1.0f / (float)(per_epoch * batch),
+                                   hist_dev + ep);
+        }
+    }
+    mm->wt_stale = true;
+    GM_HIP(hipGetLastError(), "kernel launch");
+    return GL_OK;
+}
+
+void infer(gl_mlp* mm, const uint16_t* X, int64_t n_cap, const unsigned long long* n_dev, float* y, hipStream_t s)
+{
+    launch_infer(mm, (const bf16*)X, n_cap, n_dev, y, s);
+}
+
+gl_status get_state(const gl_mlp* mmc, float* m, float* v, int64_t* step)
+{
+    gl_mlp* mm = const_cast<gl_mlp*>(mmc);
+    if (!mm || !m || !v || !step) return GL_ERR_NULL;
+    GM_HIP(hipSetDevice(mm->device), "hipSetDevice");
+    GM_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    GM_HIP(hipMemcpy(m, mm->m, sizeof(float) * kNParam, hipMemcpyDeviceToHost), "hipMemcpy");
+    GM_HIP(hipMemcpy(v, mm->v, sizeof(float) * kNParam, hipMemcpyDeviceToHost), "hipMemcpy");
+    *step = mm->step;
+    return GL_OK;
+}
+
+gl_status set_state(gl_mlp* mm, const float* m, const float* v, int64_t step)
+{
+    if (!mm || !m || !v) return GL_ERR_NULL;
+    GM_HIP(hipSetDevice(mm->device), "hipSetDevice");
+    GM_HIP(hipMemcpy(mm->m, m, sizeof(float) * kNParam, hipMemcpyHostToDevice), "hipMemcpy");
+    GM_HIP(hipMemcpy(mm->v, v, sizeof(float) * kNParam, hipMemcpyHostToDevice), "hipMemcpy");
+    mm->step = step;
+    return GL_OK;
+}
+
+}  // namespace gl_net

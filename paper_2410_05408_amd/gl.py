@@ -430,28 +430,55 @@ def unpack_params(packed, d_in=GL_MLP_DIN, width=GL_MLP_WIDTH, depth=4):
 
 
 # ---------------------------------------------------------------- surrogate path
-EXPORTED = EXPORTED + ("gl_surrogate_samples", "gl_surrogate_num_bins", "gl_surrogate_bound",
-                       "gl_lightcurve_batch_surrogate", "gl_surrogate_save", "gl_surrogate_load")
+EXPORTED = EXPORTED + ("gl_surrogate_samples", "gl_surrogate_num_bins", "gl_surrogate_config_default",
+                       "gl_surrogate_train", "gl_surrogate_destroy", "gl_surrogate_get", "gl_surrogate_config_of",
+                       "gl_surrogate_save", "gl_surrogate_load", "gl_surrogate_file_write",
+                       "gl_surrogate_file_read", "gl_lightcurve_batch_surrogate")
+
+
+class SurrogateConfig(ctypes.Structure):
+    """gl_surrogate_config (field for field)."""
+    _fields_ = [("n_train", ctypes.c_int64), ("n_calib", ctypes.c_int64), ("epochs", ctypes.c_int),
+                ("batch", ctypes.c_int), ("lr", ctypes.c_float), ("lr_final", ctypes.c_float),
+                ("safety", ctypes.c_double), ("min_bin_count", ctypes.c_int), ("window", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("zero_predictor", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 def _sur_lib():
     L = _mlp_lib()
     if not getattr(L, "_sur_typed", False):
         vp, i, i64, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        fp, u8p, i32p = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32)
+        cfgp = ctypes.POINTER(SurrogateConfig)
         L.gl_surrogate_samples.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
         L.gl_surrogate_samples.restype = i
         L.gl_surrogate_num_bins.argtypes = []
         L.gl_surrogate_num_bins.restype = i
-        L.gl_surrogate_bound.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
-        L.gl_surrogate_bound.restype = i
-        L.gl_lightcurve_batch_surrogate.argtypes = [vp, vp, vp, vp, d, d, vp, i64, vp, vp, i64, vp, vp,
-                                                    vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
-        L.gl_lightcurve_batch_surrogate.restype = i
-        fp, u8p = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint8)
-        L.gl_surrogate_save.argtypes = [ctypes.c_char_p, fp, i64, fp, u8p, i]
+        L.gl_surrogate_config_default.argtypes = [cfgp]
+        L.gl_surrogate_config_default.restype = None
+        L.gl_surrogate_train.argtypes = [vp, cfgp, ctypes.POINTER(vp), fp, vp]
+        L.gl_surrogate_train.restype = i
+        L.gl_surrogate_destroy.argtypes = [vp]
+        L.gl_surrogate_destroy.restype = None
+        L.gl_surrogate_get.argtypes = [vp, fp, i64, fp, u8p, i32p, i]
+        L.gl_surrogate_get.restype = i
+        L.gl_surrogate_config_of.argtypes = [vp, cfgp]
+        L.gl_surrogate_config_of.restype = i
+        L.gl_surrogate_save.argtypes = [vp, ctypes.c_char_p]
         L.gl_surrogate_save.restype = i
-        L.gl_surrogate_load.argtypes = [ctypes.c_char_p, fp, i64, fp, u8p, i]
+        L.gl_surrogate_load.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_char_p]
         L.gl_surrogate_load.restype = i
+        L.gl_surrogate_file_write.argtypes = [ctypes.c_char_p, cfgp, fp, fp, fp, i64, i64, fp, u8p, i32p, i]
+        L.gl_surrogate_file_write.restype = i
+        L.gl_surrogate_file_read.argtypes = [ctypes.c_char_p, cfgp, fp, fp, fp, ctypes.POINTER(i64), i64, fp,
+                                             u8p, i32p, i]
+        L.gl_surrogate_file_read.restype = i
+        L.gl_lightcurve_batch_surrogate.argtypes = [vp, vp, d, vp, i64, vp, vp, i64, vp, vp, vp, vp,
+                                                    ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.gl_lightcurve_batch_surrogate.restype = i
         L._sur_typed = True
     return L
 
@@ -460,32 +487,90 @@ def gl_surrogate_num_bins() -> int:
     return _sur_lib().gl_surrogate_num_bins()
 
 
-def gl_surrogate_save(path: str, params: np.ndarray, table: np.ndarray, zero_bins=None) -> None:
-    """Writes a trained surrogate (host arrays: packed FP32 parameters, FP32
-    bound table, optional uint8 per-bin predictor choice)."""
-    p = np.ascontiguousarray(params, dtype=np.float32)
-    t = np.ascontiguousarray(table, dtype=np.float32)
-    z = None if zero_bins is None else np.ascontiguousarray(zero_bins, dtype=np.uint8)
-    L = _sur_lib()
-    zp = z.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if z is not None else None
-    if z is not None and z.size != t.size:
-        raise GLError(GL_ERR_SIZE, "zero_bins and table differ in length")
-    st = L.gl_surrogate_save(os.fsencode(path), _fptr(p), p.size, _fptr(t), zp, t.size)
+def gl_surrogate_config_default() -> SurrogateConfig:
+    c = SurrogateConfig()
+    _sur_lib().gl_surrogate_config_default(ctypes.byref(c))
+    return c
+
+
+def _u8p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def _i32p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def gl_surrogate_train(ctx, cfg: SurrogateConfig, stream=None):
+    """Returns (surrogate handle, per-epoch mean squared errors)."""
+    h = ctypes.c_void_p()
+    hist = np.zeros(max(1, cfg.epochs), np.float32)
+    _check(ctx, _sur_lib().gl_surrogate_train(ctx, ctypes.byref(cfg), ctypes.byref(h), _fptr(hist),
+                                              _stream_handle(stream)))
+    return h, hist[:cfg.epochs].tolist()
+
+
+def gl_surrogate_destroy(h) -> None:
+    _sur_lib().gl_surrogate_destroy(h)
+
+
+def gl_surrogate_get(h):
+    """Host copies: (params float32, table float32, zero_bins uint8, counts int32)."""
+    p = np.empty(gl_mlp_num_params(), np.float32)
+    nb = gl_surrogate_num_bins()
+    t, z, c = np.empty(nb, np.float32), np.empty(nb, np.uint8), np.empty(nb, np.int32)
+    st = _sur_lib().gl_surrogate_get(h, _fptr(p), p.size, _fptr(t), _u8p(z), _i32p(c), nb)
+    if st != GL_OK:
+        raise GLError(st, "gl_surrogate_get")
+    return p, t, z, c
+
+
+def gl_surrogate_config_of(h) -> SurrogateConfig:
+    c = SurrogateConfig()
+    st = _sur_lib().gl_surrogate_config_of(h, ctypes.byref(c))
+    if st != GL_OK:
+        raise GLError(st, "gl_surrogate_config_of")
+    return c
+
+
+def gl_surrogate_save(h, path: str) -> None:
+    st = _sur_lib().gl_surrogate_save(h, os.fsencode(path))
     if st != GL_OK:
         raise GLError(st, f"gl_surrogate_save({path})")
 
 
-def gl_surrogate_load(path: str):
-    """Reads a surrogate file: (params float32, table float32, zero_bins uint8)."""
-    L = _sur_lib()
-    p = np.empty(gl_mlp_num_params(), np.float32)
-    t = np.empty(gl_surrogate_num_bins(), np.float32)
-    z = np.empty(t.size, np.uint8)
-    st = L.gl_surrogate_load(os.fsencode(path), _fptr(p), p.size, _fptr(t),
-                             z.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), t.size)
+def gl_surrogate_load(ctx, path: str):
+    h = ctypes.c_void_p()
+    _check(ctx, _sur_lib().gl_surrogate_load(ctx, ctypes.byref(h), os.fsencode(path)))
+    return h
+
+
+def gl_surrogate_file_write(path, cfg, params, m, v, step, table, zero_bins, counts) -> None:
+    """Writes the surrogate file from host arrays (no device call)."""
+    p, mm, vv = (np.ascontiguousarray(a, dtype=np.float32) for a in (params, m, v))
+    t = np.ascontiguousarray(table, dtype=np.float32)
+    z = np.ascontiguousarray(zero_bins, dtype=np.uint8)
+    c = np.ascontiguousarray(counts, dtype=np.int32)
+    st = _sur_lib().gl_surrogate_file_write(os.fsencode(path), ctypes.byref(cfg), _fptr(p), _fptr(mm), _fptr(vv),
+                                            int(step), p.size, _fptr(t), _u8p(z), _i32p(c), t.size)
     if st != GL_OK:
-        raise GLError(st, f"gl_surrogate_load({path})")
-    return p, t, z
+        raise GLError(st, f"gl_surrogate_file_write({path})")
+
+
+def gl_surrogate_file_read(path):
+    """Reads a surrogate file into host arrays: (cfg, params, m, v, step,
+    table, zero_bins, counts)."""
+    cfg = SurrogateConfig()
+    n = gl_mlp_num_params()
+    nb = gl_surrogate_num_bins()
+    p, m, v = (np.empty(n, np.float32) for _ in range(3))
+    t, z, c = np.empty(nb, np.float32), np.empty(nb, np.uint8), np.empty(nb, np.int32)
+    step = ctypes.c_int64()
+    st = _sur_lib().gl_surrogate_file_read(os.fsencode(path), ctypes.byref(cfg), _fptr(p), _fptr(m), _fptr(v),
+                                           ctypes.byref(step), n, _fptr(t), _u8p(z), _i32p(c), nb)
+    if st != GL_OK:
+        raise GLError(st, f"gl_surrogate_file_read({path})")
+    return cfg, p, m, v, step.value, t, z, c
 
 
 def gl_surrogate_samples(ctx, params, times, feat, target, f_obl=None, f_sph=None, scale=None,
@@ -497,19 +582,15 @@ def gl_surrogate_samples(ctx, params, times, feat, target, f_obl=None, f_sph=Non
                                                 _ptr(bin), _stream_handle(stream)))
 
 
-def gl_surrogate_bound(ctx, pred, target, scale, bin, table, stream=None):
-    _check(ctx, _sur_lib().gl_surrogate_bound(ctx, _ptr(pred), _ptr(target), _ptr(scale), _ptr(bin),
-                                              pred.numel(), _ptr(table), _stream_handle(stream)))
-
-
-def gl_lightcurve_batch_surrogate(ctx, mlp, table, safety, tol, params, times, out, offsets=None,
-                                  n_ss=None, t_exp=None, stream=None, zero_bins=None):
-    """Returns (n_sub, n_fallback)."""
+def gl_lightcurve_batch_surrogate(ctx, sur, tol, params, times, out, offsets=None, n_ss=None, t_exp=None,
+                                  stream=None, counts=True):
+    """Enqueues the gated light curves; with `counts`, waits and returns
+    (in-window sub-samples, of those computed exactly although reaching the disk)."""
     _validate(params, times, offsets, n_ss, t_exp, out)
     a, b = ctypes.c_int64(), ctypes.c_int64()
     st = _sur_lib().gl_lightcurve_batch_surrogate(
-        ctx, mlp.h, _ptr(table), _ptr(zero_bins), float(safety), float(tol), _ptr(params), params.shape[1],
-        _ptr(times), _ptr(offsets), times.numel(), _ptr(n_ss), _ptr(t_exp), _ptr(out),
-        _stream_handle(stream), ctypes.byref(a), ctypes.byref(b))
+        ctx, sur, float(tol), _ptr(params), params.shape[1], _ptr(times), _ptr(offsets), times.numel(),
+        _ptr(n_ss), _ptr(t_exp), _ptr(out), _stream_handle(stream),
+        ctypes.byref(a) if counts else None, ctypes.byref(b) if counts else None)
     _check(ctx, st)
-    return a.value, b.value
+    return (a.value, b.value) if counts else None
