@@ -321,6 +321,52 @@ def exact_leg(gl, w, steps, warmup, trials=10, autotune=False, check_oracle=True
     return res, got
 
 
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
+
+
+def snap_leg(gl, w, census, exact_got, nodes_list=(1024, 8192), trials=10, dev="cuda:0"):
+    """The paper's own integrator (FP32 snap + Simpson) on the same batch:
+    time per step at each node count, its FP32 rate (nodes x the per-node
+    operation count x the sub-samples whose ellipse reaches the disk, from
+    the exact path's census) against the FP32 vector peak, and its error
+    against the exact path (itself within 1e-9 of the oracle)."""
+    import torch
+    d = gl.to_device(w, dev)
+    out = torch.empty(w.n_out, dtype=torch.float64, device=dev)
+    ctx = gl.Context(0)
+    stream = torch.cuda.Stream()
+    overlapping = census["whole_on_star"] + census["intersecting"]
+    per_node = 48  # FP32 operations per node inside the disk (FMA = 2)
+    exact = torch.from_numpy(exact_got).to(dev)
+    res = {}
+    for nodes in nodes_list:
+        def step():
+            gl.gl_lightcurve_batch_snap(ctx.handle, nodes, d["params"], d["times"], out, offsets=d["offsets"],
+                                        n_ss=d["n_ss"], t_exp=d["t_exp"], stream=stream)
+        step()
+        stream.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(trials)]
+        for a, b in ev:
+            a.record(stream)
+            step()
+            b.record(stream)
+        stream.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        flop = overlapping * nodes * per_node
+        achieved = flop / (ms * 1e-3) / 1e12
+        err = (out - exact).abs()
+        res[str(nodes)] = {
+            "ms_per_step_median": ms, "points_per_s": w.n_out / (ms * 1e-3),
+            "sub_samples_per_s": w.n_sub / (ms * 1e-3),
+            "max_abs_err_vs_exact": float(err.max().item()),
+            "p99_abs_err_changed_outputs": float(torch.quantile(err[exact < 1.0].float(), 0.99).item()),
+            "roofline": {"bound": "alu", "kernel": "k_snap", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                         "algorithmic_flop_per_launch": flop}}
+    ctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -392,6 +438,10 @@ def main():
         res["configs"]["uneven_batch"] = {"config": {"n_sets": 16384, "grid_len": "log-uniform [200, 20000]",
                                                      "n_ss": "{1, 5, 15}", "layout": "CSR", "seed": 4}, **ub}
         torch.cuda.synchronize()
+    if not args.no_extra_configs and not args.only:
+        log("the paper's integrator (FP32 snap + Simpson) on the walker batch")
+        res["paper_integrator"] = {"config": {"workload": "walker_batch", "precision": "fp32"},
+                                   **snap_leg(gl, w, res["census"], got)}
     if not args.no_surrogate and not args.only:
         log("surrogate leg: data, training, calibration, gated evaluation")
         d = gl.to_device(w, "cuda:0")

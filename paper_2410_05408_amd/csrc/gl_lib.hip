@@ -1189,6 +1189,90 @@ k_combine(const gl::SetConst* __restrict__ sc, const Counters* __restrict__ ctr,
     }
 }
 
+// The paper's integrator over a batch, a workgroup per chunk of 64 outputs
+// (wavefront w takes every fourth in-window output from the w-th on): the
+// centres of an output's sub-samples are found one per lane, then each
+// sub-sample that reaches the disk is integrated by the whole wavefront (node
+// i on lane i mod 64, Simpson weight 4 on odd nodes: odd lanes, 2 on even),
+// the three sums reduced across the lanes; outputs are box-averaged in FP64
+// (the sub-samples off the disk first, then the others in order).  node_cs:
+// cos and sin of 2 pi i / n_nodes.
+constexpr int kSnapWaves = 4;
+
+__global__ void __launch_bounds__(64 * kSnapWaves)
+k_snap(const double* __restrict__ times, int shared_grid, const gl::SetConst* __restrict__ sc,
+       const int64_t* __restrict__ seg_begin, const int64_t* __restrict__ chunk_off, const Counters* __restrict__ ctr,
+       const unsigned long long* __restrict__ masks, const int* __restrict__ chunk_set, int n_nodes,
+       const float2* __restrict__ node_cs, double* __restrict__ out)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t total = (int64_t)ctr->total_chunks;
+    const float wt = (lane & 1) ? 4.0f : 2.0f;
+    for (int64_t c = blockIdx.x; c < total; c += gridDim.x) {
+        unsigned long long M = (unsigned long long)uniform64((int64_t)masks[c]);
+        if (!M) continue;
+        for (int w = 0; w < wv; ++w) M &= M - 1ull;  // this wavefront's outputs: the wv-th, wv+4-th, ...
+        if (!M) continue;
+        const int64_t s = uniform64(chunk_set[c]);
+        const gl::SetConst& S = sc[s];
+        const gl::ChunkPos cp = gl::chunk_pos(shared_grid != 0, seg_begin[s], c - chunk_off[s]);
+        const int nss = S.n_ss;
+        const double inv_nss = 1.0 / (double)nss;
+        const float A = (float)S.A, B = (float)S.B, C = (float)S.C;
+        const double reach2 = (1.0 + S.k) * (1.0 + S.k);
+        const float k0 = (float)S.c0, k1 = (float)S.c1 * (2.0f / 3.0f), k2 = (float)S.c2;
+        const float scale = (float)(gl::kTwoPi / 3.0) / (float)n_nodes * (float)S.inv_phi;
+        while (M) {
+            const int o = __builtin_ctzll(M);  // the output (a lane of the chunk)
+            for (int w = 0; w < kSnapWaves && M; ++w) M &= M - 1ull;
+            const double t = times[cp.time0 + o];
+            // lane j: sub-sample j's centre and whether its ellipse can reach the disk
+            double x0 = 0.0, y0 = 0.0;
+            bool on = false;
+            if (lane < nss) {
+                on = gl::centre_at(S, t + (((double)lane + 0.5) * inv_nss - 0.5) * S.t_exp, x0, y0);
+                on = on && x0 * x0 + y0 * y0 < reach2;
+            }
+            const unsigned long long todo = __ballot(on);
+            double sum = (double)(nss - __popcll(todo));  // sub-samples off the disk: flux 1
+            // then, in order of j, the flux of every sub-sample that reaches the disk
+            for (int j = 0; j < nss; ++j) {
+                if (!((todo >> j) & 1ull)) continue;
+                const float xc = (float)__shfl(x0, j), yc = (float)__shfl(y0, j);
+                float sf = 0.0f, sl = 0.0f, sq = 0.0f;
+                for (int i = lane; i < n_nodes; i += 64) {
+                    const float2 q = node_cs[i];
+                    float ff, fl, fq;
+                    gl::snap_node(A, B, C, xc, yc, q.x, q.y, ff, fl, fq);
+                    sf += ff;
+                    sl += fl;
+                    sq += fq;
+                }
+                sf *= wt;
+                sl *= wt;
+                sq *= wt;
+                for (int d = 32; d >= 1; d >>= 1) {
+                    sf += __shfl_xor(sf, d);
+                    sl += __shfl_xor(sl, d);
+                    sq += __shfl_xor(sq, d);
+                }
+                sum += (double)(1.0f - (k0 * sf + k1 * sl + k2 * sq) * scale);
+            }
+            if (lane == 0) out[cp.out0 + o] = sum * inv_nss;
+        }
+    }
+}
+
+// cos and sin of 2 pi i / n, i < n (from the double-precision functions)
+__global__ void k_snap_nodes(int n, float2* __restrict__ cs)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double sn, c;
+    sincos(gl::kTwoPi * (double)i / (double)n, &sn, &c);
+    cs[i] = float2{(float)c, (float)sn};
+}
+
 // Surrogate batches: the network's rows in list order, as dense arrays
 // (features in BF16, flux slot, residual scale) and their count.
 __global__ void __launch_bounds__(64)
@@ -1566,6 +1650,9 @@ struct gl_ctx {
     int64_t pipe_chunks = 0;  // length of the per-chunk arrays
     int64_t want_sub = 0, want_hard = 0, want_arc = 0;
     bool want_net = false;  // lists and buffers of surrogate batches
+    // the paper's integrator: cos / sin of its nodes (snap_n of them, room for snap_cap)
+    float2* snap_cs = nullptr;
+    int snap_cap = 0, snap_n = 0;
     // demand-driven sizing: the record k_demand writes (pinned host memory and
     // its device address), and the per-shard capacities it asked for
     Demand* rec = nullptr;
@@ -2065,6 +2152,7 @@ void gl_ctx_destroy(gl_ctx* ctx)
     drop_graph(ctx);
     free_ws(ctx);
     (void)hipFree(ctx->ctr);
+    (void)hipFree(ctx->snap_cs);
     if (ctx->rec) (void)hipHostFree(ctx->rec);
     delete ctx;
 }
@@ -2327,6 +2415,49 @@ gl_status gl_flop_model(int64_t* per_item)
     per_item[8] = gl::kFlopTrapNode;
     per_item[9] = gl::kFlopArc;
     per_item[10] = 0;  // unconverged arcs: their pieces are already counted
+    return GL_OK;
+}
+
+gl_status gl_lightcurve_batch_snap(gl_ctx* ctx, int n_nodes, const double* params, int64_t n_sets,
+                                   const double* times, const int64_t* offsets, int64_t n_times,
+                                   const int32_t* n_ss, const double* t_exp, double* out, void* stream)
+{
+    Batch b{params, n_sets, times, offsets, n_times, n_ss, t_exp, out, (hipStream_t)stream, 0};
+    gl_status st = check_args(ctx, b);
+    if (st != GL_OK) return st;
+    if (n_nodes < 4 || n_nodes > (1 << 20) || n_nodes % 2) return fail(ctx, GL_ERR_SIZE, "n_nodes even in [4, 2^20]");
+    GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    st = ensure_ws(ctx, n_sets, b.max_chunks);
+    if (st != GL_OK) return st;
+    st = ensure_pipe(ctx, b.max_chunks);  // the window kernel's arguments (its lists stay unused)
+    if (st != GL_OK) return st;
+    hipStream_t s = b.stream;
+    const int shared = b.offsets ? 0 : 1;
+    const int64_t cps_shared = shared ? (b.n_times + kChunk - 1) / kChunk : 0;
+    hipLaunchKernelGGL(k_prep, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, s, params, n_sets, n_sets, offsets,
+                       n_times, n_ss, t_exp, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off, ctx->ctr, cps_shared,
+                       1, 1, (gl::SetConst*)nullptr);
+    if (!shared)
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, ctx->chunk_off, n_sets, b.max_chunks, ctx->ctr);
+    launch_window(ctx, b, s, 0, ctx->pipe);
+    if (n_nodes > ctx->snap_cap) {
+        GL_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        (void)hipFree(ctx->snap_cs);
+        ctx->snap_cs = nullptr;
+        ctx->snap_cap = 0;
+        if (hipMalloc(&ctx->snap_cs, sizeof(float2) * n_nodes) != hipSuccess) return fail(ctx, GL_ERR_NOMEM, "node table");
+        ctx->snap_cap = n_nodes;
+        ctx->snap_n = 0;
+    }
+    if (ctx->snap_n != n_nodes) {
+        hipLaunchKernelGGL(k_snap_nodes, dim3((unsigned)((n_nodes + 255) / 256)), dim3(256), 0, s, n_nodes, ctx->snap_cs);
+        ctx->snap_n = n_nodes;
+    }
+    // a workgroup per chunk (the dispatcher balances chunks of unequal work)
+    const unsigned grid = (unsigned)std::min<int64_t>(b.max_chunks, (int64_t)INT32_MAX);
+    hipLaunchKernelGGL(k_snap, dim3(grid), dim3(64 * kSnapWaves), 0, s, times, shared, ctx->sc, ctx->seg_begin,
+                       ctx->chunk_off, ctx->ctr, ctx->masks, ctx->chunk_set, n_nodes, ctx->snap_cs, out);
+    GL_HIP(hipGetLastError(), "kernel launch");
     return GL_OK;
 }
 

@@ -26,7 +26,7 @@ EXPORTED = ("gl_ctx_create", "gl_ctx_destroy", "gl_lightcurve_batch", "gl_ctx_sy
             "gl_ctx_last_error", "gl_autotune", "gl_ctx_get_plan", "gl_ctx_set_plan",
             "gl_ctx_set_graph", "gl_ctx_set_capacity", "gl_ctx_set_timing", "gl_ctx_get_timing",
             "gl_ctx_get_stage_timing", "gl_census", "gl_flop_model", "gl_ctx_get_unconverged",
-            "gl_ctx_get_overflow", "gl_lightcurve_batch_noalloc", "gl_version")
+            "gl_ctx_get_overflow", "gl_lightcurve_batch_noalloc", "gl_lightcurve_batch_snap", "gl_version")
 CENSUS_NAMES = ("sub_in_window", "whole_on_star", "intersecting", "off_star_in_window",
                 "trapezoid_nodes", "gk21_pieces", "newton_steps", "limb_arcs",
                 "nested_trapezoid_nodes", "ellipse_arcs", "unconverged_arcs")
@@ -59,6 +59,8 @@ def lib():
         batch_args = [vp, vp, i64, vp, vp, i64, vp, vp, vp, vp]
         L.gl_lightcurve_batch.argtypes = batch_args
         L.gl_lightcurve_batch.restype = i
+        L.gl_lightcurve_batch_snap.argtypes = [vp, i] + batch_args[1:]
+        L.gl_lightcurve_batch_snap.restype = i
         L.gl_lightcurve_batch_noalloc.argtypes = batch_args[1:]
         L.gl_lightcurve_batch_noalloc.restype = i
         L.gl_autotune.argtypes = batch_args
@@ -165,6 +167,16 @@ def gl_lightcurve_batch_noalloc(params, times, out, offsets=None, n_ss=None, t_e
                                            _stream_handle(stream))
     if st != GL_OK:
         raise GLError(st, "gl_lightcurve_batch_noalloc")
+
+
+def gl_lightcurve_batch_snap(ctx, n_nodes, params, times, out, offsets=None, n_ss=None, t_exp=None,
+                             stream=None) -> None:
+    """The paper's FP32 snap + Simpson integrator over a batch (n_nodes nodes)."""
+    _validate(params, times, offsets, n_ss, t_exp, out)
+    st = lib().gl_lightcurve_batch_snap(ctx, int(n_nodes), _ptr(params), params.shape[1], _ptr(times),
+                                        _ptr(offsets), times.numel(), _ptr(n_ss), _ptr(t_exp), _ptr(out),
+                                        _stream_handle(stream))
+    _check(ctx, st)
 
 
 def gl_autotune(ctx, params, times, out, offsets=None, n_ss=None, t_exp=None, stream=None) -> None:

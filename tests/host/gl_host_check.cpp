@@ -11,6 +11,8 @@
 //                                O: float64 instantaneous fluxes [n];
 //                                prints the number of ellipse arcs the arc
 //                                rule accepted at its last level unconverged
+//   gl_host_check snap N P T O   the same samples by the paper's integrator
+//                                (FP32 snap + Simpson, N nodes)
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -75,6 +77,25 @@ int main(int argc, char** argv)
         std::fclose(f);
         return ok ? 0 : 4;
     }
-    std::fprintf(stderr, "usage: gl_host_check math | flux params times out\n");
+    if (argc == 6 && std::strcmp(argv[1], "snap") == 0) {
+        // the paper's integrator (FP32 snap + Simpson) with N nodes
+        const int nodes = std::atoi(argv[2]);
+        const std::vector<double> p = read_all(argv[3]), t = read_all(argv[4]);
+        const size_t n = t.size();
+        if (n == 0 || p.size() != 10 * n || nodes < 2 || nodes % 2) return 2;
+        std::vector<double> out(n);
+        for (size_t s = 0; s < n; ++s) {
+            double q[10];
+            for (int i = 0; i < 10; ++i) q[i] = p[(size_t)i * n + s];
+            gl::SetConst c;
+            out[s] = gl::make_set_const(q, 0.0, 1, c) ? (double)gl::flux_snap(c, t[s], nodes) : std::nan("");
+        }
+        FILE* f = std::fopen(argv[5], "wb");
+        if (!f) return 3;
+        const bool ok = std::fwrite(out.data(), sizeof(double), n, f) == n;
+        std::fclose(f);
+        return ok ? 0 : 4;
+    }
+    std::fprintf(stderr, "usage: gl_host_check math | flux params times out | snap nodes params times out\n");
     return 1;
 }

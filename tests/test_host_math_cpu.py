@@ -92,3 +92,37 @@ def test_host_flux_matches_oracle_on_walker_draws(host_check, oracle, tmp_path):
     assert np.sum(got < 1.0) > n // 2
     assert np.max(np.abs(got - ref)) <= 1e-9
     assert unconv[0] == 0
+
+
+def host_snap(exe, tmp_path, params, times, nodes):
+    pf, tf, of = (str(tmp_path / n) for n in ("ps.bin", "ts.bin", "os.bin"))
+    np.ascontiguousarray(params, dtype=np.float64).tofile(pf)
+    np.ascontiguousarray(times, dtype=np.float64).tofile(tf)
+    subprocess.run([exe, "snap", str(nodes), pf, tf, of], check=True)
+    return np.fromfile(of)
+
+
+def test_paper_integrator_against_oracle(host_check, oracle, tmp_path):
+    """The paper's FP32 snap + Simpson integrator (host build of the kernel's
+    routine): samples whose ellipse lies inside the disk are at
+    single-precision noise at any node count; partially overlapping samples
+    converge to the oracle as the node count grows (about as 1/n: the
+    quadratic integrand jumps where the curve is moved onto the limb)."""
+    rng = np.random.default_rng(11)
+    n = 2000
+    params = W.draw_params(rng, n)
+    t14 = W.full_duration(params[W.K], params[W.B], params[W.ARS], params[W.P])
+    times = rng.uniform(-0.6, 0.6, n) * t14
+    ref = oracle_flux(oracle, params, times)
+    geo = [oracle.geometry(params[:, i], times[i]) for i in range(n)]
+    rho = np.array([math.hypot(g[1][0], g[1][1]) if g[0] else 9.0 for g in geo])
+    k = params[W.K]
+    inside, partial = rho <= 1 - k, (rho > 1 - k) & (rho < 1 + k)
+    errs = {}
+    for nodes in (256, 1024, 8192):
+        err = np.abs(host_snap(host_check, tmp_path, params, times, nodes) - ref)
+        errs[nodes] = err[partial].max()
+        assert err[inside].max() <= 3e-7, nodes
+        assert np.all(err[~inside & ~partial] == 0.0)  # centre beyond 1 + k: exactly 1
+    assert errs[256] > errs[1024] > errs[8192]
+    assert errs[8192] <= 4e-6 and errs[1024] <= 3e-5
