@@ -617,6 +617,153 @@ int64_t glo_flux_batch(const double *params, int64_t n_sets,
     return nerr;
 }
 
+/* ------------------------------------------------------------------------ */
+/* General ellipsoids (a, b, c; angles zeta, eta, xi), optionally tidally   */
+/* locked                                                                    */
+/* ------------------------------------------------------------------------ */
+/* Silhouette as the Schur complement of the body quadric: with M the
+ * rotation from observer offsets y = x - x_c to body coordinates
+ * (x' = M y; Section 2 eq. coord-map gives M = R(zeta, eta, xi), the
+ * tidally-locked map of Appendix B gives M = R(zeta, eta, xi) Rx(-alpha)
+ * Ry(beta)), the ellipsoid is y^T Q y <= 1 with Q = M^T diag(a^-2, b^-2,
+ * c^-2) M, and its orthographic shadow on the sky plane is u^T S u <= 1 with
+ * S = Q_xy,xy - Q_xy,z Q_zz^-1 Q_z,xy.  The shadow's semi-axes and the
+ * direction of the major one come from the eigen-decomposition of S.  (The
+ * GPU path uses the paper's parametric eqs. dx, dy1, dy2 instead.) */
+static int ell_params_ok(const double p[GLO_E_NPARAM])
+{
+    for (int i = 0; i < GLO_E_NPARAM; i++)
+        if (!isfinite(p[i])) return 0;
+    double amax = 0.0;
+    for (int i = GLO_E_RA; i <= GLO_E_RC; i++) {
+        if (!(p[i] > 0.0 && p[i] < 1.0)) return 0;
+        if (p[i] > amax) amax = p[i];
+    }
+    const double d = p[GLO_E_ARS];
+    if (!(d > 1.0 + amax)) return 0;
+    if (!(fabs(p[GLO_E_B]) < d)) return 0;
+    if (!(p[GLO_E_P] > 0.0)) return 0;
+    if (!(p[GLO_E_Q1] >= 0.0 && p[GLO_E_Q1] <= 1.0)) return 0;
+    if (!(p[GLO_E_Q2] >= 0.0 && p[GLO_E_Q2] <= 1.0)) return 0;
+    if (!(p[GLO_E_LOCKED] == 0.0 || p[GLO_E_LOCKED] == 1.0)) return 0;
+    return 1;
+}
+
+int glo_geometry_ell(const double p[GLO_E_NPARAM], double t, double out[9])
+{
+    const double b = p[GLO_E_B], d = p[GLO_E_ARS], P = p[GLO_E_P], t0 = p[GLO_E_T0];
+    double alpha = 2.0 * M_PI * (t - t0) / P;
+    double beta = asin(b / d);
+    double Ry[3][3], Rx[3][3], Rb[3][3];
+    rot_y(-beta, Ry);
+    rot_x(alpha, Rx);
+    mat3_mul(Ry, Rx, Rb);
+    double xc = -Rb[0][2] * d, yc = -Rb[1][2] * d, zc = -Rb[2][2] * d;
+
+    double Rzeta[3][3], Reta[3][3], Rxi[3][3], T[3][3], M[3][3];
+    rot_x(p[GLO_E_ZETA], Rzeta);
+    rot_y(p[GLO_E_ETA], Reta);
+    rot_z(p[GLO_E_XI], Rxi);
+    mat3_mul(Reta, Rxi, T);
+    mat3_mul(Rzeta, T, M); /* R(zeta, eta, xi) */
+    if (p[GLO_E_LOCKED] != 0.0) {
+        double Rma[3][3], Rpb[3][3], L[3][3], M2[3][3];
+        rot_x(-alpha, Rma);
+        rot_y(beta, Rpb);
+        mat3_mul(Rma, Rpb, L);
+        mat3_mul(M, L, M2);
+        memcpy(M, M2, sizeof(M));
+    }
+    const double inv2[3] = {1.0 / (p[GLO_E_RA] * p[GLO_E_RA]), 1.0 / (p[GLO_E_RB] * p[GLO_E_RB]),
+                            1.0 / (p[GLO_E_RC] * p[GLO_E_RC])};
+    double Q[3][3];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; k++) acc += M[k][i] * inv2[k] * M[k][j];
+            Q[i][j] = acc;
+        }
+    const double s11 = Q[0][0] - Q[0][2] * Q[2][0] / Q[2][2];
+    const double s12 = Q[0][1] - Q[0][2] * Q[2][1] / Q[2][2];
+    const double s22 = Q[1][1] - Q[1][2] * Q[2][1] / Q[2][2];
+    const double half_tr = 0.5 * (s11 + s22);
+    const double rad = hypot(0.5 * (s11 - s22), s12);
+    const double lo = half_tr - rad, hi = half_tr + rad; /* lo: major axis */
+    /* eigenvector of the smaller eigenvalue, from the better-conditioned row */
+    double ux, uy;
+    if (rad == 0.0) {
+        ux = 1.0;
+        uy = 0.0;
+    } else if (fabs(s11 - lo) >= fabs(s22 - lo)) {
+        ux = -s12;
+        uy = s11 - lo;
+    } else {
+        ux = s22 - lo;
+        uy = -s12;
+    }
+    const double nu = hypot(ux, uy);
+    ux /= nu;
+    uy /= nu;
+    out[0] = xc;
+    out[1] = yc;
+    out[2] = zc;
+    out[3] = ux; /* u_hat: major axis */
+    out[4] = uy;
+    out[5] = uy; /* s_hat = (uy, -ux): minor axis */
+    out[6] = -ux;
+    out[7] = 1.0 / sqrt(lo);
+    out[8] = 1.0 / sqrt(hi);
+    return zc < 0.0 ? 1 : 0;
+}
+
+static double flux_instant_ell(const double p[GLO_E_NPARAM], double u1, double u2, double t, double tol)
+{
+    double g[9];
+    if (!glo_geometry_ell(p, t, g)) return 1.0;
+    return 1.0 - glo_occulted(g[0], g[1], g[3], g[4], g[7], g[8] / g[7], u1, u2, tol, GLO_INNER_CLOSED);
+}
+
+int glo_flux_ell(const double p[GLO_E_NPARAM], double t, double t_exp, int n_ss, double tol, double *out)
+{
+    double u1, u2;
+    if (!ell_params_ok(p) || !isfinite(t) || !isfinite(t_exp) || t_exp < 0.0 || n_ss < 1 || n_ss > 64 ||
+        glo_kipping(p[GLO_E_Q1], p[GLO_E_Q2], &u1, &u2)) {
+        *out = NAN;
+        return -1;
+    }
+    double sum = 0.0;
+    for (int j = 0; j < n_ss; j++) {
+        double tj = t + (((double)j + 0.5) / (double)n_ss - 0.5) * t_exp;
+        sum += flux_instant_ell(p, u1, u2, tj, tol);
+    }
+    *out = sum / (double)n_ss;
+    return 0;
+}
+
+int64_t glo_flux_batch_ell(const double *params, int64_t n_sets, const double *times, const int64_t *offsets,
+                           int64_t n_times, const int32_t *n_ss, const double *t_exp, double tol, double *out,
+                           int nthreads)
+{
+    int64_t nerr = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads) reduction(+ : nerr)
+#endif
+    for (int64_t s = 0; s < n_sets; s++) {
+        double p[GLO_E_NPARAM];
+        for (int i = 0; i < GLO_E_NPARAM; i++) p[i] = params[(int64_t)i * n_sets + s];
+        int64_t a = offsets ? offsets[s] : s * n_times;
+        int64_t b = offsets ? offsets[s + 1] : (s + 1) * n_times;
+        int nss = n_ss ? n_ss[s] : 1;
+        double te = t_exp ? t_exp[s] : 0.0;
+        for (int64_t i = a; i < b; i++) {
+            double t = offsets ? times[i] : times[i - a];
+            if (glo_flux_ell(p, t, te, nss, tol, &out[i])) nerr++;
+        }
+    }
+    return nerr;
+}
+
 long glo_unconverged(void)
 {
     long n;

@@ -96,6 +96,22 @@ int64_t glo_flux_select(const double *params, int64_t n_sets,
  * narrow to split).  The tests require it to stay 0. */
 long glo_unconverged(void);
 
+/* General ellipsoids: semi-axes a, b, c (stellar radii) along the body axes
+ * x', y', z', orientation angles zeta, eta, xi (R = Rx(zeta) Ry(eta) Rz(xi),
+ * Section 2 eq. coord-map), impact parameter, a/R*, P, t0, Kipping q1, q2,
+ * and `locked` (1: the tidally-locked coordinate map of Appendix B). */
+enum { GLO_E_RA, GLO_E_RB, GLO_E_RC, GLO_E_ZETA, GLO_E_ETA, GLO_E_XI, GLO_E_B, GLO_E_ARS, GLO_E_P,
+       GLO_E_T0, GLO_E_Q1, GLO_E_Q2, GLO_E_LOCKED, GLO_E_NPARAM };
+
+/* Centre (x, y, z), unit major axis u_hat, unit minor axis s_hat and the two
+ * semi-axes (major, minor) of the sky shadow at time t; returns 1 when the
+ * planet is on the observer's side. */
+int glo_geometry_ell(const double p[GLO_E_NPARAM], double t, double out[9]);
+int glo_flux_ell(const double p[GLO_E_NPARAM], double t, double t_exp, int n_ss, double tol, double *out);
+int64_t glo_flux_batch_ell(const double *params, int64_t n_sets, const double *times, const int64_t *offsets,
+                           int64_t n_times, const int32_t *n_ss, const double *t_exp, double tol, double *out,
+                           int nthreads);
+
 /* Number of OpenMP threads a batch call with nthreads <= 0 would use. */
 int glo_max_threads(void);
 

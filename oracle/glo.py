@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libglo.so")
 
 K, F, THETA, PHI, B, ARS, P, T0, Q1, Q2 = range(10)
 NPARAM = 10
+# general ellipsoids
+E_RA, E_RB, E_RC, E_ZETA, E_ETA, E_XI, E_B, E_ARS, E_P, E_T0, E_Q1, E_Q2, E_LOCKED = range(13)
+E_NPARAM = 13
 INNER_CLOSED, INNER_ADAPTIVE = 0, 1
 DEFAULT_TOL = 1e-14
 
@@ -55,6 +58,10 @@ def lib():
         L.glo_occulted.restype = d
         L.glo_flux.argtypes = [dp, d, d, i, d, dp]
         L.glo_flux.restype = i
+        L.glo_geometry_ell.argtypes = [dp, d, dp]
+        L.glo_geometry_ell.restype = i
+        L.glo_flux_batch_ell.argtypes = [dp, i64, dp, i64p, i64, i32p, dp, d, dp, i]
+        L.glo_flux_batch_ell.restype = i64
         L.glo_flux_batch.argtypes = [dp, i64, dp, i64p, i64, i32p, dp, d, dp, i]
         L.glo_flux_batch.restype = i64
         L.glo_flux_select.argtypes = [dp, i64, dp, i64p, i64, i32p, dp, d,
@@ -158,3 +165,30 @@ def unconverged() -> int:
 
 def max_threads() -> int:
     return lib().glo_max_threads()
+
+
+def geometry_ell(p, t: float):
+    """(front, centre (x, y, z), u_hat (major axis), s_hat (minor), k_major, k_minor)."""
+    out = np.zeros(9)
+    pp = np.ascontiguousarray(p, dtype=np.float64)
+    front = lib().glo_geometry_ell(_dp(pp), float(t), _dp(out))
+    return bool(front), out[0:3].copy(), out[3:5].copy(), out[5:7].copy(), out[7], out[8]
+
+
+def flux_batch_ell(params, times, offsets=None, n_ss=None, t_exp=None, tol=DEFAULT_TOL, nthreads=0):
+    """Oracle over a batch of general ellipsoids (params [E_NPARAM, n_sets])."""
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    assert params.shape[0] == E_NPARAM
+    n_sets = params.shape[1]
+    times = np.ascontiguousarray(times, dtype=np.float64)
+    off = None if offsets is None else np.ascontiguousarray(offsets, dtype=np.int64)
+    nss = None if n_ss is None else np.ascontiguousarray(n_ss, dtype=np.int32)
+    te = None if t_exp is None else np.ascontiguousarray(t_exp, dtype=np.float64)
+    n_out = n_sets * times.size if off is None else int(off[-1])
+    out = np.empty(n_out)
+    lib().glo_flux_batch_ell(_dp(params), n_sets, _dp(times),
+                             None if off is None else off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                             times.size if off is None else 0,
+                             None if nss is None else nss.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                             None if te is None else _dp(te), float(tol), _dp(out), int(nthreads))
+    return out if off is not None else out.reshape(n_sets, times.size)

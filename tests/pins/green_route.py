@@ -49,6 +49,36 @@ def paper_deltas(k, f, theta, phi):
     return dx, dy1, dy2
 
 
+def paper_deltas_ell(a, b, c, zeta, eta, xi):
+    """(dx, dy1, dy2) of eqs. dx, dy1, dy2 for a triaxial ellipsoid with
+    semi-axes a, b, c along x', y', z' and R = Rx(zeta) Ry(eta) Rz(xi)."""
+    R = rx(zeta) @ ry(eta) @ rz(xi)
+    r1, r2, r3, r4, r5, r6, r7, r8, r9 = R.ravel()
+    dx = math.sqrt(a * a * r1 * r1 + b * b * r4 * r4 + c * c * r7 * r7)
+    dy1 = (a * a * r1 * r2 + b * b * r4 * r5 + c * c * r7 * r8) / dx
+    dy2 = math.sqrt(a * a * b * b * r9 * r9 + a * a * c * c * r6 * r6 + b * b * c * c * r3 * r3) / dx
+    return dx, dy1, dy2
+
+
+def paper_deltas_locked(a, b, c, zeta, eta, xi, alpha, beta):
+    """(dx, dy1, dy2) of the tidally-locked eqs. dx-locked, dy1-locked and
+    dy2-locked (Appendix B), term by term as printed."""
+    R = rx(zeta) @ ry(eta) @ rz(xi)
+    r1, r2, r3, r4, r5, r6, r7, r8, r9 = R.ravel()
+    sa, ca, sb, cb = math.sin(alpha), math.cos(alpha), math.sin(beta), math.cos(beta)
+    p1 = sb * (r3 * ca + r2 * sa) - r1 * cb
+    p2 = sb * (r6 * ca + r5 * sa) - r4 * cb
+    p3 = sb * (r9 * ca + r8 * sa) - r7 * cb
+    dx = math.sqrt(a * a * p1 * p1 + b * b * p2 * p2 + c * c * p3 * p3)
+    dy1 = (a * a * p1 * (r3 * sa - r2 * ca) + b * b * p2 * (r6 * sa - r5 * ca)
+           + c * c * p3 * (r9 * sa - r8 * ca)) / dx
+    w1 = r7 * sb + cb * (r9 * ca + r8 * sa)
+    w2 = r4 * sb + cb * (r6 * ca + r5 * sa)
+    w3 = r1 * sb + cb * (r3 * ca + r2 * sa)
+    dy2 = math.sqrt(a * a * b * b * w1 * w1 + a * a * c * c * w2 * w2 + b * b * c * c * w3 * w3) / dx
+    return dx, dy1, dy2
+
+
 def paper_centre(b, d, period, t0, t):
     """(x0, y0) and the line-of-sight coordinate of the planet centre."""
     alpha = 2.0 * math.pi * (t - t0) / period
