@@ -94,6 +94,35 @@ gl_status gl_lightcurve_batch(gl_ctx *ctx, const double *params, int64_t n_sets,
                               int64_t n_times, const int32_t *n_ss,
                               const double *t_exp, double *out, void *stream);
 
+/* General-ellipsoid parameter block rows (SoA, double[GL_E_NPARAM][n_sets]):
+ *  GL_E_RA, GL_E_RB, GL_E_RC  semi-axes a, b, c (stellar radii) along the
+ *            body axes x', y', z', each in (0, 1)
+ *  GL_E_ZETA, GL_E_ETA, GL_E_XI  orientation, rad: R = Rx(zeta) Ry(eta) Rz(xi)
+ *            (Section 2, eq. coord-map)
+ *  GL_E_B, GL_E_ARS, GL_E_P, GL_E_T0, GL_E_Q1, GL_E_Q2  as GL_B ... GL_Q2
+ *            (a/R* > 1 + max(a, b, c))
+ *  GL_E_LOCKED  0: the body keeps its orientation (eq. coord-map); 1: tidally
+ *            locked, body coordinates R Rx(-alpha) Ry(beta) (x - x_c)
+ *            (Appendix B), so the shadow turns with the orbital phase.
+ * The oblate block is the case b = c = k, a = k(1 - f), zeta = 0,
+ * eta = pi/2 - theta, xi = phi, locked = 0. */
+enum { GL_E_RA, GL_E_RB, GL_E_RC, GL_E_ZETA, GL_E_ETA, GL_E_XI, GL_E_B, GL_E_ARS, GL_E_P, GL_E_T0,
+       GL_E_Q1, GL_E_Q2, GL_E_LOCKED, GL_E_NPARAM };
+
+/* Light curves of triaxial planets (Section 2 for any a, b, c and orientation:
+ * the projected ellipse of eqs. dx, dy1, dy2; Appendix B for tidally-locked
+ * planets: eqs. dx-locked, dy1-locked, dy2-locked evaluated at each
+ * sub-sample's orbital phase).  Arguments, layout, window, supersampling,
+ * status word and errors as gl_lightcurve_batch, with params
+ * double[GL_E_NPARAM][n_sets]; a set's domain error (a semi-axis outside
+ * (0, 1), a/R* <= 1 + max(a, b, c), locked not 0 or 1, ...) gives NaN
+ * outputs.  Free rotators run the exact path's work lists; locked sets are
+ * evaluated by its fused per-chunk kernel.  Returns GL_OK once enqueued. */
+gl_status gl_lightcurve_batch_ellipsoid(gl_ctx *ctx, const double *params, int64_t n_sets,
+                                        const double *times, const int64_t *offsets,
+                                        int64_t n_times, const int32_t *n_ss,
+                                        const double *t_exp, double *out, void *stream);
+
 /* Allocation-free variant of gl_lightcurve_batch, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  Same arguments, layout and results (up

@@ -62,8 +62,13 @@ struct SetConst {
     double inv_phi;        // 1 / Phi
     double t_exp;          // exposure (days)
     double sx, sy;         // unit vector of the projected spin axis (minor axis direction)
+    // general ellipsoids (zero for the oblate parameter block)
+    double rot[9];         // R(zeta, eta, xi) = Rx Ry Rz, row major (r1..r9)
+    double ax2[3];         // a^2, b^2, c^2
+    double sb, cb;         // sin(beta), cos(beta)
     int n_ss;              // midpoint sub-samples per output
     int valid;             // 0: domain error, outputs are NaN
+    int locked;            // 1: tidally locked, the shadow turns with the orbit
 };
 
 // ---------------------------------------------------------------- helpers
@@ -252,6 +257,75 @@ GL_HD void projected_ellipse(double k, double f, double theta, double phi,
     C = sqrt(a2 * b2 * r9 * r9 + a2 * c2 * r6 * r6 + b2 * c2 * r3 * r3) / A;
 }
 
+// The shape terms derived from (dx, dy1, dy2) and the major semi-axis kmaj of
+// the shadow: area, second moments and the coefficients of the singularity
+// bound (zero_cosh_bound).
+GL_HD void shape_terms(SetConst& s, double kmaj)
+{
+    s.AC = s.A * s.C;
+    s.M2 = s.A * s.A + s.B * s.B + s.C * s.C;
+    s.K3 = 0.5 * (s.A * s.A + s.B * s.B - s.C * s.C);
+    s.K4 = s.B * s.C;
+    s.k = kmaj;
+    const double kq = s.AC / kmaj;  // minor semi-axis of the projected ellipse
+    s.zA = (kmaj - kq) * (kmaj + kq);
+    s.z2A_inv = s.zA > 1e-14 * kmaj * kmaj ? 1.0 / (2.0 * s.zA) : 0.0;
+    s.zC0 = kq * kq - 1.0;
+}
+
+// Semi-axes of the curve (A cos th, B cos th + C sin th): the square roots of
+// the eigenvalues of [[A^2, AB], [AB, B^2 + C^2]] (trace M2, determinant
+// (AC)^2).  Returns the major one; (ux, uy) is the unit minor-axis direction.
+GL_HD double shadow_axes(double A, double B, double C, double& ux, double& uy)
+{
+    const double s11 = A * A, s12 = A * B, s22 = B * B + C * C;
+    const double rad = sqrt(sqr(0.5 * (s11 - s22)) + s12 * s12);
+    const double hi = 0.5 * (s11 + s22) + rad;
+    const double lo = (A * C) * (A * C) / hi;
+    double vx, vy;  // eigenvector of lo from the better conditioned row
+    if (fabs(s11 - lo) >= fabs(s22 - lo)) {
+        vx = -s12;
+        vy = s11 - lo;
+    } else {
+        vx = s22 - lo;
+        vy = -s12;
+    }
+    const double n = sqrt(vx * vx + vy * vy);
+    ux = n > 0.0 ? vx / n : 1.0;
+    uy = n > 0.0 ? vy / n : 0.0;
+    return sqrt(hi);
+}
+
+// Orbit, transit window and limb darkening of a set: b, d = a/R*, P, t0,
+// Kipping q1, q2; kreach bounds the shadow's semi-axes over the orbit.
+GL_HD void orbit_and_limb(SetConst& s, double kreach, double b, double d, double P, double t0, double q1,
+                          double q2)
+{
+    // orbit (eq. coord-map): sin(beta) = b/d, x0 = d cos(alpha) sin(beta)
+    s.xb = d * (b / d);
+    s.d = d;
+    s.P = P;
+    s.inv_P = 1.0 / P;
+    s.t0 = t0;
+    s.w_orb = kTwoPi / P;
+    // overlap needs rho^2 = b^2 cos^2(alpha) + d^2 sin^2(alpha) < (1 + k)^2 with
+    // cos(alpha) > 0, i.e. sin^2(alpha) < ((1+k)^2 - b^2) / (d^2 - b^2)
+    const double num = (1.0 + kreach) * (1.0 + kreach) - b * b;
+    if (num > 0.0) {
+        const double sa = fmin(1.0, sqrt(num / ((d - b) * (d + b))));
+        s.half_win = (asin(sa) / s.w_orb) * (1.0 + 1e-9) + 1e-12 * P;
+    } else {
+        s.half_win = -1e300;  // never overlaps the disk
+    }
+    // Kipping (2013) q -> u, then I = c0 + c1 mu + c2 r^2
+    const double sq = sqrt(q1);
+    const double u1 = 2.0 * sq * q2, u2 = sq * (1.0 - 2.0 * q2);
+    s.c0 = 1.0 - u1 - 2.0 * u2;
+    s.c1 = u1 + 2.0 * u2;
+    s.c2 = u2;
+    s.inv_phi = 1.0 / (kPi * (1.0 - u1 / 3.0 - u2 / 6.0));
+}
+
 // Builds SetConst from the parameter block values (k, f, theta, phi, b, a/R*,
 // P, t0, q1, q2).  Returns false on a domain error.
 GL_HD bool make_set_const(const double* p, double t_exp, int n_ss, SetConst& s)
@@ -266,6 +340,10 @@ GL_HD bool make_set_const(const double* p, double t_exp, int n_ss, SetConst& s)
     s.valid = ok ? 1 : 0;
     s.n_ss = n_ss;
     s.t_exp = t_exp;
+    s.locked = 0;
+    for (int i = 0; i < 9; ++i) s.rot[i] = 0.0;
+    s.ax2[0] = s.ax2[1] = s.ax2[2] = 0.0;
+    s.sb = s.cb = 0.0;
     if (!ok) return false;
     projected_ellipse(k, f, theta, phi, s.A, s.B, s.C);
     {
@@ -274,42 +352,92 @@ GL_HD bool make_set_const(const double* p, double t_exp, int n_ss, SetConst& s)
         s.sx = cp;
         s.sy = -sp;
     }
-    s.AC = s.A * s.C;
-    s.M2 = s.A * s.A + s.B * s.B + s.C * s.C;
-    s.K3 = 0.5 * (s.A * s.A + s.B * s.B - s.C * s.C);
-    s.K4 = s.B * s.C;
-    s.k = k;
-    {
-        const double kq = s.AC / k;  // minor semi-axis of the projected ellipse
-        s.zA = (k - kq) * (k + kq);
-        s.z2A_inv = s.zA > 1e-14 * k * k ? 1.0 / (2.0 * s.zA) : 0.0;
-        s.zC0 = kq * kq - 1.0;
-    }
-    // orbit (eq. coord-map): sin(beta) = b/d, x0 = d cos(alpha) sin(beta)
-    s.xb = d * (b / d);
-    s.d = d;
-    s.P = P;
-    s.inv_P = 1.0 / P;
-    s.t0 = t0;
-    s.w_orb = kTwoPi / P;
-    // overlap needs rho^2 = b^2 cos^2(alpha) + d^2 sin^2(alpha) < (1 + k)^2 with
-    // cos(alpha) > 0, i.e. sin^2(alpha) < ((1+k)^2 - b^2) / (d^2 - b^2)
-    const double num = (1.0 + k) * (1.0 + k) - b * b;
-    if (num > 0.0) {
-        const double sa = fmin(1.0, sqrt(num / ((d - b) * (d + b))));
-        s.half_win = (asin(sa) / s.w_orb) * (1.0 + 1e-9) + 1e-12 * P;
-    } else {
-        s.half_win = -1e300;  // never overlaps the disk
-    }
-    // Kipping (2013) q -> u, then I = c0 + c1 mu + c2 r^2
-    const double sq = sqrt(q1);
-    const double u1 = 2.0 * sq * q2, u2 = sq * (1.0 - 2.0 * q2);
-    s.c0 = 1.0 - u1 - 2.0 * u2;
-    s.c1 = u1 + 2.0 * u2;
-    s.c2 = u2;
-    s.inv_phi = 1.0 / (kPi * (1.0 - u1 / 3.0 - u2 / 6.0));
+    // the equatorial radius k is the shadow's major semi-axis (f >= 0)
+    shape_terms(s, k);
+    orbit_and_limb(s, k, b, d, P, t0, q1, q2);
     return true;
 }
+
+// ---------------------------------------------------------------- general ellipsoids
+// Rows of the general parameter block: semi-axes a, b, c (stellar radii)
+// along x', y', z'; orientation zeta, eta, xi (R = Rx(zeta) Ry(eta) Rz(xi),
+// Section 2 eq. coord-map); impact parameter, a/R*, P, t0, Kipping q1, q2;
+// `locked` = 1 for the tidally-locked coordinate map of Appendix B.
+constexpr int kEllParams = 13;
+
+// (dx, dy1, dy2) of the shadow of the body whose body coordinates are
+// M (x - x_c), from the first two columns u, v and the third w of M:
+// dx = |D u|, dy1 = (D u . D v) / dx, dy2 = |D u x D v| / dx with
+// D = diag(a, b, c), and D u x D v = abc (w_x / a, w_y / b, w_z / c).  With
+// M = R these are eqs. dx, dy1, dy2; with M = R Rx(-alpha) Ry(beta) they are
+// eqs. dx-locked, dy1-locked, dy2-locked.
+GL_HD void deltas_of_map(const double* ax2, const double* u, const double* v, const double* w,
+                         double& A, double& B, double& C)
+{
+    const double a2 = ax2[0], b2 = ax2[1], c2 = ax2[2];
+    A = sqrt(a2 * u[0] * u[0] + b2 * u[1] * u[1] + c2 * u[2] * u[2]);
+    B = (a2 * u[0] * v[0] + b2 * u[1] * v[1] + c2 * u[2] * v[2]) / A;
+    C = sqrt(a2 * b2 * w[2] * w[2] + a2 * c2 * w[1] * w[1] + b2 * c2 * w[0] * w[0]) / A;
+}
+
+GL_HD bool make_set_const_ell(const double* p, double t_exp, int n_ss, SetConst& s)
+{
+    const double ra = p[0], rb = p[1], rc = p[2], zeta = p[3], eta = p[4], xi = p[5];
+    const double b = p[6], d = p[7], P = p[8], t0 = p[9], q1 = p[10], q2 = p[11], lk = p[12];
+    bool ok = true;
+    for (int i = 0; i < kEllParams; ++i) ok = ok && finite_d(p[i]);
+    const double amax = fmax(ra, fmax(rb, rc));
+    ok = ok && (ra > 0.0) && (ra < 1.0) && (rb > 0.0) && (rb < 1.0) && (rc > 0.0) && (rc < 1.0) &&
+         (d > 1.0 + amax) && (fabs(b) < d) && (P > 0.0) && (q1 >= 0.0) && (q1 <= 1.0) && (q2 >= 0.0) &&
+         (q2 <= 1.0) && (lk == 0.0 || lk == 1.0) && finite_d(t_exp) && (t_exp >= 0.0) && (n_ss >= 1) &&
+         (n_ss <= 64);
+    s.valid = ok ? 1 : 0;
+    s.n_ss = n_ss;
+    s.t_exp = t_exp;
+    s.locked = lk == 1.0 ? 1 : 0;
+    if (!ok) return false;
+    double sz, cz, se, ce, sx, cx;
+    sincos_pi(wrap_pi(zeta), sz, cz);
+    sincos_pi(wrap_pi(eta), se, ce);
+    sincos_pi(wrap_pi(xi), sx, cx);
+    // Ry(eta) Rz(xi), then Rx(zeta) mixes its second and third rows
+    const double m1[3] = {ce * cx, -ce * sx, se};
+    const double m2[3] = {sx, cx, 0.0};
+    const double m3[3] = {-se * cx, se * sx, ce};
+    for (int j = 0; j < 3; ++j) {
+        s.rot[j] = m1[j];
+        s.rot[3 + j] = cz * m2[j] - sz * m3[j];
+        s.rot[6 + j] = sz * m2[j] + cz * m3[j];
+    }
+    s.ax2[0] = ra * ra;
+    s.ax2[1] = rb * rb;
+    s.ax2[2] = rc * rc;
+    s.sb = b / d;
+    s.cb = sqrt((1.0 - s.sb) * (1.0 + s.sb));
+    // the set-level shadow: exact when not locked; when locked, the shadow at
+    // mid-transit (the per-sample one comes from lock_at)
+    const double* R = s.rot;
+    double u[3], v[3], w[3];
+    for (int i = 0; i < 3; ++i) {
+        const double r1 = R[3 * i], r2 = R[3 * i + 1], r3 = R[3 * i + 2];
+        if (s.locked) {  // M = R Rx(0) Ry(beta)
+            u[i] = r1 * s.cb - r3 * s.sb;
+            v[i] = r2;
+            w[i] = r1 * s.sb + r3 * s.cb;
+        } else {
+            u[i] = r1;
+            v[i] = r2;
+            w[i] = r3;
+        }
+    }
+    deltas_of_map(s.ax2, u, v, w, s.A, s.B, s.C);
+    const double kmaj = shadow_axes(s.A, s.B, s.C, s.sx, s.sy);
+    shape_terms(s, kmaj);
+    // a locked shadow changes over the orbit: its window uses the largest semi-axis
+    orbit_and_limb(s, s.locked ? amax : kmaj, b, d, P, t0, q1, q2);
+    return true;
+}
+
 
 // Time offset from the nearest mid-transit, in (-P/2, P/2].
 GL_HD double phase_time(const SetConst& s, double t)
@@ -318,6 +446,29 @@ GL_HD double phase_time(const SetConst& s, double t)
     // is half a period from a transit, with the planet behind the star)
     const double dt = t - s.t0;
     return dt - s.P * rint(dt * s.inv_P);
+}
+
+// Per-sample shadow of a locked set at time t (Appendix B): body coordinates
+// R Rx(-alpha) Ry(beta) (x - x_c) at the sample's orbital phase alpha; the
+// centre follows from centre_at with the same alpha.
+GL_HD void lock_at(const SetConst& s, double t, SetConst& o)
+{
+    o = s;
+    const double alpha = s.w_orb * phase_time(s, t);
+    double sa, ca;
+    sincos_pi(alpha, sa, ca);
+    const double sb = s.sb, cb = s.cb;
+    double u[3], v[3], w[3];
+    for (int i = 0; i < 3; ++i) {
+        const double r1 = s.rot[3 * i], r2 = s.rot[3 * i + 1], r3 = s.rot[3 * i + 2];
+        const double g = r2 * sa + r3 * ca;
+        u[i] = r1 * cb - sb * g;
+        v[i] = r2 * ca - r3 * sa;
+        w[i] = r1 * sb + cb * g;
+    }
+    deltas_of_map(s.ax2, u, v, w, o.A, o.B, o.C);
+    const double kmaj = shadow_axes(o.A, o.B, o.C, o.sx, o.sy);
+    shape_terms(o, kmaj);
 }
 
 // ---------------------------------------------------------------- work census
@@ -1374,11 +1525,7 @@ GL_HD SetConst sphere_of(const SetConst& s)
     c.A = r;
     c.B = 0.0;
     c.C = r;
-    c.AC = s.AC;
-    c.M2 = 2.0 * s.AC;
-    c.K3 = 0.0;
-    c.K4 = 0.0;
-    c.k = r;
+    shape_terms(c, r);  // a circle: M2 = 2 k^2 q, K3 = K4 = 0, zA = 0
     return c;
 }
 

@@ -214,7 +214,7 @@ __global__ void k_prep(const double* __restrict__ params, int64_t ld, int64_t n_
                        gl::SetConst* __restrict__ sc, int64_t* __restrict__ seg_begin,
                        int64_t* __restrict__ seg_len, int64_t* __restrict__ chunk_off,
                        Counters* __restrict__ ctr, int64_t cps_shared, int first, int last,
-                       gl::SetConst* __restrict__ sph)
+                       gl::SetConst* __restrict__ sph, int shape)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s == 0) {
@@ -229,13 +229,14 @@ __global__ void k_prep(const double* __restrict__ params, int64_t ld, int64_t n_
     for (int64_t i = s; i < (int64_t)kLists * kShards; i += (int64_t)gridDim.x * blockDim.x)
         ctr->lc[i / kShards][i % kShards].v = 0ull;
     if (s >= n_sets) return;
-    double p[GL_NPARAM];
-#pragma unroll
-    for (int i = 0; i < GL_NPARAM; ++i) p[i] = params[(int64_t)i * ld + s];
+    // shape 0: the oblate block (GL_NPARAM rows), 1: general ellipsoids
+    double p[gl::kEllParams];
+    const int rows = shape ? gl::kEllParams : GL_NPARAM;
+    for (int i = 0; i < rows; ++i) p[i] = params[(int64_t)i * ld + s];
     const int nss = n_ss ? n_ss[s] : 1;
     const double te = t_exp ? t_exp[s] : 0.0;
     gl::SetConst c;
-    const bool ok = gl::make_set_const(p, te, nss, c);
+    const bool ok = shape ? gl::make_set_const_ell(p, te, nss, c) : gl::make_set_const(p, te, nss, c);
     int64_t b, e;
     unsigned int flag = ok ? 0u : 1u;
     if (offsets) {
@@ -558,6 +559,14 @@ k_window_grid(const double* __restrict__ times, int64_t n_times, int64_t cps,
         chunk_set[c] = (int)s;
     }
     if (!lists || !any) return;
+    if (S.locked) {
+        // a locked shadow changes per sample: the fused kernel evaluates it
+        if (lane < nk && my_mask) {
+            chunk_fb[c] = 0;
+            to_fused(ctr, P, chunk_fb, c);
+        }
+        return;
+    }
     const int cnt = lane < nk ? __popcll(my_mask) * S.n_ss : 0;
     const gl::ChunkPos cp = gl::chunk_pos(true, ob, lc0 + lane);
     const int shard = (int)(blockIdx.x % kShards);
@@ -585,7 +594,7 @@ k_window(const double* __restrict__ times, int64_t n_sets,
     int64_t s = 0;
     if (c_first < total) s = uniform64(gl::set_of_chunk(chunk_off, n_sets, c_first));
     // lane k (k < kWinChunks) collects chunk k's description for the lists
-    int cnt_l = 0, nss_l = 0, set_l = 0;
+    int cnt_l = 0, nss_l = 0, set_l = 0, lock_l = 0;
     unsigned long long mask_l = 0ull, any = 0ull;
     int64_t i0_l = 0, t0_l = 0;
 #pragma unroll
@@ -620,14 +629,20 @@ k_window(const double* __restrict__ times, int64_t n_sets,
             cnt_l = __popcll(m) * S.n_ss;
             nss_l = S.n_ss;
             set_l = (int)s;
+            lock_l = S.locked;
             const gl::ChunkPos cp = gl::chunk_pos(false, seg_begin[s], c - chunk_off[s]);
             i0_l = cp.out0;
             t0_l = cp.time0;
         }
     }
     if (!lists || !any) return;
-    window_lists(ctr, P, chunk_fb, (int)(g % kShards), c_first + lane, cnt_l, mask_l, i0_l, t0_l, nss_l,
-                 set_l);
+    // chunks of locked sets (per-sample shadow) go to the fused kernel
+    window_lists(ctr, P, chunk_fb, (int)(g % kShards), c_first + lane, lock_l ? 0 : cnt_l, mask_l, i0_l, t0_l,
+                 nss_l, set_l);
+    if (lock_l && mask_l) {
+        chunk_fb[c_first + lane] = 0;
+        to_fused(ctr, P, chunk_fb, c_first + lane);
+    }
 }
 
 // Classification: one wavefront per group of up to 64 sub-samples of one
@@ -1438,10 +1453,14 @@ struct Counter {
 
 // Instantaneous flux, easy part only: returns false (and leaves F) when the
 // sample needs the intersection machinery.
-template <bool CENSUS>
-__device__ __attribute__((noinline)) bool flux_easy(const gl::SetConst& S, double t, double& F,
+// LOCK: a tidally-locked set, whose shadow is rebuilt for the sample's phase.
+template <bool CENSUS, bool LOCK>
+__device__ __attribute__((noinline)) bool flux_easy(const gl::SetConst& S0, double t, double& F,
                                           Counter<CENSUS>& cnt)
 {
+    gl::SetConst Ls;
+    if (LOCK) gl::lock_at(S0, t, Ls);
+    const gl::SetConst& S = LOCK ? Ls : S0;
     double x0, y0;
     gl::Census ct;
     int cls = gl::CLS_OUT;
@@ -1464,9 +1483,12 @@ __device__ __attribute__((noinline)) bool flux_easy(const gl::SetConst& S, doubl
     return easy;
 }
 
-template <bool CENSUS>
-__device__ __attribute__((noinline)) double flux_hard(const gl::SetConst& S, double t, Counter<CENSUS>& cnt)
+template <bool CENSUS, bool LOCK>
+__device__ __attribute__((noinline)) double flux_hard(const gl::SetConst& S0, double t, Counter<CENSUS>& cnt)
 {
+    gl::SetConst Ls;
+    if (LOCK) gl::lock_at(S0, t, Ls);
+    const gl::SetConst& S = LOCK ? Ls : S0;
     double x0, y0;
     (void)gl::centre_at(S, t, x0, y0);
     if (CENSUS) {
@@ -1541,7 +1563,8 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
                         const int o = (int)(((float)f + 0.5f) * inv_nss_f), j = f - o * nss;
                         const double t = times[tb + lds_idx[o]] + (((double)j + 0.5) * inv_nss - 0.5) * S.t_exp;
                         double F = 1.0;
-                        hard = !flux_easy<CENSUS>(S, t, F, cnt);
+                        hard = !(S.locked ? flux_easy<CENSUS, true>(S, t, F, cnt)
+                                          : flux_easy<CENSUS, false>(S, t, F, cnt));
                         if (!hard) lds_f[f] = F;
                     }
                     const unsigned long long hm = __ballot(hard);
@@ -1556,7 +1579,7 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
                         const int f = lds_def[k];
                         const int o = (int)(((float)f + 0.5f) * inv_nss_f), j = f - o * nss;
                         const double t = times[tb + lds_idx[o]] + (((double)j + 0.5) * inv_nss - 0.5) * S.t_exp;
-                        lds_f[f] = flux_hard<CENSUS>(S, t, cnt);
+                        lds_f[f] = S.locked ? flux_hard<CENSUS, true>(S, t, cnt) : flux_hard<CENSUS, false>(S, t, cnt);
                     }
                 }
                 __syncthreads();
@@ -1581,7 +1604,11 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
                     if (act) {
                         off = lds_idx[o];
                         const double t = times[tb + off] + frac * S.t_exp;
-                        if (!flux_easy<CENSUS>(S, t, F, cnt)) F = flux_hard<CENSUS>(S, t, cnt);
+                        if (S.locked) {
+                            if (!flux_easy<CENSUS, true>(S, t, F, cnt)) F = flux_hard<CENSUS, true>(S, t, cnt);
+                        } else if (!flux_easy<CENSUS, false>(S, t, F, cnt)) {
+                            F = flux_hard<CENSUS, false>(S, t, cnt);
+                        }
                     }
                     lds_f[lane] = F;
                     __syncthreads();
@@ -1641,6 +1668,7 @@ struct gl_ctx {
         int waves;
         void* ws;
         int passes;
+        int shape;
     } key{};
     bool have_graph = false;
     // work lists of the exact path (capacities in entries; 0 = default)
@@ -1862,6 +1890,7 @@ struct Batch {
     const float* gate_table = nullptr;
     const uint8_t* gate_zero = nullptr;
     double gate_k = 0.0;
+    int shape = 0;  // 0: oblate parameter block, 1: general ellipsoids
 };
 
 // ctx may be NULL (no message is kept)
@@ -1948,7 +1977,7 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     hipLaunchKernelGGL(k_prep, dim3(prep_blocks), dim3(256), 0, st, b.params, b.ld, b.n_sets,
                        b.offsets, b.n_times, b.n_ss, b.t_exp, ctx->sc, ctx->seg_begin,
                        ctx->seg_len, ctx->chunk_off, ctx->ctr, cps_shared, b.first, b.last,
-                       sur ? ctx->sc_sph : nullptr);
+                       sur ? ctx->sc_sph : nullptr, b.shape);
     if (!shared)
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, ctx->chunk_off, b.n_sets,
                            b.max_chunks, ctx->ctr);
@@ -2157,12 +2186,23 @@ void gl_ctx_destroy(gl_ctx* ctx)
     delete ctx;
 }
 
-gl_status gl_lightcurve_batch(gl_ctx* ctx, const double* params, int64_t n_sets,
-                              const double* times, const int64_t* offsets, int64_t n_times,
-                              const int32_t* n_ss, const double* t_exp, double* out,
-                              void* stream)
+}  // extern "C"
+
+namespace {
+
+// The exact path for either parameter block: plans and sizes the batch, then
+// replays the captured pipeline (captured again when the arguments change).
+gl_status lightcurve(gl_ctx* ctx, Batch& b)
 {
-    Batch b{params, n_sets, times, offsets, n_times, n_ss, t_exp, out, (hipStream_t)stream, 0};
+    const double* params = b.params;
+    const int64_t n_sets = b.n_sets;
+    const double* times = b.times;
+    const int64_t* offsets = b.offsets;
+    const int64_t n_times = b.n_times;
+    const int32_t* n_ss = b.n_ss;
+    const double* t_exp = b.t_exp;
+    double* out = b.out;
+    void* stream = (void*)b.stream;
     gl_status st = check_args(ctx, b);
     if (st != GL_OK) return st;
     GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
@@ -2184,6 +2224,7 @@ gl_status gl_lightcurve_batch(gl_ctx* ctx, const double* params, int64_t n_sets,
     k.waves = ctx->waves_per_cu;
     k.ws = ctx->masks;
     k.passes = ctx->passes;
+    k.shape = b.shape;
     if (!ctx->have_graph || !same_key(k, ctx->key)) {
         drop_graph(ctx);
         GL_HIP(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
@@ -2208,6 +2249,29 @@ gl_status gl_lightcurve_batch(gl_ctx* ctx, const double* params, int64_t n_sets,
     }
     GL_HIP(hipGraphLaunch(ctx->gexec, b.stream), "hipGraphLaunch");
     return GL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gl_status gl_lightcurve_batch(gl_ctx* ctx, const double* params, int64_t n_sets,
+                              const double* times, const int64_t* offsets, int64_t n_times,
+                              const int32_t* n_ss, const double* t_exp, double* out,
+                              void* stream)
+{
+    Batch b{params, n_sets, times, offsets, n_times, n_ss, t_exp, out, (hipStream_t)stream, 0};
+    return lightcurve(ctx, b);
+}
+
+gl_status gl_lightcurve_batch_ellipsoid(gl_ctx* ctx, const double* params, int64_t n_sets,
+                                        const double* times, const int64_t* offsets, int64_t n_times,
+                                        const int32_t* n_ss, const double* t_exp, double* out,
+                                        void* stream)
+{
+    Batch b{params, n_sets, times, offsets, n_times, n_ss, t_exp, out, (hipStream_t)stream, 0};
+    b.shape = 1;
+    return lightcurve(ctx, b);
 }
 
 gl_status gl_ctx_sync_status(gl_ctx* ctx)
@@ -2436,7 +2500,7 @@ gl_status gl_lightcurve_batch_snap(gl_ctx* ctx, int n_nodes, const double* param
     const int64_t cps_shared = shared ? (b.n_times + kChunk - 1) / kChunk : 0;
     hipLaunchKernelGGL(k_prep, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, s, params, n_sets, n_sets, offsets,
                        n_times, n_ss, t_exp, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off, ctx->ctr, cps_shared,
-                       1, 1, (gl::SetConst*)nullptr);
+                       1, 1, (gl::SetConst*)nullptr, 0);
     if (!shared)
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, ctx->chunk_off, n_sets, b.max_chunks, ctx->ctr);
     launch_window(ctx, b, s, 0, ctx->pipe);

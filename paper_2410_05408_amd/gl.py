@@ -21,12 +21,16 @@ STATUS_NAMES = {0: "GL_OK", -1: "GL_ERR_NULL", -2: "GL_ERR_SIZE", -3: "GL_ERR_DO
                 -4: "GL_ERR_DEVICE", -5: "GL_ERR_STATE", -6: "GL_ERR_NOMEM"}
 GL_K, GL_F, GL_THETA, GL_PHI, GL_B, GL_ARS, GL_P, GL_T0, GL_Q1, GL_Q2 = range(10)
 GL_NPARAM = 10
+(GL_E_RA, GL_E_RB, GL_E_RC, GL_E_ZETA, GL_E_ETA, GL_E_XI, GL_E_B, GL_E_ARS, GL_E_P, GL_E_T0, GL_E_Q1,
+ GL_E_Q2, GL_E_LOCKED) = range(13)
+GL_E_NPARAM = 13
 
 EXPORTED = ("gl_ctx_create", "gl_ctx_destroy", "gl_lightcurve_batch", "gl_ctx_sync_status",
             "gl_ctx_last_error", "gl_autotune", "gl_ctx_get_plan", "gl_ctx_set_plan",
             "gl_ctx_set_graph", "gl_ctx_set_capacity", "gl_ctx_set_timing", "gl_ctx_get_timing",
             "gl_ctx_get_stage_timing", "gl_census", "gl_flop_model", "gl_ctx_get_unconverged",
-            "gl_ctx_get_overflow", "gl_lightcurve_batch_noalloc", "gl_lightcurve_batch_snap", "gl_version")
+            "gl_ctx_get_overflow", "gl_lightcurve_batch_noalloc", "gl_lightcurve_batch_snap", "gl_version",
+            "gl_lightcurve_batch_ellipsoid")
 CENSUS_NAMES = ("sub_in_window", "whole_on_star", "intersecting", "off_star_in_window",
                 "trapezoid_nodes", "gk21_pieces", "newton_steps", "limb_arcs",
                 "nested_trapezoid_nodes", "ellipse_arcs", "unconverged_arcs")
@@ -59,6 +63,8 @@ def lib():
         batch_args = [vp, vp, i64, vp, vp, i64, vp, vp, vp, vp]
         L.gl_lightcurve_batch.argtypes = batch_args
         L.gl_lightcurve_batch.restype = i
+        L.gl_lightcurve_batch_ellipsoid.argtypes = batch_args
+        L.gl_lightcurve_batch_ellipsoid.restype = i
         L.gl_lightcurve_batch_snap.argtypes = [vp, i] + batch_args[1:]
         L.gl_lightcurve_batch_snap.restype = i
         L.gl_lightcurve_batch_noalloc.argtypes = batch_args[1:]
@@ -128,10 +134,10 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _validate(params, times, offsets, n_ss, t_exp, out):
+def _validate(params, times, offsets, n_ss, t_exp, out, rows=GL_NPARAM):
     import torch
     assert params.dtype == torch.float64 and params.is_cuda and params.is_contiguous()
-    assert params.dim() == 2 and params.shape[0] == GL_NPARAM
+    assert params.dim() == 2 and params.shape[0] == rows
     assert times.dtype == torch.float64 and times.is_cuda and times.is_contiguous()
     assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
     n_sets = params.shape[1]
@@ -154,6 +160,16 @@ def gl_lightcurve_batch(ctx, params, times, out, offsets=None, n_ss=None, t_exp=
     st = lib().gl_lightcurve_batch(ctx, _ptr(params), params.shape[1], _ptr(times), _ptr(offsets),
                                    times.numel(), _ptr(n_ss), _ptr(t_exp), _ptr(out),
                                    _stream_handle(stream))
+    _check(ctx, st)
+
+
+def gl_lightcurve_batch_ellipsoid(ctx, params, times, out, offsets=None, n_ss=None, t_exp=None,
+                                  stream=None) -> None:
+    """General ellipsoids: ``params`` float64 [13, n_sets] (rows GL_E_*)."""
+    _validate(params, times, offsets, n_ss, t_exp, out, rows=GL_E_NPARAM)
+    st = lib().gl_lightcurve_batch_ellipsoid(ctx, _ptr(params), params.shape[1], _ptr(times), _ptr(offsets),
+                                             times.numel(), _ptr(n_ss), _ptr(t_exp), _ptr(out),
+                                             _stream_handle(stream))
     _check(ctx, st)
 
 
@@ -307,6 +323,14 @@ class Context:
             n = params.shape[1] * times.numel() if offsets is None else times.numel()
             out = torch.empty(n, dtype=torch.float64, device=times.device)
         gl_lightcurve_batch(self.handle, params, times, out, offsets, n_ss, t_exp, stream)
+        return out
+
+    def batch_ellipsoid(self, params, times, out=None, offsets=None, n_ss=None, t_exp=None, stream=None):
+        import torch
+        if out is None:
+            n = params.shape[1] * times.numel() if offsets is None else times.numel()
+            out = torch.empty(n, dtype=torch.float64, device=times.device)
+        gl_lightcurve_batch_ellipsoid(self.handle, params, times, out, offsets, n_ss, t_exp, stream)
         return out
 
 

@@ -39,7 +39,7 @@ class Workload:
     Otherwise CSR: set ``s`` owns ``times[offsets[s]:offsets[s+1]]``.
     """
     name: str
-    params: np.ndarray                 # float64 [10, n_sets]
+    params: np.ndarray                 # float64 [10, n_sets] (general ellipsoids: [13, n_sets])
     times: np.ndarray                  # float64 [n_times] or [offsets[-1]]
     offsets: np.ndarray | None         # int64 [n_sets + 1] or None
     n_ss: np.ndarray                   # int32 [n_sets]
@@ -168,6 +168,70 @@ def surrogate_samples(n: int, seed: int, window: float = 0.6):
     t14 = full_duration(p[K], p[B], p[ARS], p[P])
     t = rng.uniform(-window, window, n) * t14
     return p, t
+
+
+# ---------------------------------------------------------------- general ellipsoids
+# Parameter block of the general model (SoA, ``float64[13][n_sets]``): semi-axes
+# a, b, c along the body axes x', y', z'; orientation zeta, eta, xi; b, a/R*,
+# P, t0, q1, q2; ``locked`` (1: tidally locked, Appendix B of the paper).
+E_NPARAM = 13
+(E_RA, E_RB, E_RC, E_ZETA, E_ETA, E_XI, E_B, E_ARS, E_P, E_T0, E_Q1, E_Q2,
+ E_LOCKED) = range(E_NPARAM)
+
+
+def draw_ellipsoids(rng: np.random.Generator, n: int, locked: bool) -> np.ndarray:
+    """Triaxial planets.  Free rotators (locked = 0): the walker priors' orbit
+    (b~U[0,0.9], a/R*~U[100,300], P = 500 d), each semi-axis U[0.03,0.15],
+    angles U[-pi,pi].  Tidally locked (locked = 1): close-in orbits
+    (b~U[0,0.8], a/R*~U[2.5,8], P~U[0.7,4] d) and tidal shapes, the axis
+    toward the star longest: c~U[0.06,0.15], b = c U[0.7,1], a = b U[0.7,1],
+    angles U[-0.3,0.3] about the equilibrium orientation.  q1, q2~U[0,1],
+    t0 = 0.  Drawn column by column in that order."""
+    p = np.empty((E_NPARAM, n))
+    if locked:
+        c = rng.uniform(0.06, 0.15, n)
+        b = c * rng.uniform(0.7, 1.0, n)
+        a = b * rng.uniform(0.7, 1.0, n)
+        p[E_RA], p[E_RB], p[E_RC] = a, b, c
+        for r in (E_ZETA, E_ETA, E_XI):
+            p[r] = rng.uniform(-0.3, 0.3, n)
+        p[E_B] = rng.uniform(0.0, 0.8, n)
+        p[E_ARS] = rng.uniform(2.5, 8.0, n)
+        p[E_P] = rng.uniform(0.7, 4.0, n)
+    else:
+        for r in (E_RA, E_RB, E_RC):
+            p[r] = rng.uniform(0.03, 0.15, n)
+        for r in (E_ZETA, E_ETA, E_XI):
+            p[r] = rng.uniform(-math.pi, math.pi, n)
+        p[E_B] = rng.uniform(0.0, 0.9, n)
+        p[E_ARS] = rng.uniform(100.0, 300.0, n)
+        p[E_P] = PERIOD_DAYS
+    p[E_Q1] = rng.uniform(0.0, 1.0, n)
+    p[E_Q2] = rng.uniform(0.0, 1.0, n)
+    p[E_T0] = 0.0
+    p[E_LOCKED] = 1.0 if locked else 0.0
+    return p
+
+
+def ellipsoid_batch(n_sets: int = 2048, n_w: int = 1500, seed: int = 6,
+                    locked_fraction: float = 0.5) -> Workload:
+    """Mixed batch of free and tidally-locked triaxial planets (the first
+    ``locked_fraction`` of the sets locked), CSR layout: each set samples
+    linspace(-T14, T14, n_w) of a sphere of its largest semi-axis, with
+    supersampling factor in {1, 5} and exposure = grid spacing."""
+    rng = np.random.default_rng(seed)
+    n_lock = int(round(locked_fraction * n_sets))
+    p = np.concatenate([draw_ellipsoids(rng, n_lock, True),
+                        draw_ellipsoids(rng, n_sets - n_lock, False)], axis=1)
+    kmax = np.max(p[E_RA:E_RC + 1], axis=0)
+    t14 = full_duration(kmax, p[E_B], p[E_ARS], p[E_P])
+    offsets = np.arange(n_sets + 1, dtype=np.int64) * n_w
+    g = np.linspace(-1.0, 1.0, n_w)
+    times = (t14[:, None] * g[None, :]).ravel()
+    t_exp = t14 * (g[1] - g[0])
+    ss = rng.choice(np.array([1, 5], np.int32), n_sets)
+    return Workload("ellipsoid_batch", p, times, offsets, ss, t_exp,
+                    {"seed": seed, "locked_sets": n_lock})
 
 
 def by_name(name: str, **kw) -> Workload:

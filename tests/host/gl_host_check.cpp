@@ -13,6 +13,9 @@
 //                                rule accepted at its last level unconverged
 //   gl_host_check snap N P T O   the same samples by the paper's integrator
 //                                (FP32 snap + Simpson, N nodes)
+//   gl_host_check ell P T O      general ellipsoids: P float64 [13][n], the
+//                                per-sample shadow of locked sets from
+//                                lock_at; prints the unconverged arc count
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -96,6 +99,36 @@ int main(int argc, char** argv)
         std::fclose(f);
         return ok ? 0 : 4;
     }
-    std::fprintf(stderr, "usage: gl_host_check math | flux params times out | snap nodes params times out\n");
+    if (argc == 5 && std::strcmp(argv[1], "ell") == 0) {
+        const std::vector<double> p = read_all(argv[2]), t = read_all(argv[3]);
+        const size_t n = t.size();
+        const int np = gl::kEllParams;
+        if (n == 0 || p.size() != (size_t)np * n) return 2;
+        std::vector<double> out(n);
+        gl::NoCensus nc;
+        for (size_t s = 0; s < n; ++s) {
+            double q[gl::kEllParams];
+            for (int i = 0; i < np; ++i) q[i] = p[(size_t)i * n + s];
+            gl::SetConst c;
+            if (!gl::make_set_const_ell(q, 0.0, 1, c)) {
+                out[s] = std::nan("");
+                continue;
+            }
+            if (c.locked) {
+                gl::SetConst l;
+                gl::lock_at(c, t[s], l);
+                out[s] = gl::flux_instant(l, t[s], nullptr, nc);
+            } else {
+                out[s] = gl::flux_instant(c, t[s], nullptr, nc);
+            }
+        }
+        std::printf("%d\n", nc.unconv);
+        FILE* f = std::fopen(argv[4], "wb");
+        if (!f) return 3;
+        const bool ok = std::fwrite(out.data(), sizeof(double), n, f) == n;
+        std::fclose(f);
+        return ok ? 0 : 4;
+    }
+    std::fprintf(stderr, "usage: gl_host_check math | flux params times out | snap nodes params times out | ell params times out\n");
     return 1;
 }

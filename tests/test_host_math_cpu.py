@@ -126,3 +126,29 @@ def test_paper_integrator_against_oracle(host_check, oracle, tmp_path):
         assert np.all(err[~inside & ~partial] == 0.0)  # centre beyond 1 + k: exactly 1
     assert errs[256] > errs[1024] > errs[8192]
     assert errs[8192] <= 4e-6 and errs[1024] <= 3e-5
+
+
+def host_ell(exe, tmp_path, params, times):
+    pf, tf, of = (str(tmp_path / n) for n in ("pe.bin", "te.bin", "oe.bin"))
+    np.ascontiguousarray(params, dtype=np.float64).tofile(pf)
+    np.ascontiguousarray(times, dtype=np.float64).tofile(tf)
+    r = subprocess.run([exe, "ell", pf, tf, of], check=True, capture_output=True, text=True)
+    return np.fromfile(of), int(r.stdout.split()[0])
+
+
+@pytest.mark.parametrize("locked", [False, True])
+def test_host_ellipsoid_matches_oracle(host_check, oracle, tmp_path, locked):
+    """General ellipsoids, free and tidally locked: the device arithmetic (the
+    paper's eqs. dx, dy1, dy2 and their locked forms, per sample when locked)
+    against the oracle's quadric shadow, instantaneous flux within 1e-9."""
+    rng = np.random.default_rng(31 + locked)
+    n = 2000
+    params = W.draw_ellipsoids(rng, n, locked)
+    kmax = params[W.E_RA:W.E_RC + 1].max(axis=0)
+    t14 = W.full_duration(kmax, params[W.E_B], params[W.E_ARS], params[W.E_P])
+    times = rng.uniform(-0.6, 0.6, n) * t14
+    got, unconv = host_ell(host_check, tmp_path, params, times)
+    ref = oracle.flux_batch_ell(params, times, offsets=np.arange(n + 1))
+    assert np.sum(got < 1.0) > n // 2
+    assert np.max(np.abs(got - ref)) <= 1e-9
+    assert unconv == 0
