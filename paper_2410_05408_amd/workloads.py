@@ -234,6 +234,64 @@ def ellipsoid_batch(n_sets: int = 2048, n_w: int = 1500, seed: int = 6,
                     {"seed": seed, "locked_sets": n_lock})
 
 
+# ---------------------------------------------------------------- MCMC walkers
+# Walker block (SoA, ``float64[10][n]``): the paper's fitting parameters
+# (Section 3, Table of priors): mean radius ratio r (geometric mean of the
+# three semi-axes), mu, nu (Appendix A), xi, b, d/R*, P, t0, q1, q2.
+W_NPARAM = 10
+W_R, W_MU, W_NU, W_XI, W_B, W_ARS, W_P, W_T0, W_Q1, W_Q2 = range(W_NPARAM)
+
+# The simulated JWST/NIRISS transit of Section 5.3: 2-minute cadence, 20 ppm
+# white noise, the fitted medians of the K2 fit (Table of fit results: r,
+# d/R*, P, b, q1, q2) with injected f = 0.15, eta = 0, xi = 29 deg.
+# f = 0.15 and eta = 0 are (mu, nu) = (0.85^2 - 0.15 * 1.85, 0) = (0.445, 0).
+JWST_CADENCE = 2.0 * MINUTE
+JWST_SIGMA = 20e-6
+JWST_TRUTH = {"r": 0.067208, "mu": 0.445, "nu": 0.0, "xi": math.radians(29.0), "b": 0.041605,
+              "ars": 231.24, "P": 542.08, "t0": 0.0, "q1": 0.26744, "q2": 0.39688}
+
+
+def jwst_truth() -> np.ndarray:
+    """The injected planet as a walker-block column, float64 [10, 1]."""
+    t = JWST_TRUTH
+    return np.array([[t["r"]], [t["mu"]], [t["nu"]], [t["xi"]], [t["b"]], [t["ars"]], [t["P"]],
+                     [t["t0"]], [t["q1"]], [t["q2"]]])
+
+
+def jwst_grid(half_span_days: float = 0.7):
+    """Times of the simulated visit (+-0.7 d around mid-transit at 2-min
+    cadence: the 0.8-d transit plus baseline), the exposure (one cadence)
+    and the supersampling factor used for it (3)."""
+    n = int(round(2.0 * half_span_days / JWST_CADENCE)) + 1
+    times = (np.arange(n) - (n - 1) / 2.0) * JWST_CADENCE
+    return times, JWST_CADENCE, 3
+
+
+def walker_ball(n: int, seed: int = 8):
+    """Walkers around the injected planet, as an MCMC run holds them after
+    burn-in: r~N(0.067208, 7e-4), xi~U[0, pi/2], b~N(0.0416, 0.1),
+    d/R*~N(231.24, 2), P~N(542.08, 2e-4), t0~N(0, 2e-3), q1~N(0.26744, 0.02),
+    q2~N(0.39688, 0.03); drawn in that order.  The (mu, nu) rows are left NaN:
+    they come from the prior sampler fed with the returned uniforms
+    uw [2, n] (u~U[0, 0.6], w~U[0.5, 1]: the corner of the prior with
+    f below about 0.5)."""
+    rng = np.random.default_rng(seed)
+    t = JWST_TRUTH
+    walk = np.full((W_NPARAM, n), np.nan)
+    walk[W_R] = rng.normal(t["r"], 7e-4, n)
+    walk[W_XI] = rng.uniform(0.0, 0.5 * math.pi, n)
+    walk[W_B] = rng.normal(t["b"], 0.1, n)
+    walk[W_ARS] = rng.normal(t["ars"], 2.0, n)
+    walk[W_P] = rng.normal(t["P"], 2e-4, n)
+    walk[W_T0] = rng.normal(0.0, 2e-3, n)
+    walk[W_Q1] = np.clip(rng.normal(t["q1"], 0.02, n), 0.0, 1.0)
+    walk[W_Q2] = np.clip(rng.normal(t["q2"], 0.03, n), 0.0, 1.0)
+    uw = np.empty((2, n))
+    uw[0] = rng.uniform(0.0, 0.6, n)
+    uw[1] = rng.uniform(0.5, 1.0, n)
+    return walk, uw
+
+
 def by_name(name: str, **kw) -> Workload:
     return {"single_transit": single_transit, "walker_batch": walker_batch,
             "high_cadence": high_cadence, "uneven_batch": uneven_batch}[name](**kw)

@@ -16,7 +16,30 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 from oracle import glo  # noqa: E402
+from oracle import mcmc  # noqa: E402
 from paper_2410_05408_amd import workloads  # noqa: E402
+
+JWST_NOISE_SEED = 541
+
+
+def make_jwst():
+    """The simulated JWST visit of Section 5.3: the oracle's light curve of the
+    injected planet plus seeded 20-ppm white noise."""
+    times, t_exp, n_ss = workloads.jwst_grid()
+    params = mcmc.params_from_walkers(workloads.jwst_truth())
+    model = glo.flux_batch(params, times, n_ss=np.array([n_ss], np.int32), t_exp=np.array([t_exp]),
+                           tol=1e-14)[0]
+    rng = np.random.default_rng(JWST_NOISE_SEED)
+    data = model + rng.normal(0.0, workloads.JWST_SIGMA, times.size)
+    path = os.path.join(HERE, "jwst_injected.txt")
+    with open(path, "w") as fh:
+        fh.write("# Simulated JWST/NIRISS visit (Section 5.3): 2-min cadence, 20 ppm white noise,\n")
+        fh.write("# K2 fit medians (Table of fit results) with injected f = 0.15, eta = 0, xi = 29 deg;\n")
+        fh.write(f"# oracle flux (n_ss = {n_ss}, t_exp = one cadence, tol 1e-14) plus N(0, sigma) noise,\n")
+        fh.write(f"# numpy default_rng({JWST_NOISE_SEED}).  columns: t_days data sigma model\n")
+        for row in zip(times, data, np.full(times.size, workloads.JWST_SIGMA), model):
+            fh.write(" ".join(f"{v:.17e}" for v in row) + "\n")
+    print("wrote", path)
 
 
 def main():
@@ -30,6 +53,7 @@ def main():
         for t, f in zip(w.times, out):
             fh.write(f"{t:.17e} {f:.17e}\n")
     print("wrote", path)
+    make_jwst()
 
 
 if __name__ == "__main__":
