@@ -123,6 +123,70 @@ gl_status gl_lightcurve_batch_ellipsoid(gl_ctx *ctx, const double *params, int64
                                         int64_t n_times, const int32_t *n_ss,
                                         const double *t_exp, double *out, void *stream);
 
+/* ---------------------------------------------------------------- MCMC glue
+ * Walker block rows (SoA, double[GL_W_NPARAM][n]): the fitting parameters of
+ * Section 3 (Table of priors):
+ *  GL_W_R    mean radius ratio r, the geometric mean of the three semi-axes
+ *            (r^3 = k^3 (1 - f) with equatorial radius k)
+ *  GL_W_MU, GL_W_NU  the reparameterised flattening and orientation of
+ *            Appendix A: mu = (f - 1)^2 + f (f - 2) cos(2 eta) in [-1, 1],
+ *            f = f_min + (1 - f_min) nu with f_min = 1 - sqrt((mu + 1) / 2),
+ *            nu in [0, 1)
+ *  GL_W_XI   orientation xi, rad (the oblate block's phi)
+ *  GL_W_B ... GL_W_Q2  as GL_B ... GL_Q2.
+ * The map to the oblate block takes eta in [0, pi/2] (mu fixes cos 2 eta
+ * only; the light curve does not see the sign of eta) and theta = pi/2 - eta. */
+enum { GL_W_R, GL_W_MU, GL_W_NU, GL_W_XI, GL_W_B, GL_W_ARS, GL_W_P, GL_W_T0, GL_W_Q1, GL_W_Q2,
+       GL_W_NPARAM };
+
+/* Inverse-transform draws from the (mu, nu) prior of Appendix A, whose density
+ * (eq. mu-nu-joint-density) makes f uniform on [0, 1] and eta cosine-
+ * distributed on [0, pi/2]: nu = u^2 / (u^2 - 2u + 2) inverts the marginal CDF
+ * of nu, mu inverts the conditional CDF F(mu | nu) at w.
+ *  uw     device double[2][n]: row 0 the uniforms u in [0, 1), row 1 the
+ *         uniforms w in [0, 1] (the caller draws them).
+ *  mu_nu  device double[2][n]: row 0 mu, row 1 nu; NaN for a pair outside
+ *         the ranges.
+ * Returns GL_ERR_NULL / GL_ERR_SIZE (n < 1), GL_ERR_DEVICE on a failed launch,
+ * else GL_OK once enqueued on stream. */
+gl_status gl_prior_mu_nu(const double *uw, int64_t n, double *mu_nu, void *stream);
+
+/* Walker block (device double[GL_W_NPARAM][n]) to the oblate parameter block
+ * (device double[GL_NPARAM][n]): k = r / cbrt(1 - f), f and eta from (mu, nu)
+ * as above, theta = pi/2 - eta, phi = xi, the other rows copied.  Values that
+ * leave the oblate block's domain (mu < -1, f >= 1, k >= 1, ...) are caught by
+ * the light-curve call as domain errors.  Returns as gl_prior_mu_nu. */
+gl_status gl_walkers_to_params(const double *walkers, int64_t n, double *params, void *stream);
+
+/* Per-walker white-noise likelihood of model light curves (Section 3's fit
+ * without its correlated-noise terms):
+ *   chi2[s] = sum_i ((data_i - model_s,i) / sigma_i)^2,
+ *   loglike[s] = -chi2[s] / 2 - sum_i log(sigma_i) - (N_s / 2) log(2 pi).
+ *  model    device double: shared grid [n_sets][n_times]; CSR indexed by
+ *           offsets (walker s owns [offsets[s], offsets[s+1])).
+ *  data, sigma  device double[n_times], indexed like one walker's grid
+ *           (shared) or like model (CSR); sigma > 0.
+ *  chi2, loglike  device double[n_sets]; either may be NULL, not both.
+ * The sums run in a fixed order (bitwise reproducible).  A walker whose model
+ * holds a NaN, or whose CSR segment is out of range, gets NaN.  Returns
+ * GL_ERR_NULL / GL_ERR_SIZE, GL_ERR_DEVICE on a failed launch, else GL_OK. */
+gl_status gl_loglike_of_model(const double *model, int64_t n_sets, const int64_t *offsets, int64_t n_times,
+                              const double *data, const double *sigma, double *chi2, double *loglike,
+                              void *stream);
+
+/* One MCMC likelihood evaluation for a batch of walkers: the walker block is
+ * converted (gl_walkers_to_params, into the context's workspace), the light
+ * curves are computed by the exact path into `model` (gl_lightcurve_batch's
+ * grid, supersampling and layout), and the per-walker chi^2 / log-likelihood
+ * against data / sigma follow (gl_loglike_of_model) -- all captured in one
+ * graph with the batch.  Walkers outside the domain give NaN light curves
+ * and NaN likelihoods, and set the status word (gl_ctx_sync_status).
+ * Returns GL_OK once enqueued, or the errors of gl_lightcurve_batch. */
+gl_status gl_loglike_batch(gl_ctx *ctx, const double *walkers, int64_t n_walkers, const double *times,
+                           const int64_t *offsets, int64_t n_times, const int32_t *n_ss, const double *t_exp,
+                           const double *data, const double *sigma, double *model, double *chi2,
+                           double *loglike, void *stream);
+
 /* Allocation-free variant of gl_lightcurve_batch, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  Same arguments, layout and results (up

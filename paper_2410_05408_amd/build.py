@@ -27,7 +27,8 @@ FLAGS = [
 def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     """Compiles the library to ``out``; ``defines`` are extra -D macros
     (e.g. GL_COMPUTE_WAVES_PER_EU=4)."""
-    srcs = [os.path.join(CSRC, "gl_lib.hip"), os.path.join(CSRC, "gl_mlp.hip"), os.path.join(CSRC, "gl_io.cpp")]
+    srcs = [os.path.join(CSRC, "gl_lib.hip"), os.path.join(CSRC, "gl_mlp.hip"),
+            os.path.join(CSRC, "gl_mcmc.hip"), os.path.join(CSRC, "gl_io.cpp")]
     cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], "-I", os.path.join(ROOT, "include"),
            "-I", CSRC, *srcs, "-o", out + ".tmp"]
     if verbose:

@@ -1,6 +1,7 @@
 // gl_internal.h -- calls between the library's translation units (not part
 // of the C ABI): the surrogate network's training loop, fused inference and
-// optimizer state, used by the surrogate path of the light-curve library.
+// optimizer state, used by the surrogate path of the light-curve library; the
+// MCMC glue's launches, captured with a light-curve batch.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,3 +32,16 @@ gl_status set_state(gl_mlp* mm, const float* m, const float* v, int64_t step);
 int max_batch(const gl_mlp* mm);
 
 }  // namespace gl_net
+
+namespace gl_mcmc {
+
+// Walker block [GL_W_NPARAM][n] -> oblate parameter block [GL_NPARAM][n].
+void launch_walk_params(const double* walk, int64_t n, double* params, hipStream_t st);
+
+// Per-walker chi^2 and log-likelihood of model against data / sigma (shared
+// grid: model [n_sets][n_times], data and sigma [n_times]; CSR: all indexed
+// alike by offsets).  chi2 or ll may be NULL.
+void launch_loglike(const double* model, int64_t n_sets, const int64_t* offsets, int64_t n_times,
+                    const double* data, const double* sigma, double* chi2, double* ll, hipStream_t st);
+
+}  // namespace gl_mcmc

@@ -1669,6 +1669,11 @@ struct gl_ctx {
         void* ws;
         int passes;
         int shape;
+        const double* walk;
+        const double* data;
+        const double* sigma;
+        double* chi2;
+        double* loglike;
     } key{};
     bool have_graph = false;
     // work lists of the exact path (capacities in entries; 0 = default)
@@ -1692,6 +1697,9 @@ struct gl_ctx {
     // every pass; t_used counts pass slots, t_batches batches
     int t_slots = 0, t_used = 0, t_batches = 0;
     hipEvent_t* ev = nullptr;  // (GL_NSTAGES + 1) events per slot
+    // parameter block converted from the walker block (gl_loglike_batch)
+    double* wparams = nullptr;
+    int64_t cap_walk = 0;
 };
 
 namespace {
@@ -1891,6 +1899,13 @@ struct Batch {
     const uint8_t* gate_zero = nullptr;
     double gate_k = 0.0;
     int shape = 0;  // 0: oblate parameter block, 1: general ellipsoids
+    // MCMC glue (gl_loglike_batch): the walker block converted into params
+    // first, the per-walker likelihood of out against data / sigma after
+    const double* walk = nullptr;
+    const double* data = nullptr;
+    const double* sigma = nullptr;
+    double* chi2 = nullptr;
+    double* loglike = nullptr;
 };
 
 // ctx may be NULL (no message is kept)
@@ -2113,7 +2128,29 @@ gl_status run_batch(gl_ctx* ctx, const Batch& b, bool census)
 
 gl_status enqueue(gl_ctx* ctx, const Batch& b, bool census = false)
 {
-    return run_batch(ctx, b, census);
+    if (b.walk) gl_mcmc::launch_walk_params(b.walk, b.n_sets, ctx->wparams, b.stream);
+    gl_status st = run_batch(ctx, b, census);
+    if (st != GL_OK) return st;
+    if (b.data)
+        gl_mcmc::launch_loglike(b.out, b.n_sets, b.offsets, b.n_times, b.data, b.sigma, b.chi2, b.loglike,
+                                b.stream);
+    GL_HIP(hipGetLastError(), "kernel launch");
+    return GL_OK;
+}
+
+// Room for the converted parameter block of n walkers (before any capture).
+gl_status ensure_walk(gl_ctx* ctx, int64_t n)
+{
+    if (n <= ctx->cap_walk) return GL_OK;
+    drop_graph(ctx);
+    GL_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    (void)hipFree(ctx->wparams);
+    ctx->wparams = nullptr;
+    ctx->cap_walk = 0;
+    if (hipMalloc(&ctx->wparams, sizeof(double) * GL_NPARAM * n) != hipSuccess)
+        return fail(ctx, GL_ERR_NOMEM, "walker parameter block");
+    ctx->cap_walk = n;
+    return GL_OK;
 }
 
 bool same_key(const gl_ctx::Key& a, const gl_ctx::Key& b)
@@ -2182,6 +2219,7 @@ void gl_ctx_destroy(gl_ctx* ctx)
     free_ws(ctx);
     (void)hipFree(ctx->ctr);
     (void)hipFree(ctx->snap_cs);
+    (void)hipFree(ctx->wparams);
     if (ctx->rec) (void)hipHostFree(ctx->rec);
     delete ctx;
 }
@@ -2203,6 +2241,15 @@ gl_status lightcurve(gl_ctx* ctx, Batch& b)
     const double* t_exp = b.t_exp;
     double* out = b.out;
     void* stream = (void*)b.stream;
+    if (b.walk) {
+        // the pipeline reads the converted block (rows of stride n_sets)
+        if (!ctx) return GL_ERR_NULL;
+        if (b.n_sets < 1) return fail(ctx, GL_ERR_SIZE, "n_sets must be >= 1");
+        GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+        gl_status wst = ensure_walk(ctx, b.n_sets);
+        if (wst != GL_OK) return wst;
+        b.params = ctx->wparams;
+    }
     gl_status st = check_args(ctx, b);
     if (st != GL_OK) return st;
     GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
@@ -2225,6 +2272,11 @@ gl_status lightcurve(gl_ctx* ctx, Batch& b)
     k.ws = ctx->masks;
     k.passes = ctx->passes;
     k.shape = b.shape;
+    k.walk = b.walk;
+    k.data = b.data;
+    k.sigma = b.sigma;
+    k.chi2 = b.chi2;
+    k.loglike = b.loglike;
     if (!ctx->have_graph || !same_key(k, ctx->key)) {
         drop_graph(ctx);
         GL_HIP(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
@@ -2271,6 +2323,24 @@ gl_status gl_lightcurve_batch_ellipsoid(gl_ctx* ctx, const double* params, int64
 {
     Batch b{params, n_sets, times, offsets, n_times, n_ss, t_exp, out, (hipStream_t)stream, 0};
     b.shape = 1;
+    return lightcurve(ctx, b);
+}
+
+gl_status gl_loglike_batch(gl_ctx* ctx, const double* walkers, int64_t n_walkers, const double* times,
+                           const int64_t* offsets, int64_t n_times, const int32_t* n_ss, const double* t_exp,
+                           const double* data, const double* sigma, double* model, double* chi2, double* loglike,
+                           void* stream)
+{
+    if (!ctx) return GL_ERR_NULL;
+    ctx->err[0] = 0;
+    if (!walkers || !data || !sigma || !model || (!chi2 && !loglike))
+        return fail(ctx, GL_ERR_NULL, "walkers, data, sigma, model and chi2 or loglike are required");
+    Batch b{nullptr, n_walkers, times, offsets, n_times, n_ss, t_exp, model, (hipStream_t)stream, 0};
+    b.walk = walkers;
+    b.data = data;
+    b.sigma = sigma;
+    b.chi2 = chi2;
+    b.loglike = loglike;
     return lightcurve(ctx, b);
 }
 

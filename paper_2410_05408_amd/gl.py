@@ -24,13 +24,16 @@ GL_NPARAM = 10
 (GL_E_RA, GL_E_RB, GL_E_RC, GL_E_ZETA, GL_E_ETA, GL_E_XI, GL_E_B, GL_E_ARS, GL_E_P, GL_E_T0, GL_E_Q1,
  GL_E_Q2, GL_E_LOCKED) = range(13)
 GL_E_NPARAM = 13
+GL_W_R, GL_W_MU, GL_W_NU, GL_W_XI, GL_W_B, GL_W_ARS, GL_W_P, GL_W_T0, GL_W_Q1, GL_W_Q2 = range(10)
+GL_W_NPARAM = 10
 
 EXPORTED = ("gl_ctx_create", "gl_ctx_destroy", "gl_lightcurve_batch", "gl_ctx_sync_status",
             "gl_ctx_last_error", "gl_autotune", "gl_ctx_get_plan", "gl_ctx_set_plan",
             "gl_ctx_set_graph", "gl_ctx_set_capacity", "gl_ctx_set_timing", "gl_ctx_get_timing",
             "gl_ctx_get_stage_timing", "gl_census", "gl_flop_model", "gl_ctx_get_unconverged",
             "gl_ctx_get_overflow", "gl_lightcurve_batch_noalloc", "gl_lightcurve_batch_snap", "gl_version",
-            "gl_lightcurve_batch_ellipsoid")
+            "gl_lightcurve_batch_ellipsoid", "gl_prior_mu_nu", "gl_walkers_to_params",
+            "gl_loglike_of_model", "gl_loglike_batch")
 CENSUS_NAMES = ("sub_in_window", "whole_on_star", "intersecting", "off_star_in_window",
                 "trapezoid_nodes", "gk21_pieces", "newton_steps", "limb_arcs",
                 "nested_trapezoid_nodes", "ellipse_arcs", "unconverged_arcs")
@@ -65,6 +68,14 @@ def lib():
         L.gl_lightcurve_batch.restype = i
         L.gl_lightcurve_batch_ellipsoid.argtypes = batch_args
         L.gl_lightcurve_batch_ellipsoid.restype = i
+        L.gl_prior_mu_nu.argtypes = [vp, i64, vp, vp]
+        L.gl_prior_mu_nu.restype = i
+        L.gl_walkers_to_params.argtypes = [vp, i64, vp, vp]
+        L.gl_walkers_to_params.restype = i
+        L.gl_loglike_of_model.argtypes = [vp, i64, vp, i64, vp, vp, vp, vp, vp]
+        L.gl_loglike_of_model.restype = i
+        L.gl_loglike_batch.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.gl_loglike_batch.restype = i
         L.gl_lightcurve_batch_snap.argtypes = [vp, i] + batch_args[1:]
         L.gl_lightcurve_batch_snap.restype = i
         L.gl_lightcurve_batch_noalloc.argtypes = batch_args[1:]
@@ -138,9 +149,13 @@ def _validate(params, times, offsets, n_ss, t_exp, out, rows=GL_NPARAM):
     import torch
     assert params.dtype == torch.float64 and params.is_cuda and params.is_contiguous()
     assert params.dim() == 2 and params.shape[0] == rows
+    _validate_grid(params.shape[1], times, offsets, n_ss, t_exp, out)
+
+
+def _validate_grid(n_sets, times, offsets, n_ss, t_exp, out):
+    import torch
     assert times.dtype == torch.float64 and times.is_cuda and times.is_contiguous()
     assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
-    n_sets = params.shape[1]
     if offsets is None:
         assert out.numel() == n_sets * times.numel()
     else:
@@ -170,6 +185,73 @@ def gl_lightcurve_batch_ellipsoid(ctx, params, times, out, offsets=None, n_ss=No
     st = lib().gl_lightcurve_batch_ellipsoid(ctx, _ptr(params), params.shape[1], _ptr(times), _ptr(offsets),
                                              times.numel(), _ptr(n_ss), _ptr(t_exp), _ptr(out),
                                              _stream_handle(stream))
+    _check(ctx, st)
+
+
+def _dev(t, dtype, rows=None, n=None):
+    import torch
+    assert t.dtype == dtype and t.is_cuda and t.is_contiguous()
+    if rows is not None:
+        assert t.dim() == 2 and t.shape[0] == rows
+    if n is not None:
+        assert t.numel() == n
+
+
+def gl_prior_mu_nu(uw, mu_nu, stream=None) -> None:
+    """(mu, nu) prior draws from the uniforms ``uw`` (float64 [2, n]) into
+    ``mu_nu`` (float64 [2, n])."""
+    import torch
+    _dev(uw, torch.float64, rows=2)
+    _dev(mu_nu, torch.float64, rows=2, n=uw.numel())
+    st = lib().gl_prior_mu_nu(_ptr(uw), uw.shape[1], _ptr(mu_nu), _stream_handle(stream))
+    if st != GL_OK:
+        raise GLError(st, "gl_prior_mu_nu")
+
+
+def gl_walkers_to_params(walkers, params, stream=None) -> None:
+    """Walker block float64 [10, n] -> oblate parameter block float64 [10, n]."""
+    import torch
+    _dev(walkers, torch.float64, rows=GL_W_NPARAM)
+    _dev(params, torch.float64, rows=GL_NPARAM, n=walkers.numel())
+    st = lib().gl_walkers_to_params(_ptr(walkers), walkers.shape[1], _ptr(params), _stream_handle(stream))
+    if st != GL_OK:
+        raise GLError(st, "gl_walkers_to_params")
+
+
+def gl_loglike_of_model(model, n_sets, data, sigma, chi2=None, loglike=None, offsets=None, stream=None) -> None:
+    import torch
+    _dev(model, torch.float64)
+    _dev(data, torch.float64)
+    _dev(sigma, torch.float64, n=data.numel())
+    if offsets is None:
+        assert model.numel() == n_sets * data.numel()
+    else:
+        _dev(offsets, torch.int64, n=n_sets + 1)
+        assert model.numel() == data.numel()
+    for t in (chi2, loglike):
+        if t is not None:
+            _dev(t, torch.float64, n=n_sets)
+    st = lib().gl_loglike_of_model(_ptr(model), n_sets, _ptr(offsets), data.numel(), _ptr(data), _ptr(sigma),
+                                   _ptr(chi2), _ptr(loglike), _stream_handle(stream))
+    if st != GL_OK:
+        raise GLError(st, "gl_loglike_of_model")
+
+
+def gl_loglike_batch(ctx, walkers, times, data, sigma, model, chi2=None, loglike=None, offsets=None,
+                     n_ss=None, t_exp=None, stream=None) -> None:
+    """One likelihood evaluation of a batch of walkers (float64 [10, n])."""
+    import torch
+    _dev(walkers, torch.float64, rows=GL_W_NPARAM)
+    n = walkers.shape[1]
+    _validate_grid(n, times, offsets, n_ss, t_exp, model)
+    _dev(data, torch.float64, n=times.numel())
+    _dev(sigma, torch.float64, n=times.numel())
+    for t in (chi2, loglike):
+        if t is not None:
+            _dev(t, torch.float64, n=n)
+    st = lib().gl_loglike_batch(ctx, _ptr(walkers), n, _ptr(times), _ptr(offsets), times.numel(), _ptr(n_ss),
+                                _ptr(t_exp), _ptr(data), _ptr(sigma), _ptr(model), _ptr(chi2), _ptr(loglike),
+                                _stream_handle(stream))
     _check(ctx, st)
 
 
@@ -324,6 +406,18 @@ class Context:
             out = torch.empty(n, dtype=torch.float64, device=times.device)
         gl_lightcurve_batch(self.handle, params, times, out, offsets, n_ss, t_exp, stream)
         return out
+
+    def loglike(self, walkers, times, data, sigma, model=None, offsets=None, n_ss=None, t_exp=None, stream=None):
+        """(chi2, loglike, model) of a walker batch, device tensors."""
+        import torch
+        n = walkers.shape[1]
+        if model is None:
+            m = n * times.numel() if offsets is None else times.numel()
+            model = torch.empty(m, dtype=torch.float64, device=times.device)
+        chi2 = torch.empty(n, dtype=torch.float64, device=times.device)
+        ll = torch.empty(n, dtype=torch.float64, device=times.device)
+        gl_loglike_batch(self.handle, walkers, times, data, sigma, model, chi2, ll, offsets, n_ss, t_exp, stream)
+        return chi2, ll, model
 
     def batch_ellipsoid(self, params, times, out=None, offsets=None, n_ss=None, t_exp=None, stream=None):
         import torch

@@ -268,8 +268,8 @@ def jwst_grid(half_span_days: float = 0.7):
 
 
 def walker_ball(n: int, seed: int = 8):
-    """Walkers around the injected planet, as an MCMC run holds them after
-    burn-in: r~N(0.067208, 7e-4), xi~U[0, pi/2], b~N(0.0416, 0.1),
+    """Walkers around the injected planet, a ball as an ensemble sampler is
+    started with: r~N(0.067208, 7e-4), xi~U[0, pi/2], b~N(0.0416, 0.1),
     d/R*~N(231.24, 2), P~N(542.08, 2e-4), t0~N(0, 2e-3), q1~N(0.26744, 0.02),
     q2~N(0.39688, 0.03); drawn in that order.  The (mu, nu) rows are left NaN:
     they come from the prior sampler fed with the returned uniforms
