@@ -367,6 +367,132 @@ def snap_leg(gl, w, census, exact_got, nodes_list=(1024, 8192), trials=10, dev="
     return res
 
 
+def timed_steps(step, stream, steps, warmup, trials=10):
+    """Warm-up, `steps` steps bracketed by synchronisations (ms per step), and
+    `trials` single steps timed by HIP events on the launch stream (median)."""
+    import torch
+    step()
+    for _ in range(warmup):
+        step()
+    stream.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    stream.synchronize()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(trials)]
+    for a, b in ev:
+        a.record(stream)
+        step()
+        b.record(stream)
+    stream.synchronize()
+    return ms, float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def ellipsoid_leg(gl, workloads, steps, warmup, dev="cuda:0"):
+    """General and tidally-locked triaxial planets (gl_lightcurve_batch_ellipsoid):
+    the mixed batch, and its free and locked halves on their own (locked sets
+    take the fused per-sample path)."""
+    import torch
+    res = {}
+    w = workloads.ellipsoid_batch()
+    n_lock = w.meta["locked_sets"]
+    parts = {"mixed": np.arange(w.n_sets), "locked": np.arange(n_lock), "free": np.arange(n_lock, w.n_sets)}
+    ctx = gl.Context(0)
+    stream = torch.cuda.Stream()
+    for name, idx in parts.items():
+        seg = np.diff(w.offsets)[idx]
+        offs = np.zeros(idx.size + 1, np.int64)
+        offs[1:] = np.cumsum(seg)
+        times = np.concatenate([w.times[w.offsets[s]:w.offsets[s + 1]] for s in idx])
+        p = torch.from_numpy(np.ascontiguousarray(w.params[:, idx])).to(dev)
+        td = torch.from_numpy(times).to(dev)
+        od = torch.from_numpy(offs).to(dev)
+        ss = torch.from_numpy(np.ascontiguousarray(w.n_ss[idx])).to(dev)
+        te = torch.from_numpy(np.ascontiguousarray(w.t_exp[idx])).to(dev)
+        out = torch.empty(times.size, dtype=torch.float64, device=dev)
+
+        def step():
+            gl.gl_lightcurve_batch_ellipsoid(ctx.handle, p, td, out, offsets=od, n_ss=ss, t_exp=te, stream=stream)
+
+        ms, med = timed_steps(step, stream, steps, warmup)
+        if gl.gl_ctx_sync_status(ctx.handle) != gl.GL_OK:
+            raise RuntimeError(gl.gl_ctx_last_error(ctx.handle))
+        got = out.cpu().numpy()
+        n_sub = int(np.sum(seg * w.n_ss[idx]))
+        res[name] = {"n_sets": int(idx.size), "outputs": int(times.size), "sub_samples": n_sub,
+                     "in_transit_points": int(np.sum(got < 1.0)), "ms_per_step": ms, "ms_median_event": med,
+                     "points_per_s": times.size / (ms * 1e-3), "sub_samples_per_s": n_sub / (ms * 1e-3)}
+    res["unconverged_arcs"] = gl.gl_ctx_get_unconverged(ctx.handle)
+    ctx.close()
+    return res
+
+
+def mcmc_leg(gl, workloads, steps, warmup, n_walkers=4096, dev="cuda:0"):
+    """One MCMC likelihood evaluation per step (gl_loglike_batch: walker map,
+    exact light curves, per-walker chi^2 and log L in one graph) for a walker
+    ball on the simulated JWST visit; the plain light-curve batch of the same
+    walkers for comparison; and the likelihood reduction alone against the
+    HBM roof (it streams the model once)."""
+    import torch
+    t, data, sigma = np.loadtxt(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                                             "jwst_injected.txt"), usecols=(0, 1, 2), unpack=True)
+    _, t_exp, n_ss = workloads.jwst_grid()
+    walk, uw = workloads.walker_ball(n_walkers, seed=8)
+    wd = torch.from_numpy(walk).to(dev)
+    mn = torch.empty((2, n_walkers), dtype=torch.float64, device=dev)
+    gl.gl_prior_mu_nu(torch.from_numpy(uw).to(dev), mn)
+    wd[workloads.W_MU:workloads.W_NU + 1] = mn
+    td, dd, sd = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (t, data, sigma))
+    ss = torch.full((n_walkers,), n_ss, dtype=torch.int32, device=dev)
+    te = torch.full((n_walkers,), t_exp, dtype=torch.float64, device=dev)
+    model = torch.empty(n_walkers * t.size, dtype=torch.float64, device=dev)
+    chi2 = torch.empty(n_walkers, dtype=torch.float64, device=dev)
+    ll = torch.empty(n_walkers, dtype=torch.float64, device=dev)
+    params = torch.empty((10, n_walkers), dtype=torch.float64, device=dev)
+    ctx = gl.Context(0)
+    stream = torch.cuda.Stream()
+
+    def step():
+        gl.gl_loglike_batch(ctx.handle, wd, td, dd, sd, model, chi2, ll, n_ss=ss, t_exp=te, stream=stream)
+
+    ms, med = timed_steps(step, stream, steps, warmup)
+    if gl.gl_ctx_sync_status(ctx.handle) != gl.GL_OK:
+        raise RuntimeError(gl.gl_ctx_last_error(ctx.handle))
+    gl.gl_walkers_to_params(wd, params)
+    ctx2 = gl.Context(0)
+
+    def lc():
+        gl.gl_lightcurve_batch(ctx2.handle, params, td, model, n_ss=ss, t_exp=te, stream=stream)
+
+    ms_lc, med_lc = timed_steps(lc, stream, steps, warmup)
+
+    def red():
+        gl.gl_loglike_of_model(model, n_walkers, dd, sd, chi2, ll, stream=stream)
+
+    _, med_red = timed_steps(red, stream, steps, warmup)
+    n_bytes = 8 * (n_walkers * t.size + 2 * t.size + 2 * n_walkers)
+    achieved = n_bytes / (med_red * 1e-3) / 1e9
+    c = chi2.cpu().numpy()
+    ctx.close()
+    ctx2.close()
+    return {
+        "config": {"workload": "jwst_visit_walker_ball", "n_walkers": n_walkers, "n_times": int(t.size),
+                   "n_ss": n_ss, "cadence_min": 2.0, "sigma_ppm": 20.0},
+        "ms_per_step": ms, "ms_median_event": med,
+        "walker_evaluations_per_s": n_walkers / (ms * 1e-3),
+        "points_per_s": n_walkers * t.size / (ms * 1e-3),
+        "lightcurve_only_ms_median_event": med_lc,
+        "glue_overhead_ms": med - med_lc,
+        "chi2_min_median": [float(np.min(c)), float(np.median(c))],
+        "loglike_reduction": {"ms_median_event": med_red, "roofline": {
+            "bound": "hbm", "kernel": "k_loglike", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+            "frac": achieved / 8000.0, "traffic": None, "algorithmic_bytes_per_launch": n_bytes}},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -376,7 +502,7 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-extra-configs", action="store_true",
                     help="skip the high-cadence and uneven-batch legs")
-    ap.add_argument("--only", choices=("walker_batch", "high_cadence", "uneven_batch"),
+    ap.add_argument("--only", choices=("walker_batch", "high_cadence", "uneven_batch", "ellipsoid_batch", "mcmc"),
                     help="run one exact leg only (profiling)")
     ap.add_argument("--sur-train", type=int, default=20_000_000)
     ap.add_argument("--sur-cal", type=int, default=1_000_000)
@@ -397,6 +523,12 @@ def main():
 
     from paper_2410_05408_amd import gl, workloads
 
+    if args.only == "ellipsoid_batch":
+        print(json.dumps({"workload": args.only, **ellipsoid_leg(gl, workloads, args.steps, args.warmup)}), flush=True)
+        return
+    if args.only == "mcmc":
+        print(json.dumps({"workload": args.only, **mcmc_leg(gl, workloads, args.steps, args.warmup)}), flush=True)
+        return
     if args.only and args.only != "walker_batch":
         w = workloads.by_name(args.only)
         log(f"{args.only}: {w.n_out} outputs")
@@ -442,6 +574,11 @@ def main():
         log("the paper's integrator (FP32 snap + Simpson) on the walker batch")
         res["paper_integrator"] = {"config": {"workload": "walker_batch", "precision": "fp32"},
                                    **snap_leg(gl, w, res["census"], got)}
+    if not args.no_extra_configs and not args.only:
+        log("general and tidally-locked ellipsoids (2048 sets x 1500 CSR times, half locked)")
+        res["ellipsoids"] = ellipsoid_leg(gl, workloads, max(3, args.steps // 4), args.warmup)
+        log("MCMC glue: likelihood of 4096 walkers on the simulated JWST visit")
+        res["mcmc"] = mcmc_leg(gl, workloads, args.steps, args.warmup)
     if not args.no_surrogate and not args.only:
         log("surrogate leg: data, training, calibration, gated evaluation")
         d = gl.to_device(w, "cuda:0")
