@@ -37,7 +37,7 @@
 
 #define GL_HD __host__ __device__ __forceinline__
 // heavy stages keep their own register allocation on the GPU
-#define GL_HD_CALL __host__ __device__ __attribute__((noinline))
+#define GL_HD_CALL static __host__ __device__ __attribute__((noinline))
 
 namespace gl {
 
@@ -356,6 +356,29 @@ GL_HD bool make_set_const(const double* p, double t_exp, int n_ss, SetConst& s)
     shape_terms(s, k);
     orbit_and_limb(s, k, b, d, P, t0, q1, q2);
     return true;
+}
+
+// ---------------------------------------------------------------- MCMC walkers
+// The fitting parameters of Section 3 (r, mu, nu, xi, b, d/R*, P, t0, q1, q2)
+// to the oblate parameter block (Appendix A): f = f_min + (1 - f_min) nu with
+// f_min = 1 - sqrt((mu + 1) / 2); cos(2 eta) = (mu - (f - 1)^2) / (f (f - 2))
+// from eq. mu, eta in [0, pi/2] (0 for a sphere); theta = pi/2 - eta; the
+// equatorial radius k = r / cbrt(1 - f) (r^3 = k^3 (1 - f)); the other rows
+// carry over.
+constexpr int kWalkParams = 10;
+
+GL_HD void walker_to_params(const double* w, double* p)
+{
+    const double r = w[0], mu = w[1], nu = w[2];
+    const double f_min = 1.0 - sqrt(0.5 * (mu + 1.0));
+    const double f = f_min + (1.0 - f_min) * nu;
+    const double den = f * (f - 2.0);
+    double c2 = den != 0.0 ? (mu - (f - 1.0) * (f - 1.0)) / den : 1.0;
+    c2 = fmin(1.0, fmax(-1.0, c2));
+    p[0] = r / cbrt(1.0 - f);
+    p[1] = f;
+    p[2] = 0.5 * kPi - 0.5 * acos(c2);
+    for (int i = 3; i < kWalkParams; ++i) p[i] = w[i];
 }
 
 // ---------------------------------------------------------------- general ellipsoids

@@ -40,8 +40,10 @@ void launch_walk_params(const double* walk, int64_t n, double* params, hipStream
 
 // Per-walker chi^2 and log-likelihood of model against data / sigma (shared
 // grid: model [n_sets][n_times], data and sigma [n_times]; CSR: all indexed
-// alike by offsets).  chi2 or ll may be NULL.
+// alike by offsets).  chi2 or ll may be NULL.  norm (device, may be NULL):
+// a shared grid's sum log(sigma) + (N/2) log(2 pi), already computed.
 void launch_loglike(const double* model, int64_t n_sets, const int64_t* offsets, int64_t n_times,
-                    const double* data, const double* sigma, double* chi2, double* ll, hipStream_t st);
+                    const double* data, const double* sigma, const double* norm, double* chi2, double* ll,
+                    hipStream_t st);
 
 }  // namespace gl_mcmc

@@ -109,6 +109,7 @@ struct Counters {
     unsigned long long sur_on;        // of those, with the ellipse reaching the disk
     unsigned long long sur_acc;       // of those, accepted by the gate
     unsigned long long net_total;     // rows of the current pass's network batch
+    double ll_norm;                   // likelihood batches on a shared grid: sum log(sigma) + (N/2) log(2 pi)
     Demand demand;                    // kept here; k_demand stores a copy to the host's record
     // work census (census launches only): in-window sub-samples, whole-on-star,
     // intersecting, in-window but off the star, trapezoid nodes of the rigorous
@@ -214,7 +215,8 @@ __global__ void k_prep(const double* __restrict__ params, int64_t ld, int64_t n_
                        gl::SetConst* __restrict__ sc, int64_t* __restrict__ seg_begin,
                        int64_t* __restrict__ seg_len, int64_t* __restrict__ chunk_off,
                        Counters* __restrict__ ctr, int64_t cps_shared, int first, int last,
-                       gl::SetConst* __restrict__ sph, int shape)
+                       gl::SetConst* __restrict__ sph, int shape, const double* __restrict__ sigma,
+                       int64_t n_sigma, double* __restrict__ norm)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s == 0) {
@@ -228,15 +230,34 @@ __global__ void k_prep(const double* __restrict__ params, int64_t ld, int64_t n_
     }
     for (int64_t i = s; i < (int64_t)kLists * kShards; i += (int64_t)gridDim.x * blockDim.x)
         ctr->lc[i / kShards][i % kShards].v = 0ull;
+    if (norm && blockIdx.x == gridDim.x - 1) {
+        // the extra last workgroup: a shared grid's likelihood normalisation
+        // sum log(sigma) + (N/2) log(2 pi), in a fixed order
+        __shared__ double part[256 / 64];
+        double acc = 0.0;
+        for (int64_t i = threadIdx.x; i < n_sigma; i += blockDim.x) acc += log(sigma[i]);
+        for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d);
+        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            norm[0] = ((part[0] + part[1]) + (part[2] + part[3])) + 0.5 * (double)n_sigma * 1.8378770664093454836;
+        return;
+    }
     if (s >= n_sets) return;
-    // shape 0: the oblate block (GL_NPARAM rows), 1: general ellipsoids
+    // shape 0: the oblate block (GL_NPARAM rows), 1: general ellipsoids,
+    // 2: MCMC walkers (converted to the oblate block)
     double p[gl::kEllParams];
-    const int rows = shape ? gl::kEllParams : GL_NPARAM;
+    const int rows = shape == 1 ? gl::kEllParams : GL_NPARAM;
     for (int i = 0; i < rows; ++i) p[i] = params[(int64_t)i * ld + s];
+    if (shape == 2) {
+        double w[gl::kWalkParams];
+        for (int i = 0; i < gl::kWalkParams; ++i) w[i] = p[i];
+        gl::walker_to_params(w, p);
+    }
     const int nss = n_ss ? n_ss[s] : 1;
     const double te = t_exp ? t_exp[s] : 0.0;
     gl::SetConst c;
-    const bool ok = shape ? gl::make_set_const_ell(p, te, nss, c) : gl::make_set_const(p, te, nss, c);
+    const bool ok = shape == 1 ? gl::make_set_const_ell(p, te, nss, c) : gl::make_set_const(p, te, nss, c);
     int64_t b, e;
     unsigned int flag = ok ? 0u : 1u;
     if (offsets) {
@@ -1669,7 +1690,6 @@ struct gl_ctx {
         void* ws;
         int passes;
         int shape;
-        const double* walk;
         const double* data;
         const double* sigma;
         double* chi2;
@@ -1697,9 +1717,6 @@ struct gl_ctx {
     // every pass; t_used counts pass slots, t_batches batches
     int t_slots = 0, t_used = 0, t_batches = 0;
     hipEvent_t* ev = nullptr;  // (GL_NSTAGES + 1) events per slot
-    // parameter block converted from the walker block (gl_loglike_batch)
-    double* wparams = nullptr;
-    int64_t cap_walk = 0;
 };
 
 namespace {
@@ -1898,10 +1915,9 @@ struct Batch {
     const float* gate_table = nullptr;
     const uint8_t* gate_zero = nullptr;
     double gate_k = 0.0;
-    int shape = 0;  // 0: oblate parameter block, 1: general ellipsoids
-    // MCMC glue (gl_loglike_batch): the walker block converted into params
-    // first, the per-walker likelihood of out against data / sigma after
-    const double* walk = nullptr;
+    int shape = 0;  // 0: oblate parameter block, 1: general ellipsoids, 2: MCMC walkers
+    // MCMC glue (gl_loglike_batch): the per-walker likelihood of out against
+    // data / sigma after the light curves
     const double* data = nullptr;
     const double* sigma = nullptr;
     double* chi2 = nullptr;
@@ -1987,12 +2003,15 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
         P.gate_zero = b.gate_zero;
         P.gate_k = b.gate_k;
     }
-    const unsigned prep_blocks = (unsigned)((b.n_sets + 255) / 256);
+    // with a likelihood on a shared grid, an extra workgroup of the first
+    // pass forms its normalisation
+    const bool norm = b.data && shared && b.first;
+    const unsigned prep_blocks = (unsigned)((b.n_sets + 255) / 256) + (norm ? 1u : 0u);
     const int64_t cps_shared = shared ? (b.n_times + kChunk - 1) / kChunk : 0;
     hipLaunchKernelGGL(k_prep, dim3(prep_blocks), dim3(256), 0, st, b.params, b.ld, b.n_sets,
                        b.offsets, b.n_times, b.n_ss, b.t_exp, ctx->sc, ctx->seg_begin,
                        ctx->seg_len, ctx->chunk_off, ctx->ctr, cps_shared, b.first, b.last,
-                       sur ? ctx->sc_sph : nullptr, b.shape);
+                       sur ? ctx->sc_sph : nullptr, b.shape, b.sigma, b.n_times, norm ? &ctx->ctr->ll_norm : nullptr);
     if (!shared)
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, ctx->chunk_off, b.n_sets,
                            b.max_chunks, ctx->ctr);
@@ -2032,7 +2051,11 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
                        ctx->chunk_fb, b.out);
     GL_STAGE_DONE();
     const DemandArgs dem{ctx->rec_dev, b.first, b.last, ctx->passes, (double)b.slots};
-    hipLaunchKernelGGL(k_compute<CENSUS>, dim3((unsigned)std::max<int64_t>(1, n_cu / 4)), dim3(64), 0, st, b.times, shared,
+    // the fused kernel takes the chunks the lists could not hold (few: a
+    // quarter wave per CU), and every chunk of a tidally-locked set (general
+    // ellipsoids: a full grid at its occupancy of two waves per SIMD)
+    const unsigned fused_grid = b.shape ? (unsigned)(n_cu * 8) : (unsigned)std::max<int64_t>(1, n_cu / 4);
+    hipLaunchKernelGGL(k_compute<CENSUS>, dim3(fused_grid), dim3(64), 0, st, b.times, shared,
                        ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, ctx->masks, ctx->chunk_set,
                        P, dem, b.out);
     GL_STAGE_DONE();
@@ -2128,28 +2151,15 @@ gl_status run_batch(gl_ctx* ctx, const Batch& b, bool census)
 
 gl_status enqueue(gl_ctx* ctx, const Batch& b, bool census = false)
 {
-    if (b.walk) gl_mcmc::launch_walk_params(b.walk, b.n_sets, ctx->wparams, b.stream);
     gl_status st = run_batch(ctx, b, census);
     if (st != GL_OK) return st;
-    if (b.data)
-        gl_mcmc::launch_loglike(b.out, b.n_sets, b.offsets, b.n_times, b.data, b.sigma, b.chi2, b.loglike,
+    if (b.data) {
+        // a shared grid's normalisation came from the first pass's k_prep
+        const double* norm = b.offsets ? nullptr : &ctx->ctr->ll_norm;
+        gl_mcmc::launch_loglike(b.out, b.n_sets, b.offsets, b.n_times, b.data, b.sigma, norm, b.chi2, b.loglike,
                                 b.stream);
+    }
     GL_HIP(hipGetLastError(), "kernel launch");
-    return GL_OK;
-}
-
-// Room for the converted parameter block of n walkers (before any capture).
-gl_status ensure_walk(gl_ctx* ctx, int64_t n)
-{
-    if (n <= ctx->cap_walk) return GL_OK;
-    drop_graph(ctx);
-    GL_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
-    (void)hipFree(ctx->wparams);
-    ctx->wparams = nullptr;
-    ctx->cap_walk = 0;
-    if (hipMalloc(&ctx->wparams, sizeof(double) * GL_NPARAM * n) != hipSuccess)
-        return fail(ctx, GL_ERR_NOMEM, "walker parameter block");
-    ctx->cap_walk = n;
     return GL_OK;
 }
 
@@ -2219,7 +2229,6 @@ void gl_ctx_destroy(gl_ctx* ctx)
     free_ws(ctx);
     (void)hipFree(ctx->ctr);
     (void)hipFree(ctx->snap_cs);
-    (void)hipFree(ctx->wparams);
     if (ctx->rec) (void)hipHostFree(ctx->rec);
     delete ctx;
 }
@@ -2241,15 +2250,6 @@ gl_status lightcurve(gl_ctx* ctx, Batch& b)
     const double* t_exp = b.t_exp;
     double* out = b.out;
     void* stream = (void*)b.stream;
-    if (b.walk) {
-        // the pipeline reads the converted block (rows of stride n_sets)
-        if (!ctx) return GL_ERR_NULL;
-        if (b.n_sets < 1) return fail(ctx, GL_ERR_SIZE, "n_sets must be >= 1");
-        GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-        gl_status wst = ensure_walk(ctx, b.n_sets);
-        if (wst != GL_OK) return wst;
-        b.params = ctx->wparams;
-    }
     gl_status st = check_args(ctx, b);
     if (st != GL_OK) return st;
     GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
@@ -2272,7 +2272,6 @@ gl_status lightcurve(gl_ctx* ctx, Batch& b)
     k.ws = ctx->masks;
     k.passes = ctx->passes;
     k.shape = b.shape;
-    k.walk = b.walk;
     k.data = b.data;
     k.sigma = b.sigma;
     k.chi2 = b.chi2;
@@ -2335,8 +2334,8 @@ gl_status gl_loglike_batch(gl_ctx* ctx, const double* walkers, int64_t n_walkers
     ctx->err[0] = 0;
     if (!walkers || !data || !sigma || !model || (!chi2 && !loglike))
         return fail(ctx, GL_ERR_NULL, "walkers, data, sigma, model and chi2 or loglike are required");
-    Batch b{nullptr, n_walkers, times, offsets, n_times, n_ss, t_exp, model, (hipStream_t)stream, 0};
-    b.walk = walkers;
+    Batch b{walkers, n_walkers, times, offsets, n_times, n_ss, t_exp, model, (hipStream_t)stream, 0};
+    b.shape = 2;  // k_prep converts the walker block
     b.data = data;
     b.sigma = sigma;
     b.chi2 = chi2;
@@ -2570,7 +2569,7 @@ gl_status gl_lightcurve_batch_snap(gl_ctx* ctx, int n_nodes, const double* param
     const int64_t cps_shared = shared ? (b.n_times + kChunk - 1) / kChunk : 0;
     hipLaunchKernelGGL(k_prep, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, s, params, n_sets, n_sets, offsets,
                        n_times, n_ss, t_exp, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off, ctx->ctr, cps_shared,
-                       1, 1, (gl::SetConst*)nullptr, 0);
+                       1, 1, (gl::SetConst*)nullptr, 0, (const double*)nullptr, (int64_t)0, (double*)nullptr);
     if (!shared)
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, ctx->chunk_off, n_sets, b.max_chunks, ctx->ctr);
     launch_window(ctx, b, s, 0, ctx->pipe);

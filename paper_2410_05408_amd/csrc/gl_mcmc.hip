@@ -12,8 +12,10 @@
 //                   equatorial radius k = r / cbrt(1 - f) (r: geometric mean
 //                   of the three semi-axes, r^3 = k^3 (1 - f))
 //   k_loglike       per-walker white-noise chi^2 and log-likelihood of a
-//                   model light curve against data: one workgroup per walker,
+//                   model light curve against data: one wavefront per walker,
 //                   a fixed-order reduction (bitwise reproducible)
+// (the light-curve batch of gl_loglike_batch converts its walkers inside its
+// own set-up kernel, with the same walker_to_params)
 //
 // All three are bandwidth-light elementwise or streaming kernels; the
 // light-curve batch between the first two and the last is the work.
@@ -23,6 +25,7 @@
 #include <cstdint>
 
 #include "gl.h"
+#include "gl_device.h"
 #include "gl_internal.h"
 
 namespace {
@@ -55,18 +58,10 @@ k_walk_params(const double* __restrict__ walk, int64_t n, double* __restrict__ p
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double r = walk[i], mu = walk[n + i], nu = walk[2 * n + i];
-    const double f_min = 1.0 - sqrt(0.5 * (mu + 1.0));
-    const double f = f_min + (1.0 - f_min) * nu;
-    const double den = f * (f - 2.0);
-    double c2 = den != 0.0 ? (mu - (f - 1.0) * (f - 1.0)) / den : 1.0;  // a sphere: eta = 0
-    c2 = fmin(1.0, fmax(-1.0, c2));
-    const double eta = 0.5 * acos(c2);
-    params[i] = r / cbrt(1.0 - f);
-    params[n + i] = f;
-    params[2 * n + i] = 0.5 * 3.14159265358979323846 - eta;
-    // xi, b, d/R*, P, t0, q1, q2 carry over (rows 3.. of both blocks)
-    for (int row = 3; row < GL_NPARAM; ++row) params[row * n + i] = walk[row * n + i];
+    double w[gl::kWalkParams], p[GL_NPARAM];
+    for (int row = 0; row < gl::kWalkParams; ++row) w[row] = walk[row * n + i];
+    gl::walker_to_params(w, p);
+    for (int row = 0; row < GL_NPARAM; ++row) params[row * n + i] = p[row];
 }
 
 // Sum of a value per thread over the workgroup in a fixed order: butterfly
@@ -100,40 +95,69 @@ __global__ void __launch_bounds__(kLLThreads) k_loglike_finish(const double* __r
     for (int64_t w = threadIdx.x; w < n_sets; w += kLLThreads) ll[w] = -0.5 * ll[w] - norm;
 }
 
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    return v;
+}
+
+// One wavefront per walker (four per workgroup: a shared grid's data and
+// sigma are read once per workgroup from the caches).  The data set of a
+// likelihood batch is about one latency-bandwidth product of HBM, so each
+// lane issues all kLLUnroll loads of a 64 x kLLUnroll slice before it does any
+// arithmetic; per-lane sums run in a fixed order, then a fixed butterfly.
+// With `norm` (a shared grid's sum log(sigma) + (N/2) log(2 pi), computed
+// before) the log-likelihood is finished here; without it, a shared grid
+// leaves chi^2 in ll for k_loglike_finish.
+constexpr int kLLUnroll = 16;
+
+template <bool CSR>
 __global__ void __launch_bounds__(kLLThreads)
 k_loglike(const double* __restrict__ model, int64_t n_sets, const int64_t* __restrict__ offsets, int64_t n_times,
-          const double* __restrict__ data, const double* __restrict__ sigma, double* __restrict__ chi2,
-          double* __restrict__ ll)
+          const double* __restrict__ data, const double* __restrict__ sigma, const double* __restrict__ norm,
+          double* __restrict__ chi2, double* __restrict__ ll)
 {
-    __shared__ double lds[kLLThreads / 64];
-    for (int64_t s = blockIdx.x; s < n_sets; s += gridDim.x) {
-        int64_t a, len;
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (kLLThreads / 64);
+    for (int64_t s = (int64_t)blockIdx.x * (kLLThreads / 64) + (threadIdx.x >> 6); s < n_sets; s += waves) {
+        int64_t a = 0, len = n_times;
         bool ok = true;
-        if (offsets) {
+        if (CSR) {
             a = offsets[s];
             const int64_t b = offsets[s + 1];
             ok = a >= 0 && b >= a && b <= n_times;
             len = ok ? b - a : 0;
-        } else {
-            a = 0;
-            len = n_times;
         }
-        const double* m = model + (offsets ? a : s * n_times);
+        const double* m = model + (CSR ? a : s * n_times);
         const double* d = data + a;
         const double* sg = sigma + a;
         double acc = 0.0, accl = 0.0;
-        for (int64_t i = threadIdx.x; i < len; i += kLLThreads) {
-            const double r = (d[i] - m[i]) / sg[i];
-            acc += r * r;
-            if (offsets) accl += log(sg[i]);
+        for (int64_t i0 = 0; i0 < len; i0 += 64 * kLLUnroll) {
+            double mv[kLLUnroll], dv[kLLUnroll], sv[kLLUnroll];
+#pragma unroll
+            for (int k = 0; k < kLLUnroll; ++k) {
+                const int64_t j = i0 + lane + 64 * k;
+                const bool in = j < len;
+                mv[k] = in ? m[j] : 0.0;
+                dv[k] = in ? d[j] : 0.0;
+                sv[k] = in ? sg[j] : 1.0;
+            }
+#pragma unroll
+            for (int k = 0; k < kLLUnroll; ++k) {
+                const double r = (dv[k] - mv[k]) / sv[k];
+                acc += r * r;
+                if (CSR && i0 + lane + 64 * k < len) accl += log(sv[k]);
+            }
         }
-        const double c = block_sum(acc, lds);
-        const double l = offsets ? block_sum(accl, lds) : 0.0;
-        if (threadIdx.x == 0) {
+        const double c = wave_sum(acc);
+        const double l = CSR ? wave_sum(accl) : 0.0;
+        if (lane == 0) {
             const double cc = ok ? c : __builtin_nan("");
             if (chi2) chi2[s] = cc;
-            // shared grid: chi^2 for now, finished by k_loglike_finish
-            if (ll) ll[s] = offsets ? -0.5 * cc - (l + 0.5 * (double)len * kLog2Pi) : cc;
+            if (ll) {
+                if (CSR) ll[s] = -0.5 * cc - (l + 0.5 * (double)len * kLog2Pi);
+                else ll[s] = norm ? -0.5 * cc - norm[0] : cc;  // finished later without norm
+            }
         }
     }
 }
@@ -150,12 +174,18 @@ void launch_walk_params(const double* walk, int64_t n, double* params, hipStream
 }
 
 void launch_loglike(const double* model, int64_t n_sets, const int64_t* offsets, int64_t n_times,
-                    const double* data, const double* sigma, double* chi2, double* ll, hipStream_t st)
+                    const double* data, const double* sigma, const double* norm, double* chi2, double* ll,
+                    hipStream_t st)
 {
-    const unsigned grid = (unsigned)(n_sets < (int64_t)1 << 20 ? n_sets : (int64_t)1 << 20);
-    hipLaunchKernelGGL(k_loglike, dim3(grid), dim3(kLLThreads), 0, st, model, n_sets, offsets, n_times, data, sigma,
-                       chi2, ll);
-    if (!offsets && ll)
+    const int64_t blocks = (n_sets + kLLThreads / 64 - 1) / (kLLThreads / 64);
+    const unsigned grid = (unsigned)(blocks < (int64_t)1 << 20 ? blocks : (int64_t)1 << 20);
+    if (offsets)
+        hipLaunchKernelGGL(k_loglike<true>, dim3(grid), dim3(kLLThreads), 0, st, model, n_sets, offsets, n_times, data,
+                           sigma, norm, chi2, ll);
+    else
+        hipLaunchKernelGGL(k_loglike<false>, dim3(grid), dim3(kLLThreads), 0, st, model, n_sets, offsets, n_times,
+                           data, sigma, norm, chi2, ll);
+    if (!offsets && ll && !norm)
         hipLaunchKernelGGL(k_loglike_finish, dim3(1), dim3(kLLThreads), 0, st, sigma, n_times, n_sets, ll);
 }
 
@@ -184,7 +214,8 @@ gl_status gl_loglike_of_model(const double* model, int64_t n_sets, const int64_t
 {
     if (!model || !data || !sigma || (!chi2 && !loglike)) return GL_ERR_NULL;
     if (n_sets < 1 || n_times < (offsets ? 0 : 1)) return GL_ERR_SIZE;
-    gl_mcmc::launch_loglike(model, n_sets, offsets, n_times, data, sigma, chi2, loglike, (hipStream_t)stream);
+    gl_mcmc::launch_loglike(model, n_sets, offsets, n_times, data, sigma, nullptr, chi2, loglike,
+                            (hipStream_t)stream);
     return hipGetLastError() == hipSuccess ? GL_OK : GL_ERR_DEVICE;
 }
 
