@@ -616,13 +616,31 @@ GL_HD void solve_quartic_inl(const Poly4& q, QuarticRoots& out, CT& ct)
         }
     }
     const double e[4] = {-Bnd, i0, i1, Bnd};
-    // critical points: a root of q' in each interval where it changes sign
+    // critical points: a root of q' in each interval where it changes sign,
+    // solved in a loop over the lane's own sign changes (nearly every sample
+    // has exactly one, in a slot that differs from lane to lane: one Newton
+    // loop per lane instead of one per slot)
+    double fe[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) fe[i] = dp4(q, e[i]);
+    unsigned ctodo = 0u;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        const double lo = e[i], hi = e[i + 1];
-        const double flo = dp4(q, lo), fhi = dp4(q, hi);
-        out.cv[i] = (flo < 0.0) != (fhi < 0.0) && flo != 0.0 && fhi != 0.0;
-        out.c[i] = out.cv[i] ? bracket_root<1>(q, lo, hi, flo, fhi, ct) : lo;
+        out.cv[i] = (fe[i] < 0.0) != (fe[i + 1] < 0.0) && fe[i] != 0.0 && fe[i + 1] != 0.0;
+        out.c[i] = e[i];
+        ctodo |= (out.cv[i] ? 1u : 0u) << i;
+    }
+    while (ctodo) {
+        const int i = __builtin_ctz(ctodo);
+        ctodo &= ctodo - 1u;
+        const double lo = i == 0 ? e[0] : i == 1 ? e[1] : e[2];
+        const double hi = i == 0 ? e[1] : i == 1 ? e[2] : e[3];
+        const double flo = i == 0 ? fe[0] : i == 1 ? fe[1] : fe[2];
+        const double fhi = i == 0 ? fe[1] : i == 1 ? fe[2] : fe[3];
+        const double x = bracket_root<1>(q, lo, hi, flo, fhi, ct);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (k == i) out.c[k] = x;
     }
     // roots of q between consecutive critical points; an empty critical slot
     // keeps the left end of its interval, which only splits a stretch where

@@ -209,13 +209,16 @@ __device__ __forceinline__ const gl::SetConst& entry_set(const gl::SetConst* __r
 // parameter sets (the whole pipeline per pass); `ld` is the row stride of the
 // parameter block, `first` / `last` mark the batch's first and last pass
 // (census reset, CSR end checks).
+// SHAPE 0: the oblate block (GL_NPARAM rows), 1: general ellipsoids, 2: MCMC
+// walkers (converted to the oblate block); one instance per block kind.
+template <int SHAPE>
 __global__ void k_prep(const double* __restrict__ params, int64_t ld, int64_t n_sets,
                        const int64_t* __restrict__ offsets, int64_t n_times,
                        const int32_t* __restrict__ n_ss, const double* __restrict__ t_exp,
                        gl::SetConst* __restrict__ sc, int64_t* __restrict__ seg_begin,
                        int64_t* __restrict__ seg_len, int64_t* __restrict__ chunk_off,
                        Counters* __restrict__ ctr, int64_t cps_shared, int first, int last,
-                       gl::SetConst* __restrict__ sph, int shape, const double* __restrict__ sigma,
+                       gl::SetConst* __restrict__ sph, const double* __restrict__ sigma,
                        int64_t n_sigma, double* __restrict__ norm)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -244,20 +247,22 @@ __global__ void k_prep(const double* __restrict__ params, int64_t ld, int64_t n_
         return;
     }
     if (s >= n_sets) return;
-    // shape 0: the oblate block (GL_NPARAM rows), 1: general ellipsoids,
-    // 2: MCMC walkers (converted to the oblate block)
-    double p[gl::kEllParams];
-    const int rows = shape == 1 ? gl::kEllParams : GL_NPARAM;
+    constexpr int rows = SHAPE == 1 ? gl::kEllParams : GL_NPARAM;
+    double p[rows];
+#pragma unroll
     for (int i = 0; i < rows; ++i) p[i] = params[(int64_t)i * ld + s];
-    if (shape == 2) {
+    if (SHAPE == 2) {
         double w[gl::kWalkParams];
+#pragma unroll
         for (int i = 0; i < gl::kWalkParams; ++i) w[i] = p[i];
         gl::walker_to_params(w, p);
     }
     const int nss = n_ss ? n_ss[s] : 1;
     const double te = t_exp ? t_exp[s] : 0.0;
     gl::SetConst c;
-    const bool ok = shape == 1 ? gl::make_set_const_ell(p, te, nss, c) : gl::make_set_const(p, te, nss, c);
+    bool ok;
+    if constexpr (SHAPE == 1) ok = gl::make_set_const_ell(p, te, nss, c);
+    else ok = gl::make_set_const(p, te, nss, c);
     int64_t b, e;
     unsigned int flag = ok ? 0u : 1u;
     if (offsets) {
@@ -1535,7 +1540,9 @@ __device__ __attribute__((noinline)) double flux_hard(const gl::SetConst& S0, do
 #define GL_COMPUTE_ATTR __launch_bounds__(64)
 #endif
 
-template <bool CENSUS>
+// ELL: batches of general ellipsoids, whose tidally-locked sets rebuild
+// their shadow per sub-sample (lock_at); the oblate instance carries none of it.
+template <bool CENSUS, bool ELL>
 __global__ void GL_COMPUTE_ATTR
 k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst* __restrict__ sc,
           const int64_t* __restrict__ seg_begin, const int64_t* __restrict__ chunk_off,
@@ -1584,8 +1591,8 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
                         const int o = (int)(((float)f + 0.5f) * inv_nss_f), j = f - o * nss;
                         const double t = times[tb + lds_idx[o]] + (((double)j + 0.5) * inv_nss - 0.5) * S.t_exp;
                         double F = 1.0;
-                        hard = !(S.locked ? flux_easy<CENSUS, true>(S, t, F, cnt)
-                                          : flux_easy<CENSUS, false>(S, t, F, cnt));
+                        hard = !((ELL && S.locked) ? flux_easy<CENSUS, ELL>(S, t, F, cnt)
+                                                   : flux_easy<CENSUS, false>(S, t, F, cnt));
                         if (!hard) lds_f[f] = F;
                     }
                     const unsigned long long hm = __ballot(hard);
@@ -1600,7 +1607,8 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
                         const int f = lds_def[k];
                         const int o = (int)(((float)f + 0.5f) * inv_nss_f), j = f - o * nss;
                         const double t = times[tb + lds_idx[o]] + (((double)j + 0.5) * inv_nss - 0.5) * S.t_exp;
-                        lds_f[f] = S.locked ? flux_hard<CENSUS, true>(S, t, cnt) : flux_hard<CENSUS, false>(S, t, cnt);
+                        lds_f[f] = (ELL && S.locked) ? flux_hard<CENSUS, ELL>(S, t, cnt)
+                                                     : flux_hard<CENSUS, false>(S, t, cnt);
                     }
                 }
                 __syncthreads();
@@ -1625,8 +1633,8 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
                     if (act) {
                         off = lds_idx[o];
                         const double t = times[tb + off] + frac * S.t_exp;
-                        if (S.locked) {
-                            if (!flux_easy<CENSUS, true>(S, t, F, cnt)) F = flux_hard<CENSUS, true>(S, t, cnt);
+                        if (ELL && S.locked) {
+                            if (!flux_easy<CENSUS, ELL>(S, t, F, cnt)) F = flux_hard<CENSUS, ELL>(S, t, cnt);
                         } else if (!flux_easy<CENSUS, false>(S, t, F, cnt)) {
                             F = flux_hard<CENSUS, false>(S, t, cnt);
                         }
@@ -1717,6 +1725,10 @@ struct gl_ctx {
     // every pass; t_used counts pass slots, t_batches batches
     int t_slots = 0, t_used = 0, t_batches = 0;
     hipEvent_t* ev = nullptr;  // (GL_NSTAGES + 1) events per slot
+    // a second stream for the trapezoid stage, which depends on the
+    // classification only and runs beside the hard-sample chain
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -2008,10 +2020,11 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     const bool norm = b.data && shared && b.first;
     const unsigned prep_blocks = (unsigned)((b.n_sets + 255) / 256) + (norm ? 1u : 0u);
     const int64_t cps_shared = shared ? (b.n_times + kChunk - 1) / kChunk : 0;
-    hipLaunchKernelGGL(k_prep, dim3(prep_blocks), dim3(256), 0, st, b.params, b.ld, b.n_sets,
+    auto prep = b.shape == 1 ? k_prep<1> : b.shape == 2 ? k_prep<2> : k_prep<0>;
+    hipLaunchKernelGGL(prep, dim3(prep_blocks), dim3(256), 0, st, b.params, b.ld, b.n_sets,
                        b.offsets, b.n_times, b.n_ss, b.t_exp, ctx->sc, ctx->seg_begin,
                        ctx->seg_len, ctx->chunk_off, ctx->ctr, cps_shared, b.first, b.last,
-                       sur ? ctx->sc_sph : nullptr, b.shape, b.sigma, b.n_times, norm ? &ctx->ctr->ll_norm : nullptr);
+                       sur ? ctx->sc_sph : nullptr, b.sigma, b.n_times, norm ? &ctx->ctr->ll_norm : nullptr);
     if (!shared)
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, ctx->chunk_off, b.n_sets,
                            b.max_chunks, ctx->ctr);
@@ -2030,8 +2043,17 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
                            ctx->chunk_set, ctx->chunk_fb);
     GL_STAGE_DONE();
     const unsigned twaves = GL_TRAP_WAVES_PER_CU > 0 ? (unsigned)(n_cu * GL_TRAP_WAVES_PER_CU) : waves;
-    hipLaunchKernelGGL(k_trap<CENSUS>, dim3((twaves + kTrapWaves - 1) / kTrapWaves), dim3(kTrapThreads), 0, st,
-                       ctx->sc, ctx->ctr, P);
+    // whole ellipses (trapezoid) need nothing from the hard-sample chain and
+    // write other sub-samples: on the side stream they run beside it (joined
+    // before the averages); the stage timing keeps every stage in order
+    const bool fork = ctx->side != nullptr && ev == nullptr;
+    if (fork) {
+        GL_HIP(hipEventRecord(ctx->ev_fork, st), "hipEventRecord");
+        GL_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0), "hipStreamWaitEvent");
+    }
+    hipLaunchKernelGGL(k_trap<CENSUS>, dim3((twaves + kTrapWaves - 1) / kTrapWaves), dim3(kTrapThreads), 0,
+                       fork ? ctx->side : st, ctx->sc, ctx->ctr, P);
+    if (fork) GL_HIP(hipEventRecord(ctx->ev_join, ctx->side), "hipEventRecord");
     GL_STAGE_DONE();
     hipLaunchKernelGGL(k_hard<CENSUS>, dim3(waves), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
     GL_STAGE_DONE();
@@ -2040,6 +2062,7 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     launch_arcs<CENSUS>(ctx, st, GL_GK_WAVES_PER_CU > 0 ? (unsigned)(n_cu * GL_GK_WAVES_PER_CU) : waves, P);
     GL_STAGE_DONE();
     hipLaunchKernelGGL(k_combine, dim3((unsigned)(n_cu * 8)), dim3(256), 0, st, ctx->sc, ctx->ctr, P);
+    if (fork) GL_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0), "hipStreamWaitEvent");
     if (sur) {
         // the network's residuals on the accepted sub-samples' sphere fluxes
         hipLaunchKernelGGL(k_net_gather, dim3((unsigned)(n_cu * 8)), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
@@ -2055,7 +2078,8 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     // quarter wave per CU), and every chunk of a tidally-locked set (general
     // ellipsoids: a full grid at its occupancy of two waves per SIMD)
     const unsigned fused_grid = b.shape ? (unsigned)(n_cu * 8) : (unsigned)std::max<int64_t>(1, n_cu / 4);
-    hipLaunchKernelGGL(k_compute<CENSUS>, dim3(fused_grid), dim3(64), 0, st, b.times, shared,
+    auto fused = b.shape == 1 ? k_compute<CENSUS, true> : k_compute<CENSUS, false>;
+    hipLaunchKernelGGL(fused, dim3(fused_grid), dim3(64), 0, st, b.times, shared,
                        ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, ctx->masks, ctx->chunk_set,
                        P, dem, b.out);
     GL_STAGE_DONE();
@@ -2207,6 +2231,16 @@ gl_status gl_ctx_create(gl_ctx** out, int device)
         delete ctx;
         return GL_ERR_DEVICE;
     }
+    // default priority, non-blocking (no implicit order with the legacy
+    // default stream); without it every stage runs on the caller's stream
+    if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
+        if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+        if (ctx->side) (void)hipStreamDestroy(ctx->side);
+        ctx->side = nullptr;
+        ctx->ev_fork = ctx->ev_join = nullptr;
+    }
     *out = ctx;
     return GL_OK;
 }
@@ -2230,6 +2264,9 @@ void gl_ctx_destroy(gl_ctx* ctx)
     (void)hipFree(ctx->ctr);
     (void)hipFree(ctx->snap_cs);
     if (ctx->rec) (void)hipHostFree(ctx->rec);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     delete ctx;
 }
 
@@ -2567,9 +2604,9 @@ gl_status gl_lightcurve_batch_snap(gl_ctx* ctx, int n_nodes, const double* param
     hipStream_t s = b.stream;
     const int shared = b.offsets ? 0 : 1;
     const int64_t cps_shared = shared ? (b.n_times + kChunk - 1) / kChunk : 0;
-    hipLaunchKernelGGL(k_prep, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, s, params, n_sets, n_sets, offsets,
-                       n_times, n_ss, t_exp, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off, ctx->ctr, cps_shared,
-                       1, 1, (gl::SetConst*)nullptr, 0, (const double*)nullptr, (int64_t)0, (double*)nullptr);
+    hipLaunchKernelGGL(k_prep<0>, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, s, params, n_sets, n_sets,
+                       offsets, n_times, n_ss, t_exp, ctx->sc, ctx->seg_begin, ctx->seg_len, ctx->chunk_off, ctx->ctr,
+                       cps_shared, 1, 1, (gl::SetConst*)nullptr, (const double*)nullptr, (int64_t)0, (double*)nullptr);
     if (!shared)
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, ctx->chunk_off, n_sets, b.max_chunks, ctx->ctr);
     launch_window(ctx, b, s, 0, ctx->pipe);
