@@ -311,7 +311,8 @@ def exact_leg(gl, w, steps, warmup, trials=10, autotune=False, check_oracle=True
         "in_transit_points": in_transit, "outputs": w.n_out, "sub_samples": w.n_sub,
         "roofline": roof, "roofline_stages": roof_stages, "stage_ms": stage_ms,
         "pipeline_ms_direct_launch": sum(stage_ms.values()),
-        "plan": {"waves_per_cu": gl.gl_ctx_get_plan(ctx.handle), "passes": passes,
+        "plan": {"waves_per_cu": gl.gl_ctx_get_plan(ctx.handle),
+                 "stage_plan_classify_traphard_arcs": list(gl.gl_ctx_get_stage_plan(ctx.handle)), "passes": passes,
                  "fused_chunks": fused, "autotuned": autotune},
         "census": census, "unconverged_arcs": unconv,
     }
@@ -539,7 +540,7 @@ def main():
 
     log("walker batch (4096 sets x 3000 shared times x 15 sub-samples)")
     w = workloads.walker_batch()
-    head, got = exact_leg(gl, w, args.steps, args.warmup, check_oracle=False)
+    head, got = exact_leg(gl, w, args.steps, args.warmup, autotune=True, check_oracle=False)
     res = {
         "metric": "light-curve points/sec on 1 MI355X: exact (≤1e-9) vs surrogate+fallback (≤1 ppm)",
         "value": head.pop("value"),
@@ -562,7 +563,7 @@ def main():
     if not args.no_extra_configs and not args.only:
         res["configs"] = {}
         log("high-cadence batch (512 sets x 65536 shared times, no supersampling)")
-        hc, _ = exact_leg(gl, workloads.high_cadence(), args.steps, args.warmup)
+        hc, _ = exact_leg(gl, workloads.high_cadence(), args.steps, args.warmup, autotune=True)
         res["configs"]["high_cadence"] = {"config": {"n_sets": 512, "n_times": 65536, "n_ss": 1,
                                                      "cadence_s": 60, "seed": 3}, **hc}
         log("uneven CSR batch (16384 walkers, own grids of 200..20000 times, n_ss in {1,5,15})")

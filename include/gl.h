@@ -239,20 +239,35 @@ const char *gl_ctx_last_error(const gl_ctx *ctx);
 
 /* Launch-plan autotuner: times the candidate persistent-grid sizes of the
  * work-list kernels on a representative batch (same arguments as
- * gl_lightcurve_batch; `out` is overwritten) and keeps the fastest in the
- * context's plan.  Synchronises `stream`.  Quadrature orders are not a plan
- * setting: every sample picks its own (self-checking rules). */
+ * gl_lightcurve_batch; `out` is overwritten), one stage group at a time
+ * (trapezoid and hard-sample kernels {8, 16, 24, 32, 48, 64} waves per CU,
+ * then classification {8, 16, 24, 32, 48}, then the arc-rule levels
+ * {8, 12, 16, 20, 32, 48}; more waves than fit at once queue behind the
+ * resident ones, which balances uneven per-wave work;
+ * coordinate descent, each candidate timed over three batches after a warm-up)
+ * and keeps the fastest in the context's plan.  Synchronises `stream`.
+ * Quadrature orders are not a plan setting: every sample picks its own
+ * (self-checking rules). */
 gl_status gl_autotune(gl_ctx *ctx, const double *params, int64_t n_sets,
                       const double *times, const int64_t *offsets, int64_t n_times,
                       const int32_t *n_ss, const double *t_exp, double *out,
                       void *stream);
 
-/* Current plan: persistent wavefronts per compute unit of the work-list
- * kernels (trapezoid, hard-sample and arc stages). */
+/* Current plan: persistent wavefronts per compute unit of the trapezoid and
+ * hard-sample kernels. */
 gl_status gl_ctx_get_plan(const gl_ctx *ctx, int *waves_per_cu);
 
-/* Sets the plan; waves_per_cu in [1, 32] (default 16). */
+/* Sets that part of the plan; waves_per_cu in [1, 64] (default 16). */
 gl_status gl_ctx_set_plan(gl_ctx *ctx, int waves_per_cu);
+
+/* The whole plan: persistent wavefronts per compute unit of the
+ * classification (default 24), the trapezoid and hard-sample kernels
+ * (default 16, the value of gl_ctx_get_plan) and the arc-rule levels
+ * (default 20).  Any pointer may be NULL. */
+gl_status gl_ctx_get_stage_plan(const gl_ctx *ctx, int *classify, int *trap_hard, int *gk);
+
+/* Sets the whole plan; each value in [1, 64], else GL_ERR_SIZE. */
+gl_status gl_ctx_set_stage_plan(gl_ctx *ctx, int classify, int trap_hard, int gk);
 
 /* Work-list capacities of the exact path, in entries: sub-sample flux slots
  * (and trapezoid entries) <= 2^27 - 1, hard samples and ellipse arcs

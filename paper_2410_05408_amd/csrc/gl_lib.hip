@@ -1667,7 +1667,9 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
 struct gl_ctx {
     int device = 0;
     int n_cu = 256;
-    int waves_per_cu = 16;  // persistent waves per CU of the list kernels
+    int waves_per_cu = 16;  // persistent waves per CU of the trapezoid and hard-sample kernels
+    int waves_classify = GL_CLASSIFY_WAVES_PER_CU;  // of the classification
+    int waves_gk = GL_GK_WAVES_PER_CU;              // of the arc-rule levels
     bool use_graph = true;
     char err[256] = {};  // last host-side error (fixed buffer: error paths allocate nothing)
     // workspace
@@ -1694,7 +1696,7 @@ struct gl_ctx {
         const double* t_exp;
         double* out;
         void* stream;
-        int waves;
+        int waves, waves_classify, waves_gk;
         void* ws;
         int passes;
         int shape;
@@ -2034,11 +2036,11 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     GL_STAGE_DONE();
     const unsigned waves = (unsigned)std::max<int64_t>(4, n_cu * ctx->waves_per_cu);
     if (sur)
-        hipLaunchKernelGGL((k_classify<false, true>), dim3((unsigned)(n_cu * GL_CLASSIFY_WAVES_PER_CU)), dim3(64), 0, st, b.times,
+        hipLaunchKernelGGL((k_classify<false, true>), dim3((unsigned)(n_cu * ctx->waves_classify)), dim3(64), 0, st, b.times,
                            shared, ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks, ctx->chunk_set,
                            ctx->chunk_fb);
     else
-        hipLaunchKernelGGL((k_classify<CENSUS, false>), dim3((unsigned)(n_cu * GL_CLASSIFY_WAVES_PER_CU)), dim3(64), 0, st,
+        hipLaunchKernelGGL((k_classify<CENSUS, false>), dim3((unsigned)(n_cu * ctx->waves_classify)), dim3(64), 0, st,
                            b.times, shared, ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks,
                            ctx->chunk_set, ctx->chunk_fb);
     GL_STAGE_DONE();
@@ -2059,7 +2061,7 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     GL_STAGE_DONE();
     hipLaunchKernelGGL(k_nested<CENSUS>, dim3((unsigned)(n_cu * 4)), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
     GL_STAGE_DONE();
-    launch_arcs<CENSUS>(ctx, st, GL_GK_WAVES_PER_CU > 0 ? (unsigned)(n_cu * GL_GK_WAVES_PER_CU) : waves, P);
+    launch_arcs<CENSUS>(ctx, st, ctx->waves_gk > 0 ? (unsigned)(n_cu * ctx->waves_gk) : waves, P);
     GL_STAGE_DONE();
     hipLaunchKernelGGL(k_combine, dim3((unsigned)(n_cu * 8)), dim3(256), 0, st, ctx->sc, ctx->ctr, P);
     if (fork) GL_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0), "hipStreamWaitEvent");
@@ -2306,6 +2308,8 @@ gl_status lightcurve(gl_ctx* ctx, Batch& b)
     k.out = out;
     k.stream = stream;
     k.waves = ctx->waves_per_cu;
+    k.waves_classify = ctx->waves_classify;
+    k.waves_gk = ctx->waves_gk;
     k.ws = ctx->masks;
     k.passes = ctx->passes;
     k.shape = b.shape;
@@ -2409,10 +2413,31 @@ gl_status gl_ctx_get_plan(const gl_ctx* ctx, int* waves_per_cu)
     return GL_OK;
 }
 
+gl_status gl_ctx_get_stage_plan(const gl_ctx* ctx, int* classify, int* trap_hard, int* gk)
+{
+    if (!ctx) return GL_ERR_NULL;
+    if (classify) *classify = ctx->waves_classify;
+    if (trap_hard) *trap_hard = ctx->waves_per_cu;
+    if (gk) *gk = ctx->waves_gk;
+    return GL_OK;
+}
+
+gl_status gl_ctx_set_stage_plan(gl_ctx* ctx, int classify, int trap_hard, int gk)
+{
+    if (!ctx) return GL_ERR_NULL;
+    if (classify < 1 || classify > 64 || trap_hard < 1 || trap_hard > 64 || gk < 1 || gk > 64)
+        return fail(ctx, GL_ERR_SIZE, "waves per CU in [1, 64]");
+    ctx->waves_classify = classify;
+    ctx->waves_per_cu = trap_hard;
+    ctx->waves_gk = gk;
+    drop_graph(ctx);
+    return GL_OK;
+}
+
 gl_status gl_ctx_set_plan(gl_ctx* ctx, int waves_per_cu)
 {
     if (!ctx) return GL_ERR_NULL;
-    if (waves_per_cu < 1 || waves_per_cu > 32) return fail(ctx, GL_ERR_SIZE, "waves_per_cu in [1, 32]");
+    if (waves_per_cu < 1 || waves_per_cu > 64) return fail(ctx, GL_ERR_SIZE, "waves_per_cu in [1, 64]");
     ctx->waves_per_cu = waves_per_cu;
     return GL_OK;
 }
@@ -2435,37 +2460,59 @@ gl_status gl_autotune(gl_ctx* ctx, const double* params, int64_t n_sets, const d
     GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     st = prepare_batch(ctx, b);
     if (st != GL_OK) return st;
-    const bool graph = ctx->use_graph;
     drop_graph(ctx);
     hipEvent_t e0, e1;
     GL_HIP(hipEventCreate(&e0), "hipEventCreate");
     GL_HIP(hipEventCreate(&e1), "hipEventCreate");
-    const int cands[] = {4, 8, 16, 24, 32};
-    int best = ctx->waves_per_cu;
-    float best_ms = 1e30f;
-    for (int w : cands) {
-        ctx->waves_per_cu = w;
-        st = enqueue(ctx, b);  // warm-up
-        if (st != GL_OK) break;
+    // coordinate descent over the three grid sizes: trapezoid and hard-sample
+    // kernels, classification, arc levels (each candidate: one warm-up batch,
+    // then three timed).  Candidates run the way the batch call will run them:
+    // captured and replayed as a graph where the caller's stream allows one
+    // (branches of a graph and of direct launches overlap differently).
+    auto time_plan = [&](float& ms_out) -> gl_status {
+        Batch c = b;
+        gl_status r = lightcurve(ctx, c);  // warm-up (and the capture)
+        if (r != GL_OK) return r;
         float tot = 0.0f;
-        for (int r = 0; r < 3; ++r) {
+        for (int rep = 0; rep < 3; ++rep) {
             (void)hipEventRecord(e0, b.stream);
-            st = enqueue(ctx, b);
+            c = b;
+            r = lightcurve(ctx, c);
             (void)hipEventRecord(e1, b.stream);
             (void)hipEventSynchronize(e1);
             float ms = 0.0f;
             (void)hipEventElapsedTime(&ms, e0, e1);
             tot += ms;
         }
-        if (tot < best_ms) {
-            best_ms = tot;
-            best = w;
+        ms_out = tot;
+        return r;
+    };
+    struct Knob {
+        int* v;
+        std::vector<int> cands;
+    };
+    Knob knobs[3] = {{&ctx->waves_per_cu, {8, 16, 24, 32, 48, 64}},
+                     {&ctx->waves_classify, {8, 16, 24, 32, 48}},
+                     {&ctx->waves_gk, {8, 12, 16, 20, 32, 48}}};
+    for (Knob& kn : knobs) {
+        int best = *kn.v;
+        float best_ms = 1e30f;
+        for (int w : kn.cands) {
+            *kn.v = w;
+            float ms = 0.0f;
+            st = time_plan(ms);
+            if (st != GL_OK) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = w;
+            }
         }
+        *kn.v = best;
+        if (st != GL_OK) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    ctx->waves_per_cu = best;
-    ctx->use_graph = graph;
+    drop_graph(ctx);
     return st;
 }
 

@@ -33,7 +33,7 @@ EXPORTED = ("gl_ctx_create", "gl_ctx_destroy", "gl_lightcurve_batch", "gl_ctx_sy
             "gl_ctx_get_stage_timing", "gl_census", "gl_flop_model", "gl_ctx_get_unconverged",
             "gl_ctx_get_overflow", "gl_lightcurve_batch_noalloc", "gl_lightcurve_batch_snap", "gl_version",
             "gl_lightcurve_batch_ellipsoid", "gl_prior_mu_nu", "gl_walkers_to_params",
-            "gl_loglike_of_model", "gl_loglike_batch")
+            "gl_loglike_of_model", "gl_loglike_batch", "gl_ctx_get_stage_plan", "gl_ctx_set_stage_plan")
 CENSUS_NAMES = ("sub_in_window", "whole_on_star", "intersecting", "off_star_in_window",
                 "trapezoid_nodes", "gk21_pieces", "newton_steps", "limb_arcs",
                 "nested_trapezoid_nodes", "ellipse_arcs", "unconverged_arcs")
@@ -90,6 +90,10 @@ def lib():
         L.gl_ctx_get_plan.restype = i
         L.gl_ctx_set_plan.argtypes = [vp, i]
         L.gl_ctx_set_plan.restype = i
+        L.gl_ctx_get_stage_plan.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
+        L.gl_ctx_get_stage_plan.restype = i
+        L.gl_ctx_set_stage_plan.argtypes = [vp, i, i, i]
+        L.gl_ctx_set_stage_plan.restype = i
         L.gl_ctx_set_graph.argtypes = [vp, i]
         L.gl_ctx_set_graph.restype = i
         L.gl_ctx_set_timing.argtypes = [vp, i]
@@ -306,6 +310,17 @@ def gl_ctx_get_plan(ctx) -> int:
 
 def gl_ctx_set_plan(ctx, waves_per_cu: int) -> None:
     _check(ctx, lib().gl_ctx_set_plan(ctx, int(waves_per_cu)))
+
+
+def gl_ctx_get_stage_plan(ctx):
+    """(classify, trap_hard, gk) persistent wavefronts per compute unit."""
+    c, t, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(ctx, lib().gl_ctx_get_stage_plan(ctx, ctypes.byref(c), ctypes.byref(t), ctypes.byref(g)))
+    return c.value, t.value, g.value
+
+
+def gl_ctx_set_stage_plan(ctx, classify: int, trap_hard: int, gk: int) -> None:
+    _check(ctx, lib().gl_ctx_set_stage_plan(ctx, int(classify), int(trap_hard), int(gk)))
 
 
 def gl_ctx_set_graph(ctx, on: bool) -> None:
