@@ -134,7 +134,8 @@ def measured_traffic(kernel):
 
 
 STAGE_KERNELS = {"window": "k_window_grid", "classify": "k_classify", "trapezoid": "k_trap",
-                 "hard": "k_hard", "nested": "k_nested", "arcs": "k_gk<0>, k_gk<1>, k_gk_tail",
+                 "hard": "k_hard", "nested": "k_rare (nested trapezoid, in-place samples, arcs from level 2)",
+                 "arcs": "k_gk<0>, k_gk<1>",
                  "combine": "k_combine + k_average"}
 # stages whose work is FP64 arithmetic (the others move data)
 FLOP_STAGES = ("classify", "trapezoid", "hard", "nested", "arcs")

@@ -307,8 +307,9 @@ gl_status gl_ctx_set_graph(gl_ctx *ctx, int on);
  *  0 set-up (parameter preparation, chunk scan), 1 window test (fills the
  *  outputs that cannot overlap the star), 2 classification, 3 whole-ellipse
  *  trapezoid, 4 hard samples (intersection quartic, break points, limb arcs),
- *  5 nested trapezoid for whole ellipses near the limb, 6 ellipse arcs
- *  (Gauss-Kronrod levels 0..4), 7 combination of each hard sample's sums and
+ *  5 ellipse arcs (Gauss-Kronrod levels 0 and 1), 6 rare paths (nested
+ *  trapezoid for whole ellipses near the limb, samples integrated in place,
+ *  arcs from level 2 on), 7 combination of each hard sample's sums and
  *  supersample averages, 8 fused kernel for chunks beyond the work-list
  *  capacities. */
 #define GL_NSTAGES 9

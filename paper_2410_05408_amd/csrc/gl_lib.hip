@@ -19,11 +19,13 @@
 //   k_hard      one thread per hard entry: intersection quartic, break points,
 //               limb arcs in closed form, ellipse arcs appended to an arc list;
 //               whole ellipses near the limb go to the nested-trapezoid list.
-//   k_nested    one thread per nested entry: nested periodic trapezoid.
 //   k_gk<L>     level L = 0, 1 of the self-checking arc rule: one thread per
 //               Gauss-Kronrod piece (2^L pieces per arc, summed across lanes);
 //               arcs whose error estimate is too large go on to level L + 1.
-//   k_gk_tail   the few arcs that reach level 2: the rule from there on, per lane.
+//   k_rare      the rare paths in one launch: one thread per in-place entry
+//               (nested periodic trapezoid, or the whole boundary walk with the
+//               arc rule in place), and one per arc that reached level 2 (the
+//               rule from there on).
 //   k_combine   one thread per hard entry: limb sums + its arcs -> flux.
 //   k_average   one wavefront per listed chunk: box average of each output's
 //               sub-samples in a fixed order (deterministic).
@@ -480,6 +482,19 @@ __device__ __forceinline__ int64_t shard_slot_run(const ShardMap& m, int64_t g, 
     return shard_slot(m, g, scap);
 }
 
+// shard_slot for a wave-uniform index g: the shard found with scalar reads of
+// the prefix counts (no cross-lane shuffles).
+__device__ __forceinline__ int64_t shard_slot_uniform(const ShardMap& m, int64_t g, int64_t scap)
+{
+    g = uniform64(g);
+    int j = 0;
+#pragma unroll
+    for (int step = kShards / 2; step >= 1; step >>= 1)
+        if (readlane64(m.incl, j + step - 1) <= g) j += step;
+    const int64_t prev = j > 0 ? readlane64(m.incl, j - 1) : 0;
+    return (int64_t)j * scap + (g - prev);
+}
+
 // Queues chunk c for the fused kernel once (the first caller wins).
 __device__ __forceinline__ void to_fused(Counters* ctr, const Pipe& P, int* chunk_fb, int64_t c)
 {
@@ -694,7 +709,7 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
     const ShardMap m = shard_map(ctr, L_GRP, gcap);
     unsigned long long c_in = 0, c_whole = 0, c_off = 0, c_sur_in = 0, c_sur_on = 0, c_sur_acc = 0;
     for (int64_t gi = blockIdx.x; gi < m.total; gi += gridDim.x) {
-        const Group G = P.grp[shard_slot(m, gi, gcap)];
+        const Group G = P.grp[shard_slot_uniform(m, gi, gcap)];
         const int64_t c = uniform64(G.c);
         if (c < 0) continue;
         const int64_t base = uniform64(G.base);
@@ -920,7 +935,7 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
     ArcRec* al = P.arcs + (int64_t)shard * acap;
     for (int64_t g0 = (int64_t)blockIdx.x * 64; g0 < m.total; g0 += (int64_t)gridDim.x * 64) {
         const int64_t g = g0 + lane;
-        const int64_t slot = shard_slot(m, g < m.total ? g : 0, scap);
+        const int64_t slot = shard_slot_run(m, g < m.total ? g : 0, g0, std::min(g0 + 63, m.total - 1), scap);
         Entry e{0.0, 0.0, -1, 0};
         if (g < m.total) e = P.hard[slot];
         const bool valid = g < m.total && e.set >= 0;
@@ -1048,9 +1063,10 @@ k_hard(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
 // nested periodic trapezoid 8 -> 64 per thread (cluster arcs in place if it
 // does not settle); samples whose arcs did not fit the arc list take the
 // whole boundary walk with the arc rule in place.
+// (workgroups bid of nb of the rare-path launch)
 template <bool CENSUS>
-__global__ void __launch_bounds__(64)
-k_nested(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P)
+__device__ __forceinline__ void nested_part(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr,
+                                            const Pipe& P, int64_t bid, int64_t nb)
 {
     const int lane = threadIdx.x;
     const int64_t scap = P.scap[L_NEST];
@@ -1058,9 +1074,9 @@ k_nested(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P
     unsigned long long nodes = 0;
     gl::Census ct;
     gl::NoCensus nc;
-    for (int64_t g0 = (int64_t)blockIdx.x * 64; g0 < m.total; g0 += (int64_t)gridDim.x * 64) {
+    for (int64_t g0 = bid * 64; g0 < m.total; g0 += nb * 64) {
         const int64_t g = g0 + lane;
-        const int64_t slot = shard_slot(m, g < m.total ? g : 0, scap);
+        const int64_t slot = shard_slot_run(m, g < m.total ? g : 0, g0, std::min(g0 + 63, m.total - 1), scap);
         if (g >= m.total) continue;
         const Entry e = P.nest[slot];
         const int sub = e.sub & kSubMask;
@@ -1126,7 +1142,7 @@ k_gk(Counters* __restrict__ ctr, Pipe P)
         const int64_t p = p0 + lane;
         const bool valid = p < n;
         const int q = (int)(p & (np - 1));
-        const int64_t slot = shard_slot(m, valid ? (p >> L) : 0, scap);
+        const int64_t slot = shard_slot_run(m, valid ? (p >> L) : 0, p0 >> L, std::min(p0 + 63, n - 1) >> L, scap);
         ArcRef r{-1, -1};
         gl::Sums K{0.0, 0.0, 0.0};
         double err = 0.0;
@@ -1170,19 +1186,18 @@ k_gk(Counters* __restrict__ ctr, Pipe P)
 }
 
 // Arcs that failed levels 0 and 1 (rare): one thread per arc runs the rule
-// from level 2 on in place.
+// from level 2 on in place (workgroups bid of nb of the rare-path launch).
 template <bool CENSUS>
-__global__ void __launch_bounds__(64)
-k_gk_tail(Counters* __restrict__ ctr, Pipe P)
+__device__ __forceinline__ void gk_tail_part(Counters* __restrict__ ctr, const Pipe& P, int64_t bid, int64_t nb)
 {
     const int lane = threadIdx.x;
     const int64_t scap = P.scap[L_LVL0 + 2];
     const ShardMap m = shard_map(ctr, L_LVL0 + 2, scap);
     gl::Census ct;
     gl::NoCensus nc;
-    for (int64_t g0 = (int64_t)blockIdx.x * 64; g0 < m.total; g0 += (int64_t)gridDim.x * 64) {
+    for (int64_t g0 = bid * 64; g0 < m.total; g0 += nb * 64) {
         const int64_t g = g0 + lane;
-        const int64_t slot = shard_slot(m, g < m.total ? g : 0, scap);
+        const int64_t slot = shard_slot_run(m, g < m.total ? g : 0, g0, std::min(g0 + 63, m.total - 1), scap);
         if (g >= m.total) continue;
         const ArcRef r = P.lvl[2][slot];
         const ArcRec A = P.arcs[r.arc];
@@ -1196,6 +1211,18 @@ k_gk_tail(Counters* __restrict__ ctr, Pipe P)
     unconverged_add(ctr, CENSUS ? ct.unconv : nc.unconv, CENSUS);
 }
 
+// The two rare paths in one launch, after the arc levels: the in-place list
+// (nested trapezoid, samples integrated in place; independent of the arc
+// lists) on the first nb_nest workgroups, the arcs that reached level 2 on
+// the rest.
+template <bool CENSUS>
+__global__ void __launch_bounds__(64)
+k_rare(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pipe P, int nb_nest)
+{
+    if ((int)blockIdx.x < nb_nest) nested_part<CENSUS>(sc, ctr, P, blockIdx.x, nb_nest);
+    else gk_tail_part<CENSUS>(ctr, P, (int64_t)blockIdx.x - nb_nest, (int64_t)gridDim.x - nb_nest);
+}
+
 // Hard samples with ellipse arcs: limb sums plus the accepted arc sums in
 // list order -> flux.
 __global__ void __launch_bounds__(256)
@@ -1207,7 +1234,7 @@ k_combine(const gl::SetConst* __restrict__ sc, const Counters* __restrict__ ctr,
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); g0 < m.total; g0 += stride) {
         const int64_t g = g0 + lane;
-        const int64_t slot = shard_slot(m, g < m.total ? g : 0, scap);
+        const int64_t slot = shard_slot_run(m, g < m.total ? g : 0, g0, std::min(g0 + 63, m.total - 1), scap);
         if (g >= m.total) continue;
         const HardRec& R = P.hrec[slot];
         const int na = R.n_arcs;
@@ -1325,7 +1352,7 @@ k_net_gather(const gl::SetConst* __restrict__ sc, Counters* __restrict__ ctr, Pi
     if (blockIdx.x == 0 && lane == 0) ctr->net_total = (unsigned long long)m.total;
     for (int64_t g0 = (int64_t)blockIdx.x * 64; g0 < m.total; g0 += (int64_t)gridDim.x * 64) {
         const int64_t g = g0 + lane;
-        const int64_t slot = shard_slot(m, g < m.total ? g : 0, scap);
+        const int64_t slot = shard_slot_run(m, g < m.total ? g : 0, g0, std::min(g0 + 63, m.total - 1), scap);
         if (g >= m.total) continue;
         const Entry e = P.net[slot];
         float fe[gl::kSurFeat];
@@ -1370,7 +1397,7 @@ k_average(const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_b
     const int64_t wcap = P.scap[L_WC];
     const ShardMap m = shard_map(ctr, L_WC, wcap);
     for (int64_t w = blockIdx.x; w < m.total; w += gridDim.x) {
-        const WorkChunk W = P.wc[shard_slot(m, w, wcap)];
+        const WorkChunk W = P.wc[shard_slot_uniform(m, w, wcap)];
         const int64_t base = uniform64(W.base), c = uniform64(W.c);
         if (base < 0) continue;
         if (__builtin_amdgcn_readfirstlane(chunk_fb[c])) continue;  // evaluated by the fused kernel
@@ -1991,8 +2018,16 @@ void launch_arcs(gl_ctx* ctx, hipStream_t st, unsigned grid, const Pipe& P)
 {
     hipLaunchKernelGGL((k_gk<0, CENSUS>), dim3(grid), dim3(64), 0, st, ctx->ctr, P);
     hipLaunchKernelGGL((k_gk<1, CENSUS>), dim3(grid), dim3(64), 0, st, ctx->ctr, P);
-    // few arcs reach the deeper levels: one small launch finishes them per lane
-    hipLaunchKernelGGL((k_gk_tail<CENSUS>), dim3(std::max(1u, grid / 16)), dim3(64), 0, st, ctx->ctr, P);
+}
+
+// few arcs reach the deeper levels and few samples take the in-place list:
+// one launch finishes both, per lane
+template <bool CENSUS>
+void launch_rare(gl_ctx* ctx, hipStream_t st, unsigned arc_grid, const Pipe& P)
+{
+    const int nb_nest = (int)(ctx->n_cu * 4);
+    const unsigned grid = (unsigned)nb_nest + std::max(1u, arc_grid / 16);
+    hipLaunchKernelGGL((k_rare<CENSUS>), dim3(grid), dim3(64), 0, st, ctx->sc, ctx->ctr, P, nb_nest);
 }
 
 template <bool CENSUS>
@@ -2059,9 +2094,10 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     GL_STAGE_DONE();
     hipLaunchKernelGGL(k_hard<CENSUS>, dim3(waves), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
     GL_STAGE_DONE();
-    hipLaunchKernelGGL(k_nested<CENSUS>, dim3((unsigned)(n_cu * 4)), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
+    const unsigned arc_grid = ctx->waves_gk > 0 ? (unsigned)(n_cu * ctx->waves_gk) : waves;
+    launch_arcs<CENSUS>(ctx, st, arc_grid, P);
     GL_STAGE_DONE();
-    launch_arcs<CENSUS>(ctx, st, ctx->waves_gk > 0 ? (unsigned)(n_cu * ctx->waves_gk) : waves, P);
+    launch_rare<CENSUS>(ctx, st, arc_grid, P);
     GL_STAGE_DONE();
     hipLaunchKernelGGL(k_combine, dim3((unsigned)(n_cu * 8)), dim3(256), 0, st, ctx->sc, ctx->ctr, P);
     if (fork) GL_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0), "hipStreamWaitEvent");

@@ -38,7 +38,7 @@ CENSUS_NAMES = ("sub_in_window", "whole_on_star", "intersecting", "off_star_in_w
                 "trapezoid_nodes", "gk21_pieces", "newton_steps", "limb_arcs",
                 "nested_trapezoid_nodes", "ellipse_arcs", "unconverged_arcs")
 GL_NSTAGES = 9
-STAGE_NAMES = ("setup", "window", "classify", "trapezoid", "hard", "nested", "arcs", "combine", "fused")
+STAGE_NAMES = ("setup", "window", "classify", "trapezoid", "hard", "arcs", "nested", "combine", "fused")
 
 
 class GLError(RuntimeError):
