@@ -28,10 +28,12 @@
 //               rule from there on).
 //   k_combine   one thread per hard entry: limb sums + its arcs -> flux.
 //   k_average   one wavefront per listed chunk: box average of each output's
-//               sub-samples in a fixed order (deterministic).
+//               sub-samples in a fixed order (deterministic); its first
+//               wavefront records the pass's work-list demand (sizes the next
+//               batch).
 //   k_compute   the fused per-lane evaluation, for chunks whose sub-samples
-//               did not fit the work-list capacities; its first wavefront
-//               records the pass's work-list demand (sizes the next batch).
+//               did not fit the work-list capacities (and the chunks of
+//               tidally-locked sets); returns at once when none is queued.
 // A batch too large for one pass runs the pipeline once per range of sets.
 // Every list is appended through per-shard counters (see kShards).  The
 // launches are captured once into a HIP graph and replayed while the
@@ -1384,43 +1386,6 @@ __global__ void k_net_add(const Counters* __restrict__ ctr, Pipe P)
     }
 }
 
-// One wavefront per listed chunk: each in-window output averages its
-// sub-sample fluxes in order (loaded 16 at a time, so that one memory round
-// trip serves up to 16 of them, then summed one by one).
-__global__ void __launch_bounds__(64)
-k_average(const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_begin,
-          const int64_t* __restrict__ chunk_off, const Counters* __restrict__ ctr, Pipe P,
-          const unsigned long long* __restrict__ masks, const int* __restrict__ chunk_set,
-          const int* __restrict__ chunk_fb, double* __restrict__ out)
-{
-    const int lane = threadIdx.x;
-    const int64_t wcap = P.scap[L_WC];
-    const ShardMap m = shard_map(ctr, L_WC, wcap);
-    for (int64_t w = blockIdx.x; w < m.total; w += gridDim.x) {
-        const WorkChunk W = P.wc[shard_slot_uniform(m, w, wcap)];
-        const int64_t base = uniform64(W.base), c = uniform64(W.c);
-        if (base < 0) continue;
-        if (__builtin_amdgcn_readfirstlane(chunk_fb[c])) continue;  // evaluated by the fused kernel
-        const unsigned long long M = (unsigned long long)uniform64((int64_t)W.mask);
-        const int nss = __builtin_amdgcn_readfirstlane(W.nss);
-        const int64_t i0 = uniform64(W.i0);
-        if ((M >> lane) & 1ull) {
-            const int64_t o = lanes_below(M);
-            const double* f = P.fsub + base + o * nss;
-            double sum = 0.0;
-            for (int j0 = 0; j0 < nss; j0 += 16) {
-                double v[16];
-#pragma unroll
-                for (int j = 0; j < 16; ++j) v[j] = j0 + j < nss ? f[j0 + j] : 0.0;
-#pragma unroll
-                for (int j = 0; j < 16; ++j)
-                    if (j0 + j < nss) sum += v[j];
-            }
-            out[i0 + lane] = sum / (double)nss;
-        }
-    }
-}
-
 // Updates the demand record at the end of every pass (in device memory) and
 // stores a copy into the host's pinned record, which the host reads when it
 // plans the next batch (a stale read only delays a resize).  Only stores
@@ -1483,6 +1448,46 @@ __device__ void demand_update(Counters* __restrict__ ctr, const Pipe& P, const D
         ctr->fused_batch += n_fb;
     }
 }
+
+// One wavefront per listed chunk: each in-window output averages its
+// sub-sample fluxes in order (loaded 16 at a time, so that one memory round
+// trip serves up to 16 of them, then summed one by one).
+__global__ void __launch_bounds__(64)
+k_average(const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_begin,
+          const int64_t* __restrict__ chunk_off, Counters* __restrict__ ctr, Pipe P,
+          const unsigned long long* __restrict__ masks, const int* __restrict__ chunk_set,
+          const int* __restrict__ chunk_fb, DemandArgs dem, double* __restrict__ out)
+{
+    // the pass's lists are complete here: the first wavefront records their demand
+    if (blockIdx.x == 0 && dem.rec) demand_update(ctr, P, dem);
+    const int lane = threadIdx.x;
+    const int64_t wcap = P.scap[L_WC];
+    const ShardMap m = shard_map(ctr, L_WC, wcap);
+    for (int64_t w = blockIdx.x; w < m.total; w += gridDim.x) {
+        const WorkChunk W = P.wc[shard_slot_uniform(m, w, wcap)];
+        const int64_t base = uniform64(W.base), c = uniform64(W.c);
+        if (base < 0) continue;
+        if (__builtin_amdgcn_readfirstlane(chunk_fb[c])) continue;  // evaluated by the fused kernel
+        const unsigned long long M = (unsigned long long)uniform64((int64_t)W.mask);
+        const int nss = __builtin_amdgcn_readfirstlane(W.nss);
+        const int64_t i0 = uniform64(W.i0);
+        if ((M >> lane) & 1ull) {
+            const int64_t o = lanes_below(M);
+            const double* f = P.fsub + base + o * nss;
+            double sum = 0.0;
+            for (int j0 = 0; j0 < nss; j0 += 16) {
+                double v[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) v[j] = j0 + j < nss ? f[j0 + j] : 0.0;
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    if (j0 + j < nss) sum += v[j];
+            }
+            out[i0 + lane] = sum / (double)nss;
+        }
+    }
+}
+
 
 // Sub-samples of one chunk kept in LDS by the three-phase path (n_ss <= 16).
 constexpr int kMaxSubLds = kChunk * 16;
@@ -1574,10 +1579,9 @@ __global__ void GL_COMPUTE_ATTR
 k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst* __restrict__ sc,
           const int64_t* __restrict__ seg_begin, const int64_t* __restrict__ chunk_off,
           Counters* __restrict__ ctr, const unsigned long long* __restrict__ masks,
-          const int* __restrict__ chunk_set, Pipe P, DemandArgs dem, double* __restrict__ out)
+          const int* __restrict__ chunk_set, Pipe P, double* __restrict__ out)
 {
-    // the pass's lists are complete here: the first wavefront records their demand
-    if (blockIdx.x == 0 && dem.rec) demand_update(ctr, P, dem);
+    if (ctr->n_fb == 0ull) return;  // nothing queued (the usual case): no work head to touch
     const int64_t* __restrict__ fb_chunk = P.fb_chunk;
     __shared__ double lds_f[kMaxSubLds];   // sub-sample fluxes of the chunk
     __shared__ short lds_def[kMaxSubLds];  // deferred (hard) sub-samples
@@ -2107,19 +2111,19 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
         gl_net::infer(b.net, P.net_x, (int64_t)kShards * P.scap[L_NET], &ctx->ctr->net_total, P.net_y, st);
         hipLaunchKernelGGL(k_net_add, dim3((unsigned)(n_cu * 8)), dim3(256), 0, st, ctx->ctr, P);
     }
+    const DemandArgs dem{ctx->rec_dev, b.first, b.last, ctx->passes, (double)b.slots};
     hipLaunchKernelGGL(k_average, dim3((unsigned)(n_cu * 32)), dim3(64), 0, st, ctx->sc,
                        ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks, ctx->chunk_set,
-                       ctx->chunk_fb, b.out);
+                       ctx->chunk_fb, dem, b.out);
     GL_STAGE_DONE();
-    const DemandArgs dem{ctx->rec_dev, b.first, b.last, ctx->passes, (double)b.slots};
     // the fused kernel takes the chunks the lists could not hold (few: a
     // quarter wave per CU), and every chunk of a tidally-locked set (general
     // ellipsoids: a full grid at its occupancy of two waves per SIMD)
-    const unsigned fused_grid = b.shape ? (unsigned)(n_cu * 8) : (unsigned)std::max<int64_t>(1, n_cu / 4);
+    const unsigned fused_grid = b.shape == 1 ? (unsigned)(n_cu * 8) : (unsigned)std::max<int64_t>(1, n_cu / 4);
     auto fused = b.shape == 1 ? k_compute<CENSUS, true> : k_compute<CENSUS, false>;
     hipLaunchKernelGGL(fused, dim3(fused_grid), dim3(64), 0, st, b.times, shared,
                        ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, ctx->masks, ctx->chunk_set,
-                       P, dem, b.out);
+                       P, b.out);
     GL_STAGE_DONE();
 #undef GL_STAGE_DONE
     GL_HIP(hipGetLastError(), "kernel launch");
