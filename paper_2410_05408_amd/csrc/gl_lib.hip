@@ -710,8 +710,13 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
     const int64_t gcap = P.scap[L_GRP];
     const ShardMap m = shard_map(ctr, L_GRP, gcap);
     unsigned long long c_in = 0, c_whole = 0, c_off = 0, c_sur_in = 0, c_sur_on = 0, c_sur_acc = 0;
+    // each group record is loaded one iteration ahead (its latency overlaps
+    // the current group's work)
+    Group Gn{};
+    if ((int64_t)blockIdx.x < m.total) Gn = P.grp[shard_slot_uniform(m, blockIdx.x, gcap)];
     for (int64_t gi = blockIdx.x; gi < m.total; gi += gridDim.x) {
-        const Group G = P.grp[shard_slot_uniform(m, gi, gcap)];
+        const Group G = Gn;
+        if (gi + gridDim.x < m.total) Gn = P.grp[shard_slot_uniform(m, gi + gridDim.x, gcap)];
         const int64_t c = uniform64(G.c);
         if (c < 0) continue;
         const int64_t base = uniform64(G.base);
@@ -1463,8 +1468,11 @@ k_average(const gl::SetConst* __restrict__ sc, const int64_t* __restrict__ seg_b
     const int lane = threadIdx.x;
     const int64_t wcap = P.scap[L_WC];
     const ShardMap m = shard_map(ctr, L_WC, wcap);
+    WorkChunk Wn{};  // loaded one iteration ahead
+    if ((int64_t)blockIdx.x < m.total) Wn = P.wc[shard_slot_uniform(m, blockIdx.x, wcap)];
     for (int64_t w = blockIdx.x; w < m.total; w += gridDim.x) {
-        const WorkChunk W = P.wc[shard_slot_uniform(m, w, wcap)];
+        const WorkChunk W = Wn;
+        if (w + gridDim.x < m.total) Wn = P.wc[shard_slot_uniform(m, w + gridDim.x, wcap)];
         const int64_t base = uniform64(W.base), c = uniform64(W.c);
         if (base < 0) continue;
         if (__builtin_amdgcn_readfirstlane(chunk_fb[c])) continue;  // evaluated by the fused kernel
