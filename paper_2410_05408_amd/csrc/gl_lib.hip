@@ -109,9 +109,6 @@ struct Counters {
     // over every batch since gl_ctx_get_unconverged last read it
     unsigned long long unconverged;
     unsigned long long fused_batch;   // chunks of the latest batch evaluated by the fused kernel
-    unsigned long long sur_in;        // surrogate batches: in-window sub-samples
-    unsigned long long sur_on;        // of those, with the ellipse reaching the disk
-    unsigned long long sur_acc;       // of those, accepted by the gate
     unsigned long long net_total;     // rows of the current pass's network batch
     double ll_norm;                   // likelihood batches on a shared grid: sum log(sigma) + (N/2) log(2 pi)
     Demand demand;                    // kept here; k_demand stores a copy to the host's record
@@ -119,7 +116,12 @@ struct Counters {
     // intersecting, in-window but off the star, trapezoid nodes of the rigorous
     // rule, Gauss-Kronrod pieces, Newton steps, limb arcs, nested-trapezoid
     // nodes, ellipse arcs, arcs accepted unconverged
-    unsigned long long census[kCensus];
+    // tallies added by every wavefront of a launch go to the shard of its
+    // workgroup (one address for all of them serialises the atomics at L2);
+    // the host sums the shards
+    LineCount census[kCensus][kShards];
+    LineCount sur[3][kShards];        // surrogate batches: in-window sub-samples, of those
+                                      // reaching the disk, of those accepted by the gate
     LineCount lc[kLists][kShards];    // shard counters (reset by k_prep)
 };
 
@@ -231,12 +233,15 @@ __global__ void k_prep(const double* __restrict__ params, int64_t ld, int64_t n_
         ctr->n_fb = ctr->fb_head = 0ull;
         if (first) {
             ctr->fused_batch = 0ull;
-            ctr->sur_in = ctr->sur_on = ctr->sur_acc = 0ull;
-            for (int i = 0; i < kCensus; ++i) ctr->census[i] = 0ull;
         }
     }
     for (int64_t i = s; i < (int64_t)kLists * kShards; i += (int64_t)gridDim.x * blockDim.x)
         ctr->lc[i / kShards][i % kShards].v = 0ull;
+    if (first)
+        for (int64_t i = s; i < (int64_t)(kCensus + 3) * kShards; i += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t r = i / kShards, j = i % kShards;
+            (r < kCensus ? ctr->census[r][j] : ctr->sur[r - kCensus][j]).v = 0ull;
+        }
     if (norm && blockIdx.x == gridDim.x - 1) {
         // the extra last workgroup: a shared grid's likelihood normalisation
         // sum log(sigma) + (N/2) log(2 pi), in a fixed order
@@ -387,7 +392,7 @@ __device__ __forceinline__ int lanes_below(unsigned long long m)
 __device__ __forceinline__ void census_add(Counters* ctr, int idx, unsigned long long v)
 {
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-    if ((threadIdx.x & 63) == 0 && v) atomicAdd(&ctr->census[idx], v);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(&ctr->census[idx][blockIdx.x % kShards].v, v);
 }
 
 // Adds a wave's count of unconverged arcs (and to the census in census launches).
@@ -397,7 +402,7 @@ __device__ __forceinline__ void unconverged_add(Counters* ctr, int v, bool censu
     for (int d = 32; d >= 1; d >>= 1) u += __shfl_xor(u, d);
     if ((threadIdx.x & 63) == 0 && u) {
         atomicAdd(&ctr->unconverged, u);
-        if (census) atomicAdd(&ctr->census[10], u);
+        if (census) atomicAdd(&ctr->census[10][blockIdx.x % kShards].v, u);
     }
 }
 
@@ -829,9 +834,10 @@ k_classify(const double* __restrict__ times, int shared_grid, const gl::SetConst
             b += __shfl_xor(b, d);
         }
         if (lane == 0) {
-            if (a) atomicAdd(&ctr->sur_in, a);
-            if (o) atomicAdd(&ctr->sur_on, o);
-            if (b) atomicAdd(&ctr->sur_acc, b);
+            const int j = (int)(blockIdx.x % kShards);
+            if (a) atomicAdd(&ctr->sur[0][j].v, a);
+            if (o) atomicAdd(&ctr->sur[1][j].v, o);
+            if (b) atomicAdd(&ctr->sur[2][j].v, b);
         }
     }
 }
@@ -1694,7 +1700,7 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
         for (int i = 0; i < 8; ++i) {
             unsigned long long v = cnt.v[i];
             for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-            if (lane == 0) atomicAdd(&ctr->census[i], v);
+            if (lane == 0) atomicAdd(&ctr->census[i][blockIdx.x % kShards].v, v);
         }
     }
     unconverged_add(ctr, cnt.unconv, CENSUS);
@@ -2660,9 +2666,13 @@ gl_status gl_census(gl_ctx* ctx, const double* params, int64_t n_sets, const dou
     st = enqueue(ctx, b, true);
     if (st != GL_OK) return st;
     GL_HIP(hipStreamSynchronize(b.stream), "hipStreamSynchronize");
-    unsigned long long c[kCensus];
-    GL_HIP(hipMemcpy(c, ctx->ctr->census, sizeof(c), hipMemcpyDeviceToHost), "hipMemcpy");
-    for (int i = 0; i < kCensus; ++i) counts[i] = (int64_t)c[i];
+    std::vector<LineCount> c((size_t)kCensus * kShards);
+    GL_HIP(hipMemcpy(c.data(), ctx->ctr->census, sizeof(LineCount) * c.size(), hipMemcpyDeviceToHost), "hipMemcpy");
+    for (int i = 0; i < kCensus; ++i) {
+        unsigned long long t = 0;
+        for (int j = 0; j < kShards; ++j) t += c[(size_t)i * kShards + j].v;
+        counts[i] = (int64_t)t;
+    }
     return GL_OK;
 }
 
@@ -3383,8 +3393,11 @@ gl_status gl_lightcurve_batch_surrogate(gl_ctx* ctx, const gl_surrogate* s, doub
     if (st != GL_OK) return st;
     if (n_sub_out || n_fallback_out) {
         unsigned long long c[3] = {0ull, 0ull, 0ull};  // in window, reaching the disk, accepted
+        std::vector<LineCount> sh((size_t)3 * kShards);
         GL_HIP(hipStreamSynchronize(b.stream), "hipStreamSynchronize");
-        GL_HIP(hipMemcpy(c, &ctx->ctr->sur_in, sizeof(c), hipMemcpyDeviceToHost), "hipMemcpy");
+        GL_HIP(hipMemcpy(sh.data(), ctx->ctr->sur, sizeof(LineCount) * sh.size(), hipMemcpyDeviceToHost), "hipMemcpy");
+        for (int r = 0; r < 3; ++r)
+            for (int j = 0; j < kShards; ++j) c[r] += sh[(size_t)r * kShards + j].v;
         if (n_sub_out) *n_sub_out = (int64_t)c[0];
         if (n_fallback_out) *n_fallback_out = (int64_t)(c[1] - c[2]);
     }
