@@ -311,21 +311,29 @@ gl_status gl_ctx_set_graph(gl_ctx *ctx, int on);
  *  trapezoid for whole ellipses near the limb, samples integrated in place,
  *  arcs from level 2 on), 7 combination of each hard sample's sums and
  *  supersample averages, 8 fused kernel for chunks beyond the work-list
- *  capacities. */
+ *  capacities.  Stage 3 (on the caller's stream) runs beside stages 4 to 6
+ *  and the combination (on a second stream of the context, joined before the
+ *  averages): both need only the classification.  Stage 4 is timed from the
+ *  second stream's start, so stage times overlap and need not add up to the
+ *  batch time. */
 #define GL_NSTAGES 9
 
 /* Instrumentation: with n_slots > 0, the next n_slots batches are launched
- * directly (no graph) with a HIP event recorded on their stream before the
- * first stage and after every stage.  n_slots = 0 turns it off. */
+ * directly (no graph), with the same two-stream overlap a graph has, and
+ * record a HIP event before the first stage and after every stage of every
+ * pass, on the stream each stage runs on; each timed batch waits for its
+ * stream and adds its stage times before returning.  n_slots = 0 turns it
+ * off (and clears the sums). */
 gl_status gl_ctx_set_timing(gl_ctx *ctx, int n_slots);
 
-/* Waits for the recorded batches and returns the summed times (ms) of stages
- * 1..8 (compute) and 0..8 (pipeline) and how many batches were timed; frees
- * the slots for reuse.  Any output pointer may be NULL. */
+/* Returns the summed times (ms) from the start of stage 1 (compute) and of
+ * stage 0 (pipeline) to the end of stage 8 over the timed batches, and how
+ * many batches were timed; clears the sums.  Any output pointer may be NULL. */
 gl_status gl_ctx_get_timing(gl_ctx *ctx, double *compute_ms, double *pipeline_ms, int *n);
 
 /* Like gl_ctx_get_timing, per stage: stage_ms[GL_NSTAGES] (host memory)
- * receives the summed time of each stage over the timed batches. */
+ * receives the summed time of each stage over the timed batches (and the sums
+ * are cleared). */
 gl_status gl_ctx_get_stage_timing(gl_ctx *ctx, double *stage_ms, int *n);
 
 /* Work census: runs the batch once (same arguments and results as

@@ -1709,6 +1709,25 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
 }  // namespace
 
 // ---------------------------------------------------------------- context
+// Timing events of one pass: the caller's stream marks the start and the
+// ends of set-up, window, classification, trapezoid, averages and fused
+// stage; the second stream marks its start (its wait on the classification
+// met) and the ends of the hard samples, arc levels and rare paths.  Each
+// stage is timed between two of them (kStageEv), on the stream it runs on.
+enum {
+    E_START, E_SETUP, E_WINDOW, E_CLASSIFY, E_TRAP, E_SIDE, E_HARD, E_ARCS, E_RARE, E_AVERAGE, E_FUSED, kEvPerPass
+};
+constexpr int kStageEv[GL_NSTAGES][2] = {
+    {E_START, E_SETUP}, {E_SETUP, E_WINDOW}, {E_WINDOW, E_CLASSIFY}, {E_CLASSIFY, E_TRAP}, {E_SIDE, E_HARD},
+    {E_HARD, E_ARCS},   {E_ARCS, E_RARE},    {E_RARE, E_AVERAGE},    {E_AVERAGE, E_FUSED}};
+
+// Passes: a batch whose in-window sub-samples exceed what one pass should
+// hold runs as up to kMaxPasses passes of the whole pipeline over equal
+// ranges of its parameter sets.  Results do not depend on the split (every
+// sub-sample and output is computed by itself), only the list sizes do.
+constexpr int kMaxPasses = 8;
+constexpr int64_t kPassSub = (int64_t)1 << 26;  // in-window sub-samples one pass aims at
+
 struct gl_ctx {
     int device = 0;
     int n_cu = 256;
@@ -1768,10 +1787,13 @@ struct gl_ctx {
     int64_t auto_scap[kLists] = {};
     int64_t mem_total = 0;
     int passes = 1;  // passes of the current batch (plan_passes)
-    // per-launch timing: an event before the first and after every stage of
-    // every pass; t_used counts pass slots, t_batches batches
-    int t_slots = 0, t_used = 0, t_batches = 0;
-    hipEvent_t* ev = nullptr;  // (GL_NSTAGES + 1) events per slot
+    // timing of the next t_left batches: launched directly (the HIP runtime
+    // a torch process loads rejects event records captured into a graph),
+    // one set of stage events per pass, read right after the batch
+    int t_left = 0, t_pass = 0, t_batches = 0;
+    hipEvent_t* ev = nullptr;  // kEvPerPass x kMaxPasses
+    double t_stage[GL_NSTAGES] = {};
+    double t_comp = 0.0, t_pipe = 0.0;
     // a second stream for the trapezoid stage, which depends on the
     // classification only and runs beside the hard-sample chain
     hipStream_t side = nullptr;
@@ -2048,20 +2070,35 @@ void launch_rare(gl_ctx* ctx, hipStream_t st, unsigned arc_grid, const Pipe& P)
     hipLaunchKernelGGL((k_rare<CENSUS>), dim3(grid), dim3(64), 0, st, ctx->sc, ctx->ctr, P, nb_nest);
 }
 
+// A timing event (timed batches are launched directly, never captured); on
+// failure the context's error names the pass and the event.
+gl_status record_event(gl_ctx* ctx, hipEvent_t ev, hipStream_t s, int e)
+{
+    const hipError_t r = hipEventRecord(ev, s);
+    if (r == hipSuccess) return GL_OK;
+    char what[64];
+    std::snprintf(what, sizeof(what), "timing event %d of pass %d", e, ctx->t_pass - 1);
+    return fail(ctx, GL_ERR_DEVICE, what, r);
+}
+
 template <bool CENSUS>
 gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
 {
     const int shared = b.offsets ? 0 : 1;
     hipStream_t st = b.stream;
     hipEvent_t* ev = nullptr;
-    int e = 0;
-    if (!CENSUS && ctx->t_slots > 0 && ctx->t_used < ctx->t_slots) {
-        ev = ctx->ev + (GL_NSTAGES + 1) * ctx->t_used;
-        ctx->t_used++;
-        GL_HIP(hipEventRecord(ev[e++], st), "hipEventRecord");
+    if (!CENSUS && ctx->t_left > 0 && ctx->ev && ctx->t_pass < kMaxPasses) {
+        ev = ctx->ev + kEvPerPass * ctx->t_pass;
+        ctx->t_pass++;
     }
-#define GL_STAGE_DONE() \
-    do { if (ev) GL_HIP(hipEventRecord(ev[e++], st), "hipEventRecord"); } while (0)
+#define GL_MARK(i, s)                                                     \
+    do {                                                                  \
+        if (ev) {                                                         \
+            const gl_status r_ = record_event(ctx, ev[i], s, i);          \
+            if (r_ != GL_OK) return r_;                                   \
+        }                                                                 \
+    } while (0)
+    GL_MARK(E_START, st);
     Pipe P = ctx->pipe;
     const bool sur = b.net != nullptr;
     if (sur) {
@@ -2083,10 +2120,10 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     if (!shared)
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, ctx->chunk_off, b.n_sets,
                            b.max_chunks, ctx->ctr);
-    GL_STAGE_DONE();
+    GL_MARK(E_SETUP, st);
     const int64_t n_cu = ctx->n_cu;
     launch_window(ctx, b, st, 1, P);
-    GL_STAGE_DONE();
+    GL_MARK(E_WINDOW, st);
     const unsigned waves = (unsigned)std::max<int64_t>(4, n_cu * ctx->waves_per_cu);
     if (sur)
         hipLaunchKernelGGL((k_classify<false, true>), dim3((unsigned)(n_cu * ctx->waves_classify)), dim3(64), 0, st, b.times,
@@ -2096,29 +2133,37 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
         hipLaunchKernelGGL((k_classify<CENSUS, false>), dim3((unsigned)(n_cu * ctx->waves_classify)), dim3(64), 0, st,
                            b.times, shared, ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks,
                            ctx->chunk_set, ctx->chunk_fb);
-    GL_STAGE_DONE();
+    GL_MARK(E_CLASSIFY, st);
     const unsigned twaves = GL_TRAP_WAVES_PER_CU > 0 ? (unsigned)(n_cu * GL_TRAP_WAVES_PER_CU) : waves;
     // whole ellipses (trapezoid) need nothing from the hard-sample chain and
-    // write other sub-samples: on the side stream they run beside it (joined
-    // before the averages); the stage timing keeps every stage in order
-    const bool fork = ctx->side != nullptr && ev == nullptr;
+    // write other sub-samples, so the two run side by side: the trapezoid on
+    // the caller's stream, dispatched as soon as the classification ends, the
+    // hard chain (hard samples, arc levels, rare paths, combine) on the second
+    // stream after its wait on the classification, joined before the
+    // averages.  A graph of the batch dispatches its two branches in the same
+    // order, so timed direct launches overlap as graph replays do.
+    const bool fork = ctx->side != nullptr;
+    hipStream_t hs = fork ? ctx->side : st;
     if (fork) {
-        GL_HIP(hipEventRecord(ctx->ev_fork, st), "hipEventRecord");
-        GL_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0), "hipStreamWaitEvent");
+        GL_HIP(hipEventRecord(ctx->ev_fork, st), "hipEventRecord (fork)");
+        GL_HIP(hipStreamWaitEvent(hs, ctx->ev_fork, 0), "hipStreamWaitEvent (fork)");
     }
-    hipLaunchKernelGGL(k_trap<CENSUS>, dim3((twaves + kTrapWaves - 1) / kTrapWaves), dim3(kTrapThreads), 0,
-                       fork ? ctx->side : st, ctx->sc, ctx->ctr, P);
-    if (fork) GL_HIP(hipEventRecord(ctx->ev_join, ctx->side), "hipEventRecord");
-    GL_STAGE_DONE();
-    hipLaunchKernelGGL(k_hard<CENSUS>, dim3(waves), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
-    GL_STAGE_DONE();
+    hipLaunchKernelGGL(k_trap<CENSUS>, dim3((twaves + kTrapWaves - 1) / kTrapWaves), dim3(kTrapThreads), 0, st,
+                       ctx->sc, ctx->ctr, P);
+    GL_MARK(E_TRAP, st);
+    GL_MARK(E_SIDE, hs);
+    hipLaunchKernelGGL(k_hard<CENSUS>, dim3(waves), dim3(64), 0, hs, ctx->sc, ctx->ctr, P);
+    GL_MARK(E_HARD, hs);
     const unsigned arc_grid = ctx->waves_gk > 0 ? (unsigned)(n_cu * ctx->waves_gk) : waves;
-    launch_arcs<CENSUS>(ctx, st, arc_grid, P);
-    GL_STAGE_DONE();
-    launch_rare<CENSUS>(ctx, st, arc_grid, P);
-    GL_STAGE_DONE();
-    hipLaunchKernelGGL(k_combine, dim3((unsigned)(n_cu * 8)), dim3(256), 0, st, ctx->sc, ctx->ctr, P);
-    if (fork) GL_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0), "hipStreamWaitEvent");
+    launch_arcs<CENSUS>(ctx, hs, arc_grid, P);
+    GL_MARK(E_ARCS, hs);
+    launch_rare<CENSUS>(ctx, hs, arc_grid, P);
+    GL_MARK(E_RARE, hs);
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)(n_cu * 8)), dim3(256), 0, hs, ctx->sc, ctx->ctr, P);
+    if (fork) {
+        GL_HIP(hipEventRecord(ctx->ev_join, hs), "hipEventRecord (join)");
+        GL_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0), "hipStreamWaitEvent (join)");
+    }
     if (sur) {
         // the network's residuals on the accepted sub-samples' sphere fluxes
         hipLaunchKernelGGL(k_net_gather, dim3((unsigned)(n_cu * 8)), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
@@ -2129,7 +2174,7 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     hipLaunchKernelGGL(k_average, dim3((unsigned)(n_cu * 32)), dim3(64), 0, st, ctx->sc,
                        ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks, ctx->chunk_set,
                        ctx->chunk_fb, dem, b.out);
-    GL_STAGE_DONE();
+    GL_MARK(E_AVERAGE, st);
     // the fused kernel takes the chunks the lists could not hold (few: a
     // quarter wave per CU), and every chunk of a tidally-locked set (general
     // ellipsoids: a full grid at its occupancy of two waves per SIMD)
@@ -2138,18 +2183,11 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     hipLaunchKernelGGL(fused, dim3(fused_grid), dim3(64), 0, st, b.times, shared,
                        ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, ctx->masks, ctx->chunk_set,
                        P, b.out);
-    GL_STAGE_DONE();
-#undef GL_STAGE_DONE
+    GL_MARK(E_FUSED, st);
+#undef GL_MARK
     GL_HIP(hipGetLastError(), "kernel launch");
     return GL_OK;
 }
-
-// Passes: a batch whose in-window sub-samples exceed what one pass should
-// hold runs as up to kMaxPasses passes of the whole pipeline over equal
-// ranges of its parameter sets.  Results do not depend on the split (every
-// sub-sample and output is computed by itself), only the list sizes do.
-constexpr int kMaxPasses = 8;
-constexpr int64_t kPassSub = (int64_t)1 << 26;  // in-window sub-samples one pass aims at
 
 // Bytes of the work lists at per-shard capacities c (entries).
 int64_t pipe_bytes(const int64_t* c)
@@ -2206,7 +2244,7 @@ gl_status run_batch(gl_ctx* ctx, const Batch& b, bool census)
 {
     gl_status st = GL_OK;
     const int T = ctx->passes;
-    if (ctx->t_slots > 0 && !census) ctx->t_batches++;
+    ctx->t_pass = 0;
     for (int p = 0; p < T; ++p) {
         const int64_t a = b.n_sets * p / T, e = b.n_sets * (p + 1) / T;
         Batch q = b;
@@ -2240,6 +2278,32 @@ gl_status enqueue(gl_ctx* ctx, const Batch& b, bool census = false)
                                 b.stream);
     }
     GL_HIP(hipGetLastError(), "kernel launch");
+    return GL_OK;
+}
+
+// After a timed batch (t_pass passes recorded): waits for its stream and adds
+// its stage times (kStageEv), the compute time (end of set-up to end of the
+// fused stage) and the pipeline time (start to end of the fused stage).
+gl_status finish_timed(gl_ctx* ctx, hipStream_t s)
+{
+    if (ctx->t_left <= 0 || ctx->t_pass <= 0) return GL_OK;
+    GL_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    for (int p = 0; p < ctx->t_pass; ++p) {
+        hipEvent_t* ev = ctx->ev + kEvPerPass * p;
+        for (int k = 0; k < GL_NSTAGES; ++k) {
+            float ms = 0.0f;
+            GL_HIP(hipEventElapsedTime(&ms, ev[kStageEv[k][0]], ev[kStageEv[k][1]]), "hipEventElapsedTime");
+            ctx->t_stage[k] += ms;
+        }
+        float ms = 0.0f;
+        GL_HIP(hipEventElapsedTime(&ms, ev[E_SETUP], ev[E_FUSED]), "hipEventElapsedTime");
+        ctx->t_comp += ms;
+        GL_HIP(hipEventElapsedTime(&ms, ev[E_START], ev[E_FUSED]), "hipEventElapsedTime");
+        ctx->t_pipe += ms;
+    }
+    ctx->t_batches++;
+    ctx->t_left--;
+    ctx->t_pass = 0;
     return GL_OK;
 }
 
@@ -2303,10 +2367,13 @@ gl_status gl_ctx_create(gl_ctx** out, int device)
 
 void free_timing(gl_ctx* ctx)
 {
-    for (int i = 0; i < (GL_NSTAGES + 1) * ctx->t_slots; ++i) (void)hipEventDestroy(ctx->ev[i]);
+    if (ctx->ev)
+        for (int i = 0; i < kEvPerPass * kMaxPasses; ++i) (void)hipEventDestroy(ctx->ev[i]);
     delete[] ctx->ev;
     ctx->ev = nullptr;
-    ctx->t_slots = ctx->t_used = ctx->t_batches = 0;
+    ctx->t_left = ctx->t_pass = ctx->t_batches = 0;
+    for (int k = 0; k < GL_NSTAGES; ++k) ctx->t_stage[k] = 0.0;
+    ctx->t_comp = ctx->t_pipe = 0.0;
 }
 
 void gl_ctx_destroy(gl_ctx* ctx)
@@ -2348,9 +2415,14 @@ gl_status lightcurve(gl_ctx* ctx, Batch& b)
     GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     st = prepare_batch(ctx, b);
     if (st != GL_OK) return st;
-    // the legacy default stream cannot be captured, and timed launches record
-    // events per launch: launch directly there
-    if (!ctx->use_graph || stream == nullptr || ctx->t_slots > 0) return enqueue(ctx, b);
+    // the legacy default stream cannot be captured: launch directly there,
+    // as timed batches are (their events stay out of graphs)
+    const bool timed = ctx->t_left > 0;
+    if (!ctx->use_graph || stream == nullptr || timed) {
+        st = enqueue(ctx, b);
+        if (st != GL_OK) return st;
+        return timed ? finish_timed(ctx, b.stream) : GL_OK;
+    }
     gl_ctx::Key k{};
     k.params = params;
     k.n_sets = n_sets;
@@ -2577,13 +2649,12 @@ gl_status gl_ctx_set_timing(gl_ctx* ctx, int n_slots)
     GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     GL_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
     free_timing(ctx);
+    drop_graph(ctx);  // the next batch is captured with (or without) its timing events
     if (n_slots == 0) return GL_OK;
-    drop_graph(ctx);
-    // one slot per pass of every timed batch
-    const int slots = n_slots * kMaxPasses;
-    ctx->ev = new (std::nothrow) hipEvent_t[(GL_NSTAGES + 1) * slots];
-    if (!ctx->ev) return fail(ctx, GL_ERR_NOMEM, "timing slots");
-    for (int i = 0; i < (GL_NSTAGES + 1) * slots; ++i) {
+    // one event set per pass (a timed batch is read before the next one)
+    ctx->ev = new (std::nothrow) hipEvent_t[kEvPerPass * kMaxPasses];
+    if (!ctx->ev) return fail(ctx, GL_ERR_NOMEM, "timing events");
+    for (int i = 0; i < kEvPerPass * kMaxPasses; ++i) {
         if (hipEventCreate(&ctx->ev[i]) != hipSuccess) {
             for (int j = 0; j < i; ++j) (void)hipEventDestroy(ctx->ev[j]);
             delete[] ctx->ev;
@@ -2591,43 +2662,31 @@ gl_status gl_ctx_set_timing(gl_ctx* ctx, int n_slots)
             return fail(ctx, GL_ERR_DEVICE, "hipEventCreate");
         }
     }
-    ctx->t_slots = slots;
-    ctx->t_used = ctx->t_batches = 0;
+    ctx->t_left = n_slots;
     return GL_OK;
 }
 
 gl_status gl_ctx_get_stage_timing(gl_ctx* ctx, double* stage_ms, int* n)
 {
     if (!ctx) return GL_ERR_NULL;
-    double acc[GL_NSTAGES] = {};
-    for (int i = 0; i < ctx->t_used; ++i) {
-        hipEvent_t* ev = ctx->ev + (GL_NSTAGES + 1) * i;
-        GL_HIP(hipEventSynchronize(ev[GL_NSTAGES]), "hipEventSynchronize");
-        for (int k = 0; k < GL_NSTAGES; ++k) {
-            float ms = 0.0f;
-            GL_HIP(hipEventElapsedTime(&ms, ev[k], ev[k + 1]), "hipEventElapsedTime");
-            acc[k] += ms;
-        }
-    }
     if (stage_ms)
-        for (int k = 0; k < GL_NSTAGES; ++k) stage_ms[k] = acc[k];
+        for (int k = 0; k < GL_NSTAGES; ++k) stage_ms[k] = ctx->t_stage[k];
     if (n) *n = ctx->t_batches;
-    ctx->t_used = ctx->t_batches = 0;
+    for (int k = 0; k < GL_NSTAGES; ++k) ctx->t_stage[k] = 0.0;
+    ctx->t_comp = ctx->t_pipe = 0.0;
+    ctx->t_batches = 0;
     return GL_OK;
 }
 
 gl_status gl_ctx_get_timing(gl_ctx* ctx, double* compute_ms, double* pipeline_ms, int* n)
 {
-    double st[GL_NSTAGES];
-    const gl_status r = gl_ctx_get_stage_timing(ctx, st, n);
-    if (r != GL_OK) return r;
-    double c = 0.0, p = 0.0;
-    for (int k = 0; k < GL_NSTAGES; ++k) {
-        p += st[k];
-        if (k > 0) c += st[k];
-    }
-    if (compute_ms) *compute_ms = c;
-    if (pipeline_ms) *pipeline_ms = p;
+    if (!ctx) return GL_ERR_NULL;
+    if (compute_ms) *compute_ms = ctx->t_comp;
+    if (pipeline_ms) *pipeline_ms = ctx->t_pipe;
+    if (n) *n = ctx->t_batches;
+    for (int k = 0; k < GL_NSTAGES; ++k) ctx->t_stage[k] = 0.0;
+    ctx->t_comp = ctx->t_pipe = 0.0;
+    ctx->t_batches = 0;
     return GL_OK;
 }
 
@@ -3390,6 +3449,8 @@ gl_status gl_lightcurve_batch_surrogate(gl_ctx* ctx, const gl_surrogate* s, doub
     st = prepare_batch(ctx, b);
     if (st != GL_OK) return st;
     st = run_batch(ctx, b, false);
+    if (st != GL_OK) return st;
+    st = finish_timed(ctx, b.stream);
     if (st != GL_OK) return st;
     if (n_sub_out || n_fallback_out) {
         unsigned long long c[3] = {0ull, 0ull, 0ull};  // in window, reaching the disk, accepted

@@ -433,6 +433,7 @@ def test_stage_timing(gpu_lib, ctx):
     say("case: per-stage timing events")
     w = W.walker_batch(n_sets=128)
     d = gl.to_device(w, "cuda:0")
+    ctx.batch(d["params"], d["times"], n_ss=d["n_ss"], t_exp=d["t_exp"])  # sizes the lists
     gl.gl_ctx_set_timing(ctx.handle, 3)
     for _ in range(3):
         ctx.batch(d["params"], d["times"], n_ss=d["n_ss"], t_exp=d["t_exp"])
@@ -442,3 +443,50 @@ def test_stage_timing(gpu_lib, ctx):
     say(f"  {n} batches: {st}")
     assert n == 3 and len(st) == gl.GL_NSTAGES
     assert all(v >= 0.0 for v in st.values()) and st["trapezoid"] > 0.0
+    # timed launches (trapezoid stage forked as in the graph) give the same
+    # outputs as untimed ones, and the first-to-last times hold every stage
+    ref = ctx.batch(d["params"], d["times"], n_ss=d["n_ss"], t_exp=d["t_exp"]).cpu().numpy()
+    gl.gl_ctx_set_timing(ctx.handle, 2)
+    outs = [ctx.batch(d["params"], d["times"], n_ss=d["n_ss"], t_exp=d["t_exp"]).cpu().numpy() for _ in range(2)]
+    comp, pipe, n2 = gl.gl_ctx_get_timing(ctx.handle)
+    gl.gl_ctx_set_timing(ctx.handle, 0)
+    say(f"  compute {comp / n2:.4f} ms, pipeline {pipe / n2:.4f} ms per batch")
+    assert n2 == 2 and 0.0 < comp <= pipe
+    for o in outs:
+        assert np.array_equal(o, ref)
+
+
+def test_stage_timing_graph(gpu_lib, ctx):
+    """Timing on a stream that takes the graph path: timed batches run
+    directly with the graph's stream overlap, outputs are unchanged, every
+    batch is timed, and the graph path resumes afterwards."""
+    import torch
+    from paper_2410_05408_amd import workloads as W
+    gl = gpu_lib
+    say("case: per-stage timing events on a non-default stream (graph path)")
+    w = W.walker_batch(n_sets=256)
+    d = gl.to_device(w, "cuda:0")
+    s = torch.cuda.Stream()
+    ref = ctx.batch(d["params"], d["times"], n_ss=d["n_ss"], t_exp=d["t_exp"], stream=s)
+    s.synchronize()
+    ref = ref.cpu().numpy()
+    gl.gl_ctx_set_timing(ctx.handle, 3)
+    outs = []
+    for _ in range(3):
+        o = ctx.batch(d["params"], d["times"], n_ss=d["n_ss"], t_exp=d["t_exp"], stream=s)
+        s.synchronize()
+        outs.append(o.cpu().numpy())
+    st, n = gl.gl_ctx_get_stage_timing(ctx.handle)
+    gl.gl_ctx_set_timing(ctx.handle, 2)
+    for _ in range(2):
+        ctx.batch(d["params"], d["times"], n_ss=d["n_ss"], t_exp=d["t_exp"], stream=s)
+    comp, pipe, n2 = gl.gl_ctx_get_timing(ctx.handle)
+    gl.gl_ctx_set_timing(ctx.handle, 0)
+    after = ctx.batch(d["params"], d["times"], n_ss=d["n_ss"], t_exp=d["t_exp"], stream=s)
+    s.synchronize()
+    say(f"  {n} batches: {st}; compute {comp / n2:.4f} ms, pipeline {pipe / n2:.4f} ms per batch")
+    assert n == 3 and n2 == 2
+    assert all(v >= 0.0 for v in st.values()) and st["trapezoid"] > 0.0 and st["hard"] > 0.0
+    assert 0.0 < comp <= pipe
+    for o in outs + [after.cpu().numpy()]:
+        assert np.array_equal(o, ref)
