@@ -159,6 +159,47 @@ GL_HD double sqrt_qp(double x)
 #endif
 }
 
+// Single-precision estimates (the hardware instructions on the device, the
+// IEEE functions on the host): the FP32 integrator of Section 2 and the
+// first iterates of the quartic solver.
+GL_HD float rsqrt_f(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rsqf(x);
+#else
+    return 1.0f / sqrtf(x);
+#endif
+}
+
+GL_HD float sqrt_f(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return sqrtf(x);
+#endif
+}
+
+GL_HD float rcp_f(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
+// Cube root with the sign of x, as 2^(log2|x| / 3) from the hardware base-2
+// logarithm and exponential (x = 0 gives 0).
+GL_HD float cbrt_f(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return copysignf(__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(fabsf(x)) * (1.0f / 3.0f)), x);
+#else
+    return cbrtf(x);
+#endif
+}
+
 // sin and cos of a in [-pi, pi] (orbital phase): a = k pi/2 + r with
 // |r| <= pi/4 (pi/2 split in two parts, Cody-Waite style), Taylor series of
 // sin r and cos r to r^17 and r^16 (the next terms are below 1e-17), then the
@@ -536,7 +577,8 @@ GL_HD double ddp4(const Poly4& q, double t)
 }
 
 // Root of a function that is monotone on [lo, hi] with values flo, fhi of
-// opposite sign at the ends: Newton from the regula-falsi point, with
+// opposite sign at the ends: Newton from the given first iterate (from the
+// regula-falsi point when that is missing or outside the bracket), with
 // bisection whenever a step leaves the bracket; stops when the step is below
 // its tolerance or the bracket at rounding level, or (a root of q) when |f| is
 // below the rounding noise of its own evaluation.
@@ -569,18 +611,87 @@ GL_HD double bracket_root(const Poly4& q, double lo, double hi, double flo, doub
         else hi = x;
         double xn = x - f * rcp(df);
         if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-        // a Newton step below 1e-8 leaves an error of its square (quadratic
-        // convergence); near a double root, where convergence is linear, an
-        // error of 1e-8 in t moves the region boundary by a sliver of area
-        // O(1e-16) (the limb closes the contour radially there).  A critical
+        // a Newton step below 1e-4 leaves an error near its square, 1e-8 in t
+        // (quadratic convergence).  That is enough for both kinds: a critical
         // point only brackets roots and places a cluster break point (the
-        // integral does not depend on where an arc is split): a step below
-        // 1e-4 (an error near 1e-8) is enough there
-        constexpr double step_tol = Deriv == 0 ? 1e-8 : 1e-4;
+        // integral does not depend on where an arc is split), and a crossing
+        // that is off by d only swaps a sliver between ellipse and limb whose
+        // area is of order d^2 times the crossing angle: the limb arc starts at
+        // the polar angle of the ellipse point at the computed root, so the
+        // contour closes along a ray, where the integrands of the polar form
+        // vanish.  Started from the closed-form guesses of the solver, the
+        // first step is usually below 1e-6 and ends the iteration
+        constexpr double step_tol = 1e-4;
         if (fabs(xn - x) <= step_tol * fmax(1.0, ax) || hi - lo <= 2e-16 * fmax(1.0, ax)) return xn;
         x = xn;
     }
     return x;
+}
+
+// First iterates from closed forms: coefficients in FP64, cube and square
+// roots in FP32.  A guess is used only when it lies inside its bracket, so an
+// inaccurate or missing one costs Newton steps, never accuracy; NaN marks a
+// missing guess (every comparison with it fails).
+
+// The real root of the cubic q'(t) = 4 a4 t^3 + 3 a3 t^2 + 2 a2 t + a1 when it
+// has only one: Cardano's formula for the cubic depressed about its
+// inflection point, y^3 + P y + R = 0, y = u + v with u^3 the larger of
+// -R/2 +- sqrt(R^2/4 + P^3/27) in magnitude and v = -P / (3u) (no
+// cancellation); NaN when the cubic has three real roots.
+GL_HD double cubic_one_root(const Poly4& q)
+{
+    const double ia = rcp(4.0 * q.a4);
+    const double b = 3.0 * q.a3 * ia, c = 2.0 * q.a2 * ia, d = q.a1 * ia;
+    const double P = fma(b * b, -1.0 / 3.0, c);
+    const double R = fma(b * fma(2.0 * b, b, -9.0 * c), 1.0 / 27.0, d);
+    const double disc = fma(0.25 * R, R, P * P * P * (1.0 / 27.0));
+    const float hr = (float)(-0.5 * R), sd = sqrt_f((float)fmax(disc, 0.0));
+    const float u = cbrt_f(hr >= 0.0f ? hr + sd : hr - sd);
+    const double v = u != 0.0f ? -P * (double)rcp_f(3.0f * u) : 0.0;
+    const double y = (double)u + v - b * (1.0 / 3.0);
+    return disc >= 0.0 ? y : __builtin_nan("");
+}
+
+// Real roots of the quartic q when it has exactly two (Ferrari's method):
+// with t = y - b/4 the monic quartic becomes y^4 + p y^2 + r1 y + r0; a root
+// m >= 0 of the resolvent m^3 + p m^2 + (p^2/4 - r0) m - r1^2/8 (Cardano,
+// then one FP64 Newton step: a small m loses its relative accuracy to
+// cancellation in the formula) splits it into y^2 - s y + (p/2 + m + w) and
+// y^2 + s y + (p/2 + m - w), s = sqrt(2m), w = r1 / (2s), taken as
+// sign(r1) sqrt(m^2 + p m + p^2/4 - r0), which holds at the resolvent root and
+// stays finite as m -> 0 (the biquadratic limit).  Two real roots of the
+// quartic go with a resolvent of one real root (equal discriminants, up to a
+// positive factor); with three (no real root of the quartic, or four) every
+// guess is NaN.  out[0..3] in no particular order, NaN for a quadratic
+// without real roots.
+GL_HD void quartic_guesses(const Poly4& q, float* out)
+{
+    const double ia = rcp(q.a4);
+    const double b = q.a3 * ia, c = q.a2 * ia, d = q.a1 * ia, e = q.a0 * ia;
+    const double b2 = b * b;
+    const double p = fma(-0.375, b2, c);
+    const double r1 = fma(0.125 * b2, b, fma(-0.5 * b, c, d));
+    const double r0 = fma(-3.0 / 256.0 * b2, b2, fma(0.0625 * b2, c, fma(-0.25 * b, d, e)));
+    const double C = fma(0.25 * p, p, -r0), D = -0.125 * r1 * r1;
+    const double P3 = fma(p * p, -1.0 / 3.0, C);
+    const double R3 = fma(p * fma(2.0 * p, p, -9.0 * C), 1.0 / 27.0, D);
+    const double disc = fma(0.25 * R3, R3, P3 * P3 * P3 * (1.0 / 27.0));
+    const float hr = (float)(-0.5 * R3), sd = sqrt_f((float)fmax(disc, 0.0));
+    const float u = cbrt_f(hr >= 0.0f ? hr + sd : hr - sd);
+    double m = (double)u + (u != 0.0f ? -P3 * (double)rcp_f(3.0f * u) : 0.0) - p * (1.0 / 3.0);
+    const double fm = fma(fma(m + p, m, C), m, D), dfm = fma(fma(3.0, m, 2.0 * p), m, C);
+    m = fmax(m - fm * rcp(dfm != 0.0 ? dfm : 1.0), 0.0);
+    const float s = sqrt_f((float)(2.0 * m));
+    const float w = copysignf(sqrt_f((float)fmax(fma(m + p, m, C), 0.0)), (float)r1);
+    const float h = (float)(fma(0.5, p, m)), sh = (float)(-0.25 * b);
+    const float d1 = s * s - 4.0f * (h + w), d2 = s * s - 4.0f * (h - w);
+    const float w1 = sqrt_f(d1), w2 = sqrt_f(d2);  // NaN for a negative argument
+    const bool ok = disc >= 0.0;
+    const float nan = __builtin_nanf("");
+    out[0] = ok && d1 >= 0.0f ? sh + 0.5f * (s + w1) : nan;
+    out[1] = ok && d1 >= 0.0f ? sh + 0.5f * (s - w1) : nan;
+    out[2] = ok && d2 >= 0.0f ? sh + 0.5f * (w2 - s) : nan;
+    out[3] = ok && d2 >= 0.0f ? sh - 0.5f * (s + w2) : nan;
 }
 
 // Real roots and critical points of the quartic in fixed slots, ascending
@@ -630,6 +741,8 @@ GL_HD void solve_quartic_inl(const Poly4& q, QuarticRoots& out, CT& ct)
         out.c[i] = e[i];
         ctodo |= (out.cv[i] ? 1u : 0u) << i;
     }
+    // first iterate: the cubic's one real root (NaN when it has three)
+    const double cstart = cubic_one_root(q);
     while (ctodo) {
         const int i = __builtin_ctz(ctodo);
         ctodo &= ctodo - 1u;
@@ -637,7 +750,7 @@ GL_HD void solve_quartic_inl(const Poly4& q, QuarticRoots& out, CT& ct)
         const double hi = i == 0 ? e[1] : i == 1 ? e[2] : e[3];
         const double flo = i == 0 ? fe[0] : i == 1 ? fe[1] : fe[2];
         const double fhi = i == 0 ? fe[1] : i == 1 ? fe[2] : fe[3];
-        const double x = bracket_root<1>(q, lo, hi, flo, fhi, ct);
+        const double x = bracket_root<1>(q, lo, hi, flo, fhi, ct, cstart);
 #pragma unroll
         for (int k = 0; k < 3; ++k)
             if (k == i) out.c[k] = x;
@@ -646,19 +759,13 @@ GL_HD void solve_quartic_inl(const Poly4& q, QuarticRoots& out, CT& ct)
     // keeps the left end of its interval, which only splits a stretch where
     // q is monotone
     const double pt[5] = {-Bnd, out.c[0], out.c[1], out.c[2], Bnd};
-    double fq[5], dq[5];
-    // next to a critical point c, q(c + d) ~ q(c) + q''(c) d^2 / 2: a root there
-    // sits near |d| = sqrt(-2 q(c) / q''(c)), a better first iterate than the
-    // secant across the whole bracket (dq = 1e300 where the model does not apply)
+    double fq[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        fq[i] = p4(q, pt[i]);
-        dq[i] = 1e300;
-        if (i >= 1 && i <= 3 && out.cv[i - 1]) {
-            const double m = -2.0 * fq[i] * rcp(ddp4(q, pt[i]));
-            if (m > 0.0 && m < 1e300) dq[i] = sqrt_nn(m);
-        }
-    }
+    for (int i = 0; i < 5; ++i) fq[i] = p4(q, pt[i]);
+    // first iterates: Ferrari's roots, each taken by the bracket it falls in
+    // (the secant across the bracket where none does)
+    float guess[4];
+    quartic_guesses(q, guess);
     // the brackets with a sign change are solved in a loop over the lane's own
     // brackets (one Newton loop per root of the lane, not per bracket slot:
     // the lanes of a wavefront mostly have their two roots in different slots)
@@ -679,9 +786,12 @@ GL_HD void solve_quartic_inl(const Poly4& q, QuarticRoots& out, CT& ct)
         const double hi = i == 0 ? pt[1] : i == 1 ? pt[2] : i == 2 ? pt[3] : pt[4];
         const double flo = i == 0 ? fq[0] : i == 1 ? fq[1] : i == 2 ? fq[2] : fq[3];
         const double fhi = i == 0 ? fq[1] : i == 1 ? fq[2] : i == 2 ? fq[3] : fq[4];
-        const double dlo = i == 0 ? dq[0] : i == 1 ? dq[1] : i == 2 ? dq[2] : dq[3];
-        const double dhi = i == 0 ? dq[1] : i == 1 ? dq[2] : i == 2 ? dq[3] : dq[4];
-        const double start = dlo <= dhi ? lo + dlo : hi - dhi;  // from the nearer model
+        double start = __builtin_nan("");
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double g = (double)guess[k];
+            start = (g > lo && g < hi) ? g : start;
+        }
         const double x = bracket_root<0>(q, lo, hi, flo, fhi, ct, start);
 #pragma unroll
         for (int k = 0; k < 4; ++k)
@@ -1450,32 +1560,6 @@ GL_HD double flux_instant(const SetConst& s, double t)
 // at the (possibly moved) point, and each sum is taken by Simpson's rule; in
 // single precision.  Kept here beside the exact path for comparison.
 
-GL_HD float rsqrt_f(float x)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_rsqf(x);
-#else
-    return 1.0f / sqrtf(x);
-#endif
-}
-
-GL_HD float sqrt_f(float x)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_sqrtf(x);
-#else
-    return sqrtf(x);
-#endif
-}
-
-GL_HD float rcp_f(float x)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_rcpf(x);
-#else
-    return 1.0f / x;
-#endif
-}
 
 // Occulted fraction for ellipse centre (x0, y0) by the snapped boundary and
 // a periodic Simpson rule over n (even) nodes: weights 2, 4, 2, ..., 4 times
@@ -1548,7 +1632,8 @@ GL_HD float flux_snap(const SetConst& s, double t, int n)
 // launch really did.
 constexpr int kFlopSample = 40;     // in-window sub-sample: phase, orbit, classify
 constexpr int kFlopWhole = 30;      // whole-ellipse closed forms and singularity bound
-constexpr int kFlopPartial = 160;   // quartic set-up, frame, break points
+constexpr int kFlopGuess = 97;      // closed-form first iterates (cubic 28, quartic 69)
+constexpr int kFlopPartial = 160 + kFlopGuess;  // quartic set-up, frame, break points
 constexpr int kFlopIter = 18;       // one safeguarded-Newton step on the quartic or cubic
 constexpr int kFlopLimb = 30;       // one limb arc in closed form
 constexpr int kFlopArc = 20;        // one ellipse arc set up for the tau rule
