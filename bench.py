@@ -164,9 +164,9 @@ def rooflines(stage_ms, census, per, n_out, n_in_window_out, n_times, step_ms, c
     dominant kernel is the FP64 kernel with the longest launch: a stage's time
     divided by the launches that carry its work (one per pass, the arc stage
     two level launches per pass).  Stage times come from timed direct launches
-    with the graph's overlap (the trapezoid stage runs beside the hard-sample
-    stage on a second stream, so stage times overlap); the whole pipeline is
-    rated on the measured step time."""
+    with the graph's overlap (the trapezoid stage runs on a second stream
+    beside the hard-sample chain, so stage times overlap); the whole pipeline
+    is rated on the measured step time."""
     flops = sum(census[k] * per[k] for k in census)
     stage_flops = stage_flop_split(census, per)
     dom = max(FLOP_STAGES, key=lambda k: stage_ms[k] / (STAGE_LAUNCHES.get(k, 1) * passes))
@@ -321,7 +321,7 @@ def exact_leg(gl, w, steps, warmup, trials=10, autotune=False, check_oracle=True
         "roofline": roof, "roofline_stages": roof_stages, "stage_ms": stage_ms,
         "pipeline_ms_timed_direct": pipe_ms,
         "plan": {"waves_per_cu": gl.gl_ctx_get_plan(ctx.handle),
-                 "stage_plan_classify_traphard_arcs": list(gl.gl_ctx_get_stage_plan(ctx.handle)), "passes": passes,
+                 "stage_plan_classify_hard_trap_arcs": list(gl.gl_ctx_get_stage_plan(ctx.handle)), "passes": passes,
                  "fused_chunks": fused, "autotuned": autotune},
         "census": census, "unconverged_arcs": unconv,
     }

@@ -239,12 +239,13 @@ const char *gl_ctx_last_error(const gl_ctx *ctx);
 
 /* Launch-plan autotuner: times the candidate persistent-grid sizes of the
  * work-list kernels on a representative batch (same arguments as
- * gl_lightcurve_batch; `out` is overwritten), one stage group at a time
- * (trapezoid and hard-sample kernels {8, 16, 24, 32, 48, 64} waves per CU,
- * then classification {8, 16, 24, 32, 48}, then the arc-rule levels
- * {8, 12, 16, 20, 32, 48}; more waves than fit at once queue behind the
- * resident ones, which balances uneven per-wave work;
- * coordinate descent, each candidate timed over three batches after a warm-up)
+ * gl_lightcurve_batch; `out` is overwritten), one kernel group at a time
+ * (hard-sample kernel {8, 16, 24, 32, 48, 64} waves per CU, trapezoid kernel
+ * {4, 8, 16, 24, 32, 48, 64}, classification {8, 16, 24, 32, 48}, arc-rule
+ * levels {8, 12, 16, 20, 32, 48}; more waves than fit at once queue behind
+ * the resident ones, which balances uneven per-wave work; coordinate descent
+ * in two sweeps, each candidate timed as the median of five batches after a
+ * warm-up, run the way the batch call runs: as a graph where `stream` allows)
  * and keeps the fastest in the context's plan.  Synchronises `stream`.
  * Quadrature orders are not a plan setting: every sample picks its own
  * (self-checking rules). */
@@ -253,21 +254,21 @@ gl_status gl_autotune(gl_ctx *ctx, const double *params, int64_t n_sets,
                       const int32_t *n_ss, const double *t_exp, double *out,
                       void *stream);
 
-/* Current plan: persistent wavefronts per compute unit of the trapezoid and
- * hard-sample kernels. */
+/* Current plan: persistent wavefronts per compute unit of the hard-sample
+ * kernel. */
 gl_status gl_ctx_get_plan(const gl_ctx *ctx, int *waves_per_cu);
 
 /* Sets that part of the plan; waves_per_cu in [1, 64] (default 16). */
 gl_status gl_ctx_set_plan(gl_ctx *ctx, int waves_per_cu);
 
 /* The whole plan: persistent wavefronts per compute unit of the
- * classification (default 24), the trapezoid and hard-sample kernels
- * (default 16, the value of gl_ctx_get_plan) and the arc-rule levels
- * (default 20).  Any pointer may be NULL. */
-gl_status gl_ctx_get_stage_plan(const gl_ctx *ctx, int *classify, int *trap_hard, int *gk);
+ * classification (default 24), the hard-sample kernel (default 16, the value
+ * of gl_ctx_get_plan), the trapezoid kernel (default 16) and the arc-rule
+ * levels (default 20).  Any pointer may be NULL. */
+gl_status gl_ctx_get_stage_plan(const gl_ctx *ctx, int *classify, int *hard, int *trap, int *gk);
 
 /* Sets the whole plan; each value in [1, 64], else GL_ERR_SIZE. */
-gl_status gl_ctx_set_stage_plan(gl_ctx *ctx, int classify, int trap_hard, int gk);
+gl_status gl_ctx_set_stage_plan(gl_ctx *ctx, int classify, int hard, int trap, int gk);
 
 /* Work-list capacities of the exact path, in entries: sub-sample flux slots
  * (and trapezoid entries) <= 2^27 - 1, hard samples and ellipse arcs
@@ -311,11 +312,11 @@ gl_status gl_ctx_set_graph(gl_ctx *ctx, int on);
  *  trapezoid for whole ellipses near the limb, samples integrated in place,
  *  arcs from level 2 on), 7 combination of each hard sample's sums and
  *  supersample averages, 8 fused kernel for chunks beyond the work-list
- *  capacities.  Stage 3 (on the caller's stream) runs beside stages 4 to 6
- *  and the combination (on a second stream of the context, joined before the
- *  averages): both need only the classification.  Stage 4 is timed from the
- *  second stream's start, so stage times overlap and need not add up to the
- *  batch time. */
+ *  capacities.  Stage 3 (on a second stream of the context, joined before
+ *  the averages) runs beside stages 4 to 6 and the combination (on the
+ *  caller's stream): both need only the classification.  Stage 3 is timed
+ *  from the second stream's start, so stage times overlap and need not add
+ *  up to the batch time. */
 #define GL_NSTAGES 9
 
 /* Instrumentation: with n_slots > 0, the next n_slots batches are launched

@@ -366,9 +366,9 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
 #define GL_WAVES_GK 0
 #endif
 #define GL_WAVES(n) __attribute__((amdgpu_waves_per_eu((n) > 0 ? (n) : 1)))
-// Persistent grid of the trapezoid stage in wavefronts per CU (0: the plan's).
+// Default persistent grid of the trapezoid stage in wavefronts per CU.
 #ifndef GL_TRAP_WAVES_PER_CU
-#define GL_TRAP_WAVES_PER_CU 0
+#define GL_TRAP_WAVES_PER_CU 16
 #endif
 // Persistent grid of the classification in wavefronts per CU.
 #ifndef GL_CLASSIFY_WAVES_PER_CU
@@ -1710,15 +1710,15 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
 
 // ---------------------------------------------------------------- context
 // Timing events of one pass: the caller's stream marks the start and the
-// ends of set-up, window, classification, trapezoid, averages and fused
-// stage; the second stream marks its start (its wait on the classification
-// met) and the ends of the hard samples, arc levels and rare paths.  Each
+// ends of set-up, window, classification, hard samples, arc levels, rare
+// paths, averages and fused stage; the second stream marks its start (its
+// wait on the classification met) and the end of the trapezoid stage.  Each
 // stage is timed between two of them (kStageEv), on the stream it runs on.
 enum {
-    E_START, E_SETUP, E_WINDOW, E_CLASSIFY, E_TRAP, E_SIDE, E_HARD, E_ARCS, E_RARE, E_AVERAGE, E_FUSED, kEvPerPass
+    E_START, E_SETUP, E_WINDOW, E_CLASSIFY, E_SIDE, E_TRAP, E_HARD, E_ARCS, E_RARE, E_AVERAGE, E_FUSED, kEvPerPass
 };
 constexpr int kStageEv[GL_NSTAGES][2] = {
-    {E_START, E_SETUP}, {E_SETUP, E_WINDOW}, {E_WINDOW, E_CLASSIFY}, {E_CLASSIFY, E_TRAP}, {E_SIDE, E_HARD},
+    {E_START, E_SETUP}, {E_SETUP, E_WINDOW}, {E_WINDOW, E_CLASSIFY}, {E_SIDE, E_TRAP}, {E_CLASSIFY, E_HARD},
     {E_HARD, E_ARCS},   {E_ARCS, E_RARE},    {E_RARE, E_AVERAGE},    {E_AVERAGE, E_FUSED}};
 
 // Passes: a batch whose in-window sub-samples exceed what one pass should
@@ -1731,7 +1731,8 @@ constexpr int64_t kPassSub = (int64_t)1 << 26;  // in-window sub-samples one pas
 struct gl_ctx {
     int device = 0;
     int n_cu = 256;
-    int waves_per_cu = 16;  // persistent waves per CU of the trapezoid and hard-sample kernels
+    int waves_per_cu = 16;  // persistent waves per CU of the hard-sample kernel
+    int waves_trap = GL_TRAP_WAVES_PER_CU;          // of the trapezoid kernel
     int waves_classify = GL_CLASSIFY_WAVES_PER_CU;  // of the classification
     int waves_gk = GL_GK_WAVES_PER_CU;              // of the arc-rule levels
     bool use_graph = true;
@@ -1760,7 +1761,7 @@ struct gl_ctx {
         const double* t_exp;
         double* out;
         void* stream;
-        int waves, waves_classify, waves_gk;
+        int waves, waves_trap, waves_classify, waves_gk;
         void* ws;
         int passes;
         int shape;
@@ -2134,34 +2135,37 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
                            b.times, shared, ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks,
                            ctx->chunk_set, ctx->chunk_fb);
     GL_MARK(E_CLASSIFY, st);
-    const unsigned twaves = GL_TRAP_WAVES_PER_CU > 0 ? (unsigned)(n_cu * GL_TRAP_WAVES_PER_CU) : waves;
+    const unsigned twaves = (unsigned)std::max<int64_t>(4, n_cu * ctx->waves_trap);
     // whole ellipses (trapezoid) need nothing from the hard-sample chain and
-    // write other sub-samples, so the two run side by side: the trapezoid on
-    // the caller's stream, dispatched as soon as the classification ends, the
-    // hard chain (hard samples, arc levels, rare paths, combine) on the second
-    // stream after its wait on the classification, joined before the
-    // averages.  A graph of the batch dispatches its two branches in the same
-    // order, so timed direct launches overlap as graph replays do.
+    // write other sub-samples, so the two run side by side.  The hard chain
+    // (hard samples, arc levels, rare paths, combine), the longer branch,
+    // stays on the caller's stream and is enqueued first: a graph of the
+    // batch keeps its first branch on the launching queue, so the chain
+    // starts right after the classification and the averages follow it on
+    // the same queue.  The trapezoid goes to the second stream after its
+    // wait on the classification; its end is long past when the averages
+    // wait for it.  Cross-queue waits cost ~10 us each on the critical path
+    // in the opposite arrangement.
     const bool fork = ctx->side != nullptr;
-    hipStream_t hs = fork ? ctx->side : st;
+    hipStream_t ts = fork ? ctx->side : st;
     if (fork) {
         GL_HIP(hipEventRecord(ctx->ev_fork, st), "hipEventRecord (fork)");
-        GL_HIP(hipStreamWaitEvent(hs, ctx->ev_fork, 0), "hipStreamWaitEvent (fork)");
+        GL_HIP(hipStreamWaitEvent(ts, ctx->ev_fork, 0), "hipStreamWaitEvent (fork)");
     }
-    hipLaunchKernelGGL(k_trap<CENSUS>, dim3((twaves + kTrapWaves - 1) / kTrapWaves), dim3(kTrapThreads), 0, st,
-                       ctx->sc, ctx->ctr, P);
-    GL_MARK(E_TRAP, st);
-    GL_MARK(E_SIDE, hs);
-    hipLaunchKernelGGL(k_hard<CENSUS>, dim3(waves), dim3(64), 0, hs, ctx->sc, ctx->ctr, P);
-    GL_MARK(E_HARD, hs);
+    hipLaunchKernelGGL(k_hard<CENSUS>, dim3(waves), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
+    GL_MARK(E_HARD, st);
     const unsigned arc_grid = ctx->waves_gk > 0 ? (unsigned)(n_cu * ctx->waves_gk) : waves;
-    launch_arcs<CENSUS>(ctx, hs, arc_grid, P);
-    GL_MARK(E_ARCS, hs);
-    launch_rare<CENSUS>(ctx, hs, arc_grid, P);
-    GL_MARK(E_RARE, hs);
-    hipLaunchKernelGGL(k_combine, dim3((unsigned)(n_cu * 8)), dim3(256), 0, hs, ctx->sc, ctx->ctr, P);
+    launch_arcs<CENSUS>(ctx, st, arc_grid, P);
+    GL_MARK(E_ARCS, st);
+    launch_rare<CENSUS>(ctx, st, arc_grid, P);
+    GL_MARK(E_RARE, st);
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)(n_cu * 8)), dim3(256), 0, st, ctx->sc, ctx->ctr, P);
+    GL_MARK(E_SIDE, ts);
+    hipLaunchKernelGGL(k_trap<CENSUS>, dim3((twaves + kTrapWaves - 1) / kTrapWaves), dim3(kTrapThreads), 0, ts,
+                       ctx->sc, ctx->ctr, P);
+    GL_MARK(E_TRAP, ts);
     if (fork) {
-        GL_HIP(hipEventRecord(ctx->ev_join, hs), "hipEventRecord (join)");
+        GL_HIP(hipEventRecord(ctx->ev_join, ts), "hipEventRecord (join)");
         GL_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0), "hipStreamWaitEvent (join)");
     }
     if (sur) {
@@ -2434,6 +2438,7 @@ gl_status lightcurve(gl_ctx* ctx, Batch& b)
     k.out = out;
     k.stream = stream;
     k.waves = ctx->waves_per_cu;
+    k.waves_trap = ctx->waves_trap;
     k.waves_classify = ctx->waves_classify;
     k.waves_gk = ctx->waves_gk;
     k.ws = ctx->masks;
@@ -2539,22 +2544,24 @@ gl_status gl_ctx_get_plan(const gl_ctx* ctx, int* waves_per_cu)
     return GL_OK;
 }
 
-gl_status gl_ctx_get_stage_plan(const gl_ctx* ctx, int* classify, int* trap_hard, int* gk)
+gl_status gl_ctx_get_stage_plan(const gl_ctx* ctx, int* classify, int* hard, int* trap, int* gk)
 {
     if (!ctx) return GL_ERR_NULL;
     if (classify) *classify = ctx->waves_classify;
-    if (trap_hard) *trap_hard = ctx->waves_per_cu;
+    if (hard) *hard = ctx->waves_per_cu;
+    if (trap) *trap = ctx->waves_trap;
     if (gk) *gk = ctx->waves_gk;
     return GL_OK;
 }
 
-gl_status gl_ctx_set_stage_plan(gl_ctx* ctx, int classify, int trap_hard, int gk)
+gl_status gl_ctx_set_stage_plan(gl_ctx* ctx, int classify, int hard, int trap, int gk)
 {
     if (!ctx) return GL_ERR_NULL;
-    if (classify < 1 || classify > 64 || trap_hard < 1 || trap_hard > 64 || gk < 1 || gk > 64)
+    if (classify < 1 || classify > 64 || hard < 1 || hard > 64 || trap < 1 || trap > 64 || gk < 1 || gk > 64)
         return fail(ctx, GL_ERR_SIZE, "waves per CU in [1, 64]");
     ctx->waves_classify = classify;
-    ctx->waves_per_cu = trap_hard;
+    ctx->waves_per_cu = hard;
+    ctx->waves_trap = trap;
     ctx->waves_gk = gk;
     drop_graph(ctx);
     return GL_OK;
@@ -2590,51 +2597,57 @@ gl_status gl_autotune(gl_ctx* ctx, const double* params, int64_t n_sets, const d
     hipEvent_t e0, e1;
     GL_HIP(hipEventCreate(&e0), "hipEventCreate");
     GL_HIP(hipEventCreate(&e1), "hipEventCreate");
-    // coordinate descent over the three grid sizes: trapezoid and hard-sample
-    // kernels, classification, arc levels (each candidate: one warm-up batch,
-    // then three timed).  Candidates run the way the batch call will run them:
-    // captured and replayed as a graph where the caller's stream allows one
-    // (branches of a graph and of direct launches overlap differently).
+    // coordinate descent over the four grid sizes: hard-sample kernel,
+    // trapezoid kernel (beside the hard chain, where a smaller grid can leave
+    // the chain more of the chip), classification, arc levels; two sweeps.
+    // Each candidate: one warm-up batch, then the median of five timed ones.
+    // Candidates run the way the batch call will run them: captured and
+    // replayed as a graph where the caller's stream allows one (branches of a
+    // graph and of direct launches overlap differently).
     auto time_plan = [&](float& ms_out) -> gl_status {
         Batch c = b;
         gl_status r = lightcurve(ctx, c);  // warm-up (and the capture)
         if (r != GL_OK) return r;
-        float tot = 0.0f;
-        for (int rep = 0; rep < 3; ++rep) {
+        float t[5];
+        for (int rep = 0; rep < 5; ++rep) {
             (void)hipEventRecord(e0, b.stream);
             c = b;
             r = lightcurve(ctx, c);
             (void)hipEventRecord(e1, b.stream);
             (void)hipEventSynchronize(e1);
-            float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            tot += ms;
+            t[rep] = 0.0f;
+            (void)hipEventElapsedTime(&t[rep], e0, e1);
+            if (r != GL_OK) return r;
         }
-        ms_out = tot;
+        std::sort(t, t + 5);
+        ms_out = t[2];
         return r;
     };
     struct Knob {
         int* v;
         std::vector<int> cands;
     };
-    Knob knobs[3] = {{&ctx->waves_per_cu, {8, 16, 24, 32, 48, 64}},
+    Knob knobs[4] = {{&ctx->waves_per_cu, {8, 16, 24, 32, 48, 64}},
+                     {&ctx->waves_trap, {4, 8, 16, 24, 32, 48, 64}},
                      {&ctx->waves_classify, {8, 16, 24, 32, 48}},
                      {&ctx->waves_gk, {8, 12, 16, 20, 32, 48}}};
-    for (Knob& kn : knobs) {
-        int best = *kn.v;
-        float best_ms = 1e30f;
-        for (int w : kn.cands) {
-            *kn.v = w;
-            float ms = 0.0f;
-            st = time_plan(ms);
-            if (st != GL_OK) break;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = w;
+    for (int sweep = 0; sweep < 2 && st == GL_OK; ++sweep) {
+        for (Knob& kn : knobs) {
+            int best = *kn.v;
+            float best_ms = 1e30f;
+            for (int w : kn.cands) {
+                *kn.v = w;
+                float ms = 0.0f;
+                st = time_plan(ms);
+                if (st != GL_OK) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = w;
+                }
             }
+            *kn.v = best;
+            if (st != GL_OK) break;
         }
-        *kn.v = best;
-        if (st != GL_OK) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

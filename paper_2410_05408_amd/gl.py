@@ -90,9 +90,10 @@ def lib():
         L.gl_ctx_get_plan.restype = i
         L.gl_ctx_set_plan.argtypes = [vp, i]
         L.gl_ctx_set_plan.restype = i
-        L.gl_ctx_get_stage_plan.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
+        L.gl_ctx_get_stage_plan.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
+                                            ctypes.POINTER(i)]
         L.gl_ctx_get_stage_plan.restype = i
-        L.gl_ctx_set_stage_plan.argtypes = [vp, i, i, i]
+        L.gl_ctx_set_stage_plan.argtypes = [vp, i, i, i, i]
         L.gl_ctx_set_stage_plan.restype = i
         L.gl_ctx_set_graph.argtypes = [vp, i]
         L.gl_ctx_set_graph.restype = i
@@ -313,14 +314,15 @@ def gl_ctx_set_plan(ctx, waves_per_cu: int) -> None:
 
 
 def gl_ctx_get_stage_plan(ctx):
-    """(classify, trap_hard, gk) persistent wavefronts per compute unit."""
-    c, t, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    _check(ctx, lib().gl_ctx_get_stage_plan(ctx, ctypes.byref(c), ctypes.byref(t), ctypes.byref(g)))
-    return c.value, t.value, g.value
+    """(classify, hard, trap, gk) persistent wavefronts per compute unit."""
+    c, h, t, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(ctx, lib().gl_ctx_get_stage_plan(ctx, ctypes.byref(c), ctypes.byref(h), ctypes.byref(t),
+                                            ctypes.byref(g)))
+    return c.value, h.value, t.value, g.value
 
 
-def gl_ctx_set_stage_plan(ctx, classify: int, trap_hard: int, gk: int) -> None:
-    _check(ctx, lib().gl_ctx_set_stage_plan(ctx, int(classify), int(trap_hard), int(gk)))
+def gl_ctx_set_stage_plan(ctx, classify: int, hard: int, trap: int, gk: int) -> None:
+    _check(ctx, lib().gl_ctx_set_stage_plan(ctx, int(classify), int(hard), int(trap), int(gk)))
 
 
 def gl_ctx_set_graph(ctx, on: bool) -> None:

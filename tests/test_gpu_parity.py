@@ -369,17 +369,17 @@ def test_autotune_keeps_results(gpu_lib, ctx):
     gl.gl_autotune(ctx.handle, d["params"], d["times"], out, n_ss=d["n_ss"], t_exp=d["t_exp"])
     wpc = gl.gl_ctx_get_plan(ctx.handle)
     plan = gl.gl_ctx_get_stage_plan(ctx.handle)
-    say(f"  tuned waves/CU {wpc}, stage plan (classify, trapezoid/hard, arcs) {plan}")
+    say(f"  tuned waves/CU {wpc}, stage plan (classify, hard, trapezoid, arcs) {plan}")
     assert plan[1] == wpc
     after, _ = run(gl, ctx, w)
     assert np.array_equal(before, after)
     # any plan gives the same results bit for bit (grid sizes only move work)
-    gl.gl_ctx_set_stage_plan(ctx.handle, 8, 4, 12)
-    assert gl.gl_ctx_get_stage_plan(ctx.handle) == (8, 4, 12)
+    gl.gl_ctx_set_stage_plan(ctx.handle, 8, 4, 6, 12)
+    assert gl.gl_ctx_get_stage_plan(ctx.handle) == (8, 4, 6, 12)
     other, _ = run(gl, ctx, w)
     assert np.array_equal(before, other)
     with pytest.raises(gl.GLError):
-        gl.gl_ctx_set_stage_plan(ctx.handle, 0, 16, 20)
+        gl.gl_ctx_set_stage_plan(ctx.handle, 0, 16, 16, 20)
     gl.gl_ctx_set_stage_plan(ctx.handle, *plan)
 
 
