@@ -2134,7 +2134,6 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
         hipLaunchKernelGGL((k_classify<CENSUS, false>), dim3((unsigned)(n_cu * ctx->waves_classify)), dim3(64), 0, st,
                            b.times, shared, ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks,
                            ctx->chunk_set, ctx->chunk_fb);
-    GL_MARK(E_CLASSIFY, st);
     const unsigned twaves = (unsigned)std::max<int64_t>(4, n_cu * ctx->waves_trap);
     // whole ellipses (trapezoid) need nothing from the hard-sample chain and
     // write other sub-samples, so the two run side by side.  The hard chain
@@ -2152,6 +2151,7 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
         GL_HIP(hipEventRecord(ctx->ev_fork, st), "hipEventRecord (fork)");
         GL_HIP(hipStreamWaitEvent(ts, ctx->ev_fork, 0), "hipStreamWaitEvent (fork)");
     }
+    GL_MARK(E_CLASSIFY, st);  // after the fork record: the hard stage starts with its kernel
     hipLaunchKernelGGL(k_hard<CENSUS>, dim3(waves), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
     GL_MARK(E_HARD, st);
     const unsigned arc_grid = ctx->waves_gk > 0 ? (unsigned)(n_cu * ctx->waves_gk) : waves;
