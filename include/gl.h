@@ -304,7 +304,7 @@ gl_status gl_ctx_get_overflow(gl_ctx *ctx, int64_t *fused_chunks, int *passes);
  * pipeline if their arguments equal the previous batch's (default on). */
 gl_status gl_ctx_set_graph(gl_ctx *ctx, int on);
 
-/* Stages of one batch, in launch order (timed separately):
+/* Stages of one batch (timed separately):
  *  0 set-up (parameter preparation, chunk scan), 1 window test (fills the
  *  outputs that cannot overlap the star), 2 classification, 3 whole-ellipse
  *  trapezoid, 4 hard samples (intersection quartic, break points, limb arcs),
@@ -312,9 +312,9 @@ gl_status gl_ctx_set_graph(gl_ctx *ctx, int on);
  *  trapezoid for whole ellipses near the limb, samples integrated in place,
  *  arcs from level 2 on), 7 combination of each hard sample's sums and
  *  supersample averages, 8 fused kernel for chunks beyond the work-list
- *  capacities.  Stage 3 (on a second stream of the context, joined before
- *  the averages) runs beside stages 4 to 6 and the combination (on the
- *  caller's stream): both need only the classification.  Stage 3 is timed
+ *  capacities.  Stages 3 and 8 (on a second stream of the context, joined
+ *  before the averages) run beside stages 4 to 6 and the combination (on the
+ *  caller's stream): all need only the classification.  Stage 3 is timed
  *  from the second stream's start, so stage times overlap and need not add
  *  up to the batch time. */
 #define GL_NSTAGES 9
@@ -328,8 +328,9 @@ gl_status gl_ctx_set_graph(gl_ctx *ctx, int on);
 gl_status gl_ctx_set_timing(gl_ctx *ctx, int n_slots);
 
 /* Returns the summed times (ms) from the start of stage 1 (compute) and of
- * stage 0 (pipeline) to the end of stage 8 over the timed batches, and how
- * many batches were timed; clears the sums.  Any output pointer may be NULL. */
+ * stage 0 (pipeline) to the end of stage 7 (the last on the caller's stream,
+ * after the join) over the timed batches, and how many batches were timed;
+ * clears the sums.  Any output pointer may be NULL. */
 gl_status gl_ctx_get_timing(gl_ctx *ctx, double *compute_ms, double *pipeline_ms, int *n);
 
 /* Like gl_ctx_get_timing, per stage: stage_ms[GL_NSTAGES] (host memory)

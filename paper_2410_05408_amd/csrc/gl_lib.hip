@@ -1711,15 +1711,16 @@ k_compute(const double* __restrict__ times, int shared_grid, const gl::SetConst*
 // ---------------------------------------------------------------- context
 // Timing events of one pass: the caller's stream marks the start and the
 // ends of set-up, window, classification, hard samples, arc levels, rare
-// paths, averages and fused stage; the second stream marks its start (its
-// wait on the classification met) and the end of the trapezoid stage.  Each
+// paths and averages (the pass's last stage: it waits for the second
+// stream); the second stream marks its start (its wait on the
+// classification met) and the ends of the trapezoid and fused stages.  Each
 // stage is timed between two of them (kStageEv), on the stream it runs on.
 enum {
-    E_START, E_SETUP, E_WINDOW, E_CLASSIFY, E_SIDE, E_TRAP, E_HARD, E_ARCS, E_RARE, E_AVERAGE, E_FUSED, kEvPerPass
+    E_START, E_SETUP, E_WINDOW, E_CLASSIFY, E_SIDE, E_TRAP, E_FUSED, E_HARD, E_ARCS, E_RARE, E_AVERAGE, kEvPerPass
 };
 constexpr int kStageEv[GL_NSTAGES][2] = {
     {E_START, E_SETUP}, {E_SETUP, E_WINDOW}, {E_WINDOW, E_CLASSIFY}, {E_SIDE, E_TRAP}, {E_CLASSIFY, E_HARD},
-    {E_HARD, E_ARCS},   {E_ARCS, E_RARE},    {E_RARE, E_AVERAGE},    {E_AVERAGE, E_FUSED}};
+    {E_HARD, E_ARCS},   {E_ARCS, E_RARE},    {E_RARE, E_AVERAGE},    {E_TRAP, E_FUSED}};
 
 // Passes: a batch whose in-window sub-samples exceed what one pass should
 // hold runs as up to kMaxPasses passes of the whole pipeline over equal
@@ -2164,6 +2165,18 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     hipLaunchKernelGGL(k_trap<CENSUS>, dim3((twaves + kTrapWaves - 1) / kTrapWaves), dim3(kTrapThreads), 0, ts,
                        ctx->sc, ctx->ctr, P);
     GL_MARK(E_TRAP, ts);
+    // the fused kernel takes the chunks the lists could not hold (few: a
+    // quarter wave per CU; it returns at once when none is queued), and every
+    // chunk of a tidally-locked set (general ellipsoids: a full grid at its
+    // occupancy of two waves per SIMD).  Only the window and classification
+    // queue chunks for it, and the averages skip those chunks, so it follows
+    // the trapezoid on the second stream, off the hard chain's path
+    const unsigned fused_grid = b.shape == 1 ? (unsigned)(n_cu * 8) : (unsigned)std::max<int64_t>(1, n_cu / 4);
+    auto fused = b.shape == 1 ? k_compute<CENSUS, true> : k_compute<CENSUS, false>;
+    hipLaunchKernelGGL(fused, dim3(fused_grid), dim3(64), 0, ts, b.times, shared,
+                       ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, ctx->masks, ctx->chunk_set,
+                       P, b.out);
+    GL_MARK(E_FUSED, ts);
     if (fork) {
         GL_HIP(hipEventRecord(ctx->ev_join, ts), "hipEventRecord (join)");
         GL_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0), "hipStreamWaitEvent (join)");
@@ -2179,15 +2192,6 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
                        ctx->seg_begin, ctx->chunk_off, ctx->ctr, P, ctx->masks, ctx->chunk_set,
                        ctx->chunk_fb, dem, b.out);
     GL_MARK(E_AVERAGE, st);
-    // the fused kernel takes the chunks the lists could not hold (few: a
-    // quarter wave per CU), and every chunk of a tidally-locked set (general
-    // ellipsoids: a full grid at its occupancy of two waves per SIMD)
-    const unsigned fused_grid = b.shape == 1 ? (unsigned)(n_cu * 8) : (unsigned)std::max<int64_t>(1, n_cu / 4);
-    auto fused = b.shape == 1 ? k_compute<CENSUS, true> : k_compute<CENSUS, false>;
-    hipLaunchKernelGGL(fused, dim3(fused_grid), dim3(64), 0, st, b.times, shared,
-                       ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, ctx->masks, ctx->chunk_set,
-                       P, b.out);
-    GL_MARK(E_FUSED, st);
 #undef GL_MARK
     GL_HIP(hipGetLastError(), "kernel launch");
     return GL_OK;
@@ -2287,7 +2291,8 @@ gl_status enqueue(gl_ctx* ctx, const Batch& b, bool census = false)
 
 // After a timed batch (t_pass passes recorded): waits for its stream and adds
 // its stage times (kStageEv), the compute time (end of set-up to end of the
-// fused stage) and the pipeline time (start to end of the fused stage).
+// averages, which wait for the second stream) and the pipeline time (start
+// to end of the averages).
 gl_status finish_timed(gl_ctx* ctx, hipStream_t s)
 {
     if (ctx->t_left <= 0 || ctx->t_pass <= 0) return GL_OK;
@@ -2300,9 +2305,9 @@ gl_status finish_timed(gl_ctx* ctx, hipStream_t s)
             ctx->t_stage[k] += ms;
         }
         float ms = 0.0f;
-        GL_HIP(hipEventElapsedTime(&ms, ev[E_SETUP], ev[E_FUSED]), "hipEventElapsedTime");
+        GL_HIP(hipEventElapsedTime(&ms, ev[E_SETUP], ev[E_AVERAGE]), "hipEventElapsedTime");
         ctx->t_comp += ms;
-        GL_HIP(hipEventElapsedTime(&ms, ev[E_START], ev[E_FUSED]), "hipEventElapsedTime");
+        GL_HIP(hipEventElapsedTime(&ms, ev[E_START], ev[E_AVERAGE]), "hipEventElapsedTime");
         ctx->t_pipe += ms;
     }
     ctx->t_batches++;
