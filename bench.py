@@ -464,6 +464,12 @@ def mcmc_leg(gl, workloads, steps, warmup, n_walkers=4096, dev="cuda:0"):
     params = torch.empty((10, n_walkers), dtype=torch.float64, device=dev)
     ctx = gl.Context(0)
     stream = torch.cuda.Stream()
+    # the stage plan tuned on the walkers' own light curves (the likelihood
+    # batch runs the same kernels, then the reduction)
+    gl.gl_walkers_to_params(wd, params)
+    torch.cuda.synchronize()
+    gl.gl_autotune(ctx.handle, params, td, model, n_ss=ss, t_exp=te, stream=stream)
+    plan = gl.gl_ctx_get_stage_plan(ctx.handle)
 
     def step():
         gl.gl_loglike_batch(ctx.handle, wd, td, dd, sd, model, chi2, ll, n_ss=ss, t_exp=te, stream=stream)
@@ -471,8 +477,8 @@ def mcmc_leg(gl, workloads, steps, warmup, n_walkers=4096, dev="cuda:0"):
     ms, med = timed_steps(step, stream, steps, warmup)
     if gl.gl_ctx_sync_status(ctx.handle) != gl.GL_OK:
         raise RuntimeError(gl.gl_ctx_last_error(ctx.handle))
-    gl.gl_walkers_to_params(wd, params)
     ctx2 = gl.Context(0)
+    gl.gl_ctx_set_stage_plan(ctx2.handle, *plan)
 
     def lc():
         gl.gl_lightcurve_batch(ctx2.handle, params, td, model, n_ss=ss, t_exp=te, stream=stream)
@@ -492,6 +498,7 @@ def mcmc_leg(gl, workloads, steps, warmup, n_walkers=4096, dev="cuda:0"):
         "config": {"workload": "jwst_visit_walker_ball", "n_walkers": n_walkers, "n_times": int(t.size),
                    "n_ss": n_ss, "cadence_min": 2.0, "sigma_ppm": 20.0},
         "ms_per_step": ms, "ms_median_event": med,
+        "stage_plan_classify_hard_trap_arcs": list(plan),
         "walker_evaluations_per_s": n_walkers / (ms * 1e-3),
         "points_per_s": n_walkers * t.size / (ms * 1e-3),
         "lightcurve_only_ms_median_event": med_lc,
@@ -594,6 +601,8 @@ def main():
         d = gl.to_device(w, "cuda:0")
         exact_out = torch.from_numpy(got).to("cuda:0")
         ctx = gl.Context(0)
+        # the exact leg's tuned plan (the gated batch runs the same kernels)
+        gl.gl_ctx_set_stage_plan(ctx.handle, *res["plan"]["stage_plan_classify_hard_trap_arcs"])
         res["surrogate"] = surrogate_leg(ctx, d, exact_out, res["ms_per_step"], w.n_out, args)
         ctx.close()
     if not args.no_cpu_baseline and not args.only:
