@@ -404,7 +404,7 @@ def timed_steps(step, stream, steps, warmup, trials=10):
 def ellipsoid_leg(gl, workloads, steps, warmup, dev="cuda:0"):
     """General and tidally-locked triaxial planets (gl_lightcurve_batch_ellipsoid):
     the mixed batch, and its free and locked halves on their own (locked sets
-    take the fused per-sample path)."""
+    take the fused per-sample path), each with its own autotuned plan."""
     import torch
     res = {}
     w = workloads.ellipsoid_batch()
@@ -427,6 +427,9 @@ def ellipsoid_leg(gl, workloads, steps, warmup, dev="cuda:0"):
         def step():
             gl.gl_lightcurve_batch_ellipsoid(ctx.handle, p, td, out, offsets=od, n_ss=ss, t_exp=te, stream=stream)
 
+        step()  # sizes the work lists from this batch's demand
+        gl.gl_autotune_ellipsoid(ctx.handle, p, td, out, offsets=od, n_ss=ss, t_exp=te, stream=stream)
+        plan = gl.gl_ctx_get_stage_plan(ctx.handle)
         ms, med = timed_steps(step, stream, steps, warmup)
         if gl.gl_ctx_sync_status(ctx.handle) != gl.GL_OK:
             raise RuntimeError(gl.gl_ctx_last_error(ctx.handle))
@@ -434,7 +437,8 @@ def ellipsoid_leg(gl, workloads, steps, warmup, dev="cuda:0"):
         n_sub = int(np.sum(seg * w.n_ss[idx]))
         res[name] = {"n_sets": int(idx.size), "outputs": int(times.size), "sub_samples": n_sub,
                      "in_transit_points": int(np.sum(got < 1.0)), "ms_per_step": ms, "ms_median_event": med,
-                     "points_per_s": times.size / (ms * 1e-3), "sub_samples_per_s": n_sub / (ms * 1e-3)}
+                     "points_per_s": times.size / (ms * 1e-3), "sub_samples_per_s": n_sub / (ms * 1e-3),
+                     "stage_plan_classify_hard_trap_arcs": list(plan)}
     res["unconverged_arcs"] = gl.gl_ctx_get_unconverged(ctx.handle)
     ctx.close()
     return res

@@ -254,6 +254,15 @@ gl_status gl_autotune(gl_ctx *ctx, const double *params, int64_t n_sets,
                       const int32_t *n_ss, const double *t_exp, double *out,
                       void *stream);
 
+/* gl_autotune on a batch of general ellipsoids (the arguments of
+ * gl_lightcurve_batch_ellipsoid): the same four knobs, timed on the graph of
+ * that batch (its tidally-locked sets run in the fused kernel beside the
+ * hard-sample chain, which moves the best grid sizes). */
+gl_status gl_autotune_ellipsoid(gl_ctx *ctx, const double *params, int64_t n_sets,
+                                const double *times, const int64_t *offsets, int64_t n_times,
+                                const int32_t *n_ss, const double *t_exp, double *out,
+                                void *stream);
+
 /* Current plan: persistent wavefronts per compute unit of the hard-sample
  * kernel. */
 gl_status gl_ctx_get_plan(const gl_ctx *ctx, int *waves_per_cu);

@@ -2588,11 +2588,12 @@ gl_status gl_ctx_set_graph(gl_ctx* ctx, int on)
     return GL_OK;
 }
 
-gl_status gl_autotune(gl_ctx* ctx, const double* params, int64_t n_sets, const double* times,
-                      const int64_t* offsets, int64_t n_times, const int32_t* n_ss,
-                      const double* t_exp, double* out, void* stream)
+}  // extern "C"
+
+namespace {
+
+gl_status autotune(gl_ctx* ctx, Batch b)
 {
-    Batch b{params, n_sets, times, offsets, n_times, n_ss, t_exp, out, (hipStream_t)stream, 0};
     gl_status st = check_args(ctx, b);
     if (st != GL_OK) return st;
     GL_HIP(hipSetDevice(ctx->device), "hipSetDevice");
@@ -2658,6 +2659,27 @@ gl_status gl_autotune(gl_ctx* ctx, const double* params, int64_t n_sets, const d
     (void)hipEventDestroy(e1);
     drop_graph(ctx);
     return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+gl_status gl_autotune(gl_ctx* ctx, const double* params, int64_t n_sets, const double* times,
+                      const int64_t* offsets, int64_t n_times, const int32_t* n_ss,
+                      const double* t_exp, double* out, void* stream)
+{
+    Batch b{params, n_sets, times, offsets, n_times, n_ss, t_exp, out, (hipStream_t)stream, 0};
+    return autotune(ctx, b);
+}
+
+gl_status gl_autotune_ellipsoid(gl_ctx* ctx, const double* params, int64_t n_sets, const double* times,
+                                const int64_t* offsets, int64_t n_times, const int32_t* n_ss,
+                                const double* t_exp, double* out, void* stream)
+{
+    Batch b{params, n_sets, times, offsets, n_times, n_ss, t_exp, out, (hipStream_t)stream, 0};
+    b.shape = 1;
+    return autotune(ctx, b);
 }
 
 gl_status gl_ctx_set_timing(gl_ctx* ctx, int n_slots)

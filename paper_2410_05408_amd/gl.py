@@ -32,7 +32,7 @@ EXPORTED = ("gl_ctx_create", "gl_ctx_destroy", "gl_lightcurve_batch", "gl_ctx_sy
             "gl_ctx_set_graph", "gl_ctx_set_capacity", "gl_ctx_set_timing", "gl_ctx_get_timing",
             "gl_ctx_get_stage_timing", "gl_census", "gl_flop_model", "gl_ctx_get_unconverged",
             "gl_ctx_get_overflow", "gl_lightcurve_batch_noalloc", "gl_lightcurve_batch_snap", "gl_version",
-            "gl_lightcurve_batch_ellipsoid", "gl_prior_mu_nu", "gl_walkers_to_params",
+            "gl_lightcurve_batch_ellipsoid", "gl_autotune_ellipsoid", "gl_prior_mu_nu", "gl_walkers_to_params",
             "gl_loglike_of_model", "gl_loglike_batch", "gl_ctx_get_stage_plan", "gl_ctx_set_stage_plan")
 CENSUS_NAMES = ("sub_in_window", "whole_on_star", "intersecting", "off_star_in_window",
                 "trapezoid_nodes", "gk21_pieces", "newton_steps", "limb_arcs",
@@ -68,6 +68,8 @@ def lib():
         L.gl_lightcurve_batch.restype = i
         L.gl_lightcurve_batch_ellipsoid.argtypes = batch_args
         L.gl_lightcurve_batch_ellipsoid.restype = i
+        L.gl_autotune_ellipsoid.argtypes = batch_args
+        L.gl_autotune_ellipsoid.restype = i
         L.gl_prior_mu_nu.argtypes = [vp, i64, vp, vp]
         L.gl_prior_mu_nu.restype = i
         L.gl_walkers_to_params.argtypes = [vp, i64, vp, vp]
@@ -287,6 +289,15 @@ def gl_autotune(ctx, params, times, out, offsets=None, n_ss=None, t_exp=None, st
     st = lib().gl_autotune(ctx, _ptr(params), params.shape[1], _ptr(times), _ptr(offsets),
                            times.numel(), _ptr(n_ss), _ptr(t_exp), _ptr(out),
                            _stream_handle(stream))
+    _check(ctx, st)
+
+
+def gl_autotune_ellipsoid(ctx, params, times, out, offsets=None, n_ss=None, t_exp=None, stream=None) -> None:
+    """gl_autotune on a general-ellipsoid batch (``params`` float64 [13, n_sets])."""
+    _validate(params, times, offsets, n_ss, t_exp, out, rows=GL_E_NPARAM)
+    st = lib().gl_autotune_ellipsoid(ctx, _ptr(params), params.shape[1], _ptr(times), _ptr(offsets),
+                                     times.numel(), _ptr(n_ss), _ptr(t_exp), _ptr(out),
+                                     _stream_handle(stream))
     _check(ctx, st)
 
 

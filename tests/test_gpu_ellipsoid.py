@@ -152,3 +152,36 @@ def test_domain_errors(gpu_lib, ctx):
     assert st == gpu_lib.GL_ERR_DOMAIN
     assert np.all(np.isnan(o[1:5]))
     assert np.all(np.isfinite(o[[0, 5]])) and np.min(o[[0, 5]]) < 1.0
+
+
+def test_autotune_ellipsoid_keeps_results(gpu_lib, oracle):
+    """gl_autotune_ellipsoid on a mixed batch picks a plan within the knobs'
+    candidates, and the batch gives the same outputs bit for bit under the
+    tuned plan (grid sizes only move work), still within the bar of the
+    oracle on sampled points."""
+    import torch
+    from paper_2410_05408_amd import workloads as W
+    gl = gpu_lib
+    say("case: ellipsoid autotune, 64 sets (32 locked) x 300 points, CSR")
+    w = W.ellipsoid_batch(n_sets=64, n_w=300, seed=21)
+    c = gl.Context(0)
+    try:
+        before, _ = run_ell(gl, c, w)
+        d = gl.to_device(w, "cuda:0")
+        out = torch.empty(w.n_out, dtype=torch.float64, device="cuda")
+        s = torch.cuda.Stream()
+        gl.gl_autotune_ellipsoid(c.handle, d["params"], d["times"], out, offsets=d["offsets"], n_ss=d["n_ss"],
+                                 t_exp=d["t_exp"], stream=s)
+        s.synchronize()
+        plan = gl.gl_ctx_get_stage_plan(c.handle)
+        say(f"  tuned plan (classify, hard, trapezoid, arcs) {plan}")
+        assert plan[0] in (8, 16, 24, 32, 48) and plan[1] in (8, 16, 24, 32, 48, 64)
+        assert plan[2] in (4, 8, 16, 24, 32, 48, 64) and plan[3] in (8, 12, 16, 20, 32, 48)
+        after, st = run_ell(gl, c, w)
+        assert st == gl.GL_OK
+        assert np.array_equal(before, after)
+        idx = np.arange(0, w.n_out, 7)
+        ref = oracle.flux_batch_ell(w.params, w.times, offsets=w.offsets, n_ss=w.n_ss, t_exp=w.t_exp)
+        assert np.max(np.abs(after[idx] - ref[idx])) <= TOL
+    finally:
+        c.close()
