@@ -240,9 +240,9 @@ const char *gl_ctx_last_error(const gl_ctx *ctx);
 /* Launch-plan autotuner: times the candidate persistent-grid sizes of the
  * work-list kernels on a representative batch (same arguments as
  * gl_lightcurve_batch; `out` is overwritten), one kernel group at a time
- * (hard-sample kernel {8, 16, 24, 32, 48, 64} waves per CU, trapezoid kernel
- * {4, 8, 16, 24, 32, 48, 64}, classification {8, 16, 24, 32, 48}, arc-rule
- * levels {8, 12, 16, 20, 32, 48}; more waves than fit at once queue behind
+ * (hard-sample kernel {4, 8, 16, 24, 32, 48, 64} waves per CU, trapezoid
+ * kernel {4, 8, 16, 24, 32, 48, 64}, classification {8, 16, 24, 32, 48, 64},
+ * arc-rule levels {8, 12, 16, 20, 32, 48, 64}; more waves than fit at once queue behind
  * the resident ones, which balances uneven per-wave work; coordinate descent
  * in two sweeps, each candidate timed as the median of five batches after a
  * warm-up, run the way the batch call runs: as a graph where `stream` allows)

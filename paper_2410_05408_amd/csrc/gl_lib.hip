@@ -2674,10 +2674,10 @@ gl_status autotune(gl_ctx* ctx, Batch b)
         int* v;
         std::vector<int> cands;
     };
-    Knob knobs[4] = {{&ctx->waves_per_cu, {8, 16, 24, 32, 48, 64}},
+    Knob knobs[4] = {{&ctx->waves_per_cu, {4, 8, 16, 24, 32, 48, 64}},
                      {&ctx->waves_trap, {4, 8, 16, 24, 32, 48, 64}},
-                     {&ctx->waves_classify, {8, 16, 24, 32, 48}},
-                     {&ctx->waves_gk, {8, 12, 16, 20, 32, 48}}};
+                     {&ctx->waves_classify, {8, 16, 24, 32, 48, 64}},
+                     {&ctx->waves_gk, {8, 12, 16, 20, 32, 48, 64}}};
     for (int sweep = 0; sweep < 2 && st == GL_OK; ++sweep) {
         for (Knob& kn : knobs) {
             int best = *kn.v;
