@@ -92,6 +92,43 @@ def test_walker_batch_full_size_sampled(gpu_lib, ctx, oracle):
     assert err2.max() <= TOL
 
 
+def test_walker_batch_bench_configuration(gpu_lib, oracle):
+    """The launch configuration bench.py times, at full size: a fresh context,
+    the plan from gl_autotune, the batch captured as a graph on a
+    non-default stream (hard-sample chain and trapezoid on two streams) and
+    replayed; every replay equals the direct launch bit for bit, and sampled
+    in-transit outputs are within the bar of the oracle."""
+    import torch
+    from paper_2410_05408_amd import workloads as W
+    gl = gpu_lib
+    say("case: walker batch full size in the bench's configuration (autotuned plan, graph replays)")
+    w = W.walker_batch()
+    c = gl.Context(0)
+    try:
+        direct, st = run(gl, c, w)
+        assert st == gl.GL_OK
+        d = gl.to_device(w, "cuda:0")
+        out = torch.empty(w.n_out, dtype=torch.float64, device="cuda")
+        s = torch.cuda.Stream()
+        gl.gl_autotune(c.handle, d["params"], d["times"], out, n_ss=d["n_ss"], t_exp=d["t_exp"], stream=s)
+        s.synchronize()
+        say(f"  plan (classify, hard, trapezoid, arcs) {gl.gl_ctx_get_stage_plan(c.handle)}")
+        for rep in range(2):
+            o = c.batch(d["params"], d["times"], n_ss=d["n_ss"], t_exp=d["t_exp"], stream=s)
+            s.synchronize()
+            assert gl.gl_ctx_sync_status(c.handle) == gl.GL_OK
+            assert np.array_equal(o.cpu().numpy().reshape(w.n_sets, -1), direct), f"replay {rep}"
+        rng = np.random.default_rng(5)
+        changed = np.flatnonzero(direct.ravel() < 1.0)
+        sel = rng.choice(changed, min(500, changed.size), replace=False)
+        refs = oracle.flux_select(w.params, w.times, sel, n_ss=w.n_ss, t_exp=w.t_exp)
+        err = np.abs(direct.ravel()[sel] - refs)
+        say(f"  500 in-transit outputs: max err {err.max():.3e}")
+        assert err.max() <= TOL
+    finally:
+        c.close()
+
+
 def test_high_cadence_all_points(gpu_lib, ctx, oracle):
     from paper_2410_05408_amd import workloads as W
     say("case: high cadence 512 x 65536, all 33.5M points")
