@@ -16,6 +16,11 @@
 //   gl_host_check ell P T O      general ellipsoids: P float64 [13][n], the
 //                                per-sample shadow of locked sets from
 //                                lock_at; prints the unconverged arc count
+//   gl_host_check guesses Q O    first iterates of the quartic solver: Q
+//                                float64 coefficients [n][5] (a0..a4), O
+//                                float64 [n][5]: the real root of q' when it
+//                                has one (else NaN), then the four Ferrari
+//                                guesses for the roots of q (NaN where none)
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -129,6 +134,25 @@ int main(int argc, char** argv)
         std::fclose(f);
         return ok ? 0 : 4;
     }
-    std::fprintf(stderr, "usage: gl_host_check math | flux params times out | snap nodes params times out | ell params times out\n");
+    if (argc == 4 && std::strcmp(argv[1], "guesses") == 0) {
+        const std::vector<double> q = read_all(argv[2]);
+        if (q.empty() || q.size() % 5) return 2;
+        const size_t n = q.size() / 5;
+        std::vector<double> out(5 * n);
+        for (size_t i = 0; i < n; ++i) {
+            const gl::Poly4 p{q[5 * i], q[5 * i + 1], q[5 * i + 2], q[5 * i + 3], q[5 * i + 4]};
+            out[5 * i] = gl::cubic_one_root(p);
+            float g[4];
+            gl::quartic_guesses(p, g);
+            for (int k = 0; k < 4; ++k) out[5 * i + 1 + k] = (double)g[k];
+        }
+        FILE* f = std::fopen(argv[3], "wb");
+        if (!f) return 3;
+        const bool ok = std::fwrite(out.data(), sizeof(double), out.size(), f) == out.size();
+        std::fclose(f);
+        return ok ? 0 : 4;
+    }
+    std::fprintf(stderr, "usage: gl_host_check math | flux params times out | snap nodes params times out | "
+                         "ell params times out | guesses coeffs out\n");
     return 1;
 }

@@ -152,3 +152,58 @@ def test_host_ellipsoid_matches_oracle(host_check, oracle, tmp_path, locked):
     assert np.sum(got < 1.0) > n // 2
     assert np.max(np.abs(got - ref)) <= 1e-9
     assert unconv == 0
+
+
+def host_guesses(exe, tmp_path, coeffs):
+    qf, of = str(tmp_path / "q.bin"), str(tmp_path / "g.bin")
+    np.ascontiguousarray(coeffs, dtype=np.float64).tofile(qf)
+    subprocess.run([exe, "guesses", qf, of], check=True)
+    return np.fromfile(of).reshape(-1, 5)
+
+
+def _quartic(a4, b1, c1, b2, c2):
+    """Coefficients a0..a4 of a4 (t^2 + b1 t + c1)(t^2 + b2 t + c2)."""
+    return np.stack([a4 * c1 * c2, a4 * (b1 * c2 + b2 * c1), a4 * (c1 + c2 + b1 * b2), a4 * (b1 + b2), a4], axis=1)
+
+
+def test_quartic_first_iterates(host_check, tmp_path):
+    """The closed-form first iterates of the quartic solver (host build of the
+    same source): Ferrari's guesses land on both real roots of a quartic with
+    two real roots and a complex pair, and are all NaN when it has none or
+    four; Cardano's root of q' is its real root when it has one and NaN when
+    it has three.  The roots come from the construction and from numpy."""
+    rng = np.random.default_rng(17)
+    n = 4000
+    a4 = rng.choice([-1.0, 1.0], n) * rng.uniform(0.1, 1.0, n)
+    r = np.sort(rng.uniform(-1.8, 1.8, (n, 2)), axis=1)
+    r[:, 1] = np.maximum(r[:, 1], r[:, 0] + 1e-2)
+    p = rng.uniform(-1.0, 1.0, n)
+    s = 0.25 * p * p + rng.uniform(0.05, 2.0, n)            # t^2 + p t + s has no real root
+    two = _quartic(a4, -(r[:, 0] + r[:, 1]), r[:, 0] * r[:, 1], p, s)
+    g = host_guesses(host_check, tmp_path, two)
+    fin = np.isfinite(g[:, 1:])
+    assert np.all(fin.sum(axis=1) == 2)
+    for k in (0, 1):
+        d = np.where(fin, np.abs(g[:, 1:] - r[:, k:k + 1]), np.inf).min(axis=1) / np.maximum(1.0, np.abs(r[:, k]))
+        assert d.max() <= 1e-5, d.max()
+    # no real root, and four: every guess NaN
+    p2 = rng.uniform(-1.0, 1.0, n)
+    s2 = 0.25 * p2 * p2 + rng.uniform(0.05, 2.0, n)
+    none = _quartic(a4, p, s, p2, s2)
+    r4 = np.sort(rng.uniform(-1.8, 1.8, (n, 4)), axis=1)
+    r4 += np.arange(4) * 0.05                                # distinct roots
+    four = _quartic(a4, -(r4[:, 0] + r4[:, 1]), r4[:, 0] * r4[:, 1], -(r4[:, 2] + r4[:, 3]), r4[:, 2] * r4[:, 3])
+    for q in (none, four):
+        assert np.all(np.isnan(host_guesses(host_check, tmp_path, q)[:, 1:]))
+    # the real root of q' = 4 a4 t^3 + 3 a3 t^2 + 2 a2 t + a1
+    for q, gq in ((two, g), (none, host_guesses(host_check, tmp_path, none))):
+        for i in range(n):
+            cr = np.roots([4 * q[i, 4], 3 * q[i, 3], 2 * q[i, 2], q[i, 1]])
+            im = np.abs(cr.imag)
+            if np.all(im < 1e-7):
+                gap = np.min(np.diff(np.sort(cr.real)))
+                if gap > 1e-3:
+                    assert np.isnan(gq[i, 0]), (i, cr, gq[i, 0])
+            elif np.sum(im < 1e-12) == 1 and np.min(im[im >= 1e-12]) > 1e-3:
+                x = cr.real[np.argmin(im)]
+                assert abs(gq[i, 0] - x) <= 1e-5 * max(1.0, abs(x)), (i, x, gq[i, 0])
