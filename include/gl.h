@@ -244,7 +244,7 @@ const char *gl_ctx_last_error(const gl_ctx *ctx);
  * kernel {4, 8, 16, 24, 32, 48, 64}, classification {8, 16, 24, 32, 48, 64},
  * arc-rule levels {8, 12, 16, 20, 32, 48, 64}; more waves than fit at once queue behind
  * the resident ones, which balances uneven per-wave work; coordinate descent
- * in two sweeps, each candidate timed as the median of five batches after a
+ * in two sweeps, each candidate timed as the median of seven batches after a
  * warm-up, run the way the batch call runs: as a graph where `stream` allows)
  * and keeps the fastest in the context's plan.  Synchronises `stream`.
  * Quadrature orders are not a plan setting: every sample picks its own

@@ -2647,7 +2647,7 @@ gl_status autotune(gl_ctx* ctx, Batch b)
     // coordinate descent over the four grid sizes: hard-sample kernel,
     // trapezoid kernel (beside the hard chain, where a smaller grid can leave
     // the chain more of the chip), classification, arc levels; two sweeps.
-    // Each candidate: one warm-up batch, then the median of five timed ones.
+    // Each candidate: one warm-up batch, then the median of seven timed ones.
     // Candidates run the way the batch call will run them: captured and
     // replayed as a graph where the caller's stream allows one (branches of a
     // graph and of direct launches overlap differently).
@@ -2655,8 +2655,9 @@ gl_status autotune(gl_ctx* ctx, Batch b)
         Batch c = b;
         gl_status r = lightcurve(ctx, c);  // warm-up (and the capture)
         if (r != GL_OK) return r;
-        float t[5];
-        for (int rep = 0; rep < 5; ++rep) {
+        constexpr int kReps = 7;
+        float t[kReps];
+        for (int rep = 0; rep < kReps; ++rep) {
             (void)hipEventRecord(e0, b.stream);
             c = b;
             r = lightcurve(ctx, c);
@@ -2666,8 +2667,8 @@ gl_status autotune(gl_ctx* ctx, Batch b)
             (void)hipEventElapsedTime(&t[rep], e0, e1);
             if (r != GL_OK) return r;
         }
-        std::sort(t, t + 5);
-        ms_out = t[2];
+        std::sort(t, t + kReps);
+        ms_out = t[kReps / 2];
         return r;
     };
     struct Knob {
