@@ -374,6 +374,13 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
 #ifndef GL_CHAIN_PRIO
 #define GL_CHAIN_PRIO 2
 #endif
+// Where a surrogate batch evaluates its network: 0 after the join on the
+// caller's stream; 1 on the second stream, before the trapezoid and the fused
+// kernel; 2 on the second stream, with the trapezoid and the fused kernel
+// after the hard chain on the caller's stream.
+#ifndef GL_SUR_NET_SIDE
+#define GL_SUR_NET_SIDE 2
+#endif
 // Default persistent grid of the trapezoid stage in wavefronts per CU.
 #ifndef GL_TRAP_WAVES_PER_CU
 #define GL_TRAP_WAVES_PER_CU 16
@@ -2214,10 +2221,23 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     launch_rare<CENSUS>(ctx, st, arc_grid, P);
     GL_MARK(E_RARE, st);
     hipLaunchKernelGGL(k_combine, dim3((unsigned)(n_cu * 8)), dim3(256), 0, st, ctx->sc, ctx->ctr, P);
-    GL_MARK(E_SIDE, ts);
-    hipLaunchKernelGGL(k_trap<CENSUS>, dim3((twaves + kTrapWaves - 1) / kTrapWaves), dim3(kTrapThreads), 0, ts,
+    // the network's rows (surrogate batches) need only the classification:
+    // their features are gathered and the network evaluated on the second
+    // stream, on the matrix cores beside the hard chain's FP64 work; the
+    // residuals are added after the join
+    auto net_rows = [&](hipStream_t s) {
+        hipLaunchKernelGGL(k_net_gather, dim3((unsigned)(n_cu * 8)), dim3(64), 0, s, ctx->sc, ctx->ctr, P);
+        gl_net::infer(b.net, P.net_x, (int64_t)kShards * P.scap[L_NET], &ctx->ctr->net_total, P.net_y, s);
+    };
+    const bool net_side = sur && GL_SUR_NET_SIDE >= 1;
+    if (net_side) net_rows(ts);
+    // the network's launch then makes the second stream the longer branch:
+    // the trapezoid and the fused kernel follow the hard chain instead
+    hipStream_t xs = (net_side && GL_SUR_NET_SIDE == 2) ? st : ts;
+    GL_MARK(E_SIDE, xs);
+    hipLaunchKernelGGL(k_trap<CENSUS>, dim3((twaves + kTrapWaves - 1) / kTrapWaves), dim3(kTrapThreads), 0, xs,
                        ctx->sc, ctx->ctr, P);
-    GL_MARK(E_TRAP, ts);
+    GL_MARK(E_TRAP, xs);
     // the fused kernel takes the chunks the lists could not hold (few: a
     // quarter wave per CU; it returns at once when none is queued), and every
     // chunk of a tidally-locked set (general ellipsoids: a full grid at its
@@ -2226,18 +2246,17 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     // the trapezoid on the second stream, off the hard chain's path
     const unsigned fused_grid = b.shape == 1 ? (unsigned)(n_cu * 8) : (unsigned)std::max<int64_t>(1, n_cu / 4);
     auto fused = b.shape == 1 ? k_compute<CENSUS, true> : k_compute<CENSUS, false>;
-    hipLaunchKernelGGL(fused, dim3(fused_grid), dim3(64), 0, ts, b.times, shared,
+    hipLaunchKernelGGL(fused, dim3(fused_grid), dim3(64), 0, xs, b.times, shared,
                        ctx->sc, ctx->seg_begin, ctx->chunk_off, ctx->ctr, ctx->masks, ctx->chunk_set,
                        P, b.out);
-    GL_MARK(E_FUSED, ts);
+    GL_MARK(E_FUSED, xs);
     if (fork) {
         GL_HIP(hipEventRecord(ctx->ev_join, ts), "hipEventRecord (join)");
         GL_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0), "hipStreamWaitEvent (join)");
     }
     if (sur) {
         // the network's residuals on the accepted sub-samples' sphere fluxes
-        hipLaunchKernelGGL(k_net_gather, dim3((unsigned)(n_cu * 8)), dim3(64), 0, st, ctx->sc, ctx->ctr, P);
-        gl_net::infer(b.net, P.net_x, (int64_t)kShards * P.scap[L_NET], &ctx->ctr->net_total, P.net_y, st);
+        if (!net_side) net_rows(st);
         hipLaunchKernelGGL(k_net_add, dim3((unsigned)(n_cu * 8)), dim3(256), 0, st, ctx->ctr, P);
     }
     const DemandArgs dem{ctx->rec_dev, b.first, b.last, ctx->passes, (double)b.slots};
