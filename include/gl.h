@@ -325,7 +325,9 @@ gl_status gl_ctx_set_graph(gl_ctx *ctx, int on);
  *  before the averages) run beside stages 4 to 6 and the combination (on the
  *  caller's stream): all need only the classification.  Stage 3 is timed
  *  from the second stream's start, so stage times overlap and need not add
- *  up to the batch time. */
+ *  up to the batch time.  In a surrogate batch the second stream evaluates
+ *  the network instead, and stages 3 and 8 follow the combination on the
+ *  caller's stream. */
 #define GL_NSTAGES 9
 
 /* Instrumentation: with n_slots > 0, the next n_slots batches are launched

@@ -2243,7 +2243,8 @@ gl_status enqueue_t(gl_ctx* ctx, const Batch& b)
     // chunk of a tidally-locked set (general ellipsoids: a full grid at its
     // occupancy of two waves per SIMD).  Only the window and classification
     // queue chunks for it, and the averages skip those chunks, so it follows
-    // the trapezoid on the second stream, off the hard chain's path
+    // the trapezoid, off the hard chain's path (on the caller's stream after
+    // the chain in a surrogate batch)
     const unsigned fused_grid = b.shape == 1 ? (unsigned)(n_cu * 8) : (unsigned)std::max<int64_t>(1, n_cu / 4);
     auto fused = b.shape == 1 ? k_compute<CENSUS, true> : k_compute<CENSUS, false>;
     hipLaunchKernelGGL(fused, dim3(fused_grid), dim3(64), 0, xs, b.times, shared,
