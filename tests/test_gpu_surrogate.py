@@ -90,6 +90,20 @@ def test_gated_light_curves_within_1ppm_and_network_gains(gpu_lib, ctx, tmp_path
     assert n_sub == n_sub_z
     assert n_fb < n_sub
     assert n_fb <= n_fb_z  # the per-bin choice never accepts less than the sphere alone
+    # the same gated batch on a stream of the caller (forked to the context's
+    # second stream for the network, the trapezoid after the hard chain)
+    # equals the null-stream launch bit for bit, on every repeat
+    say("case: gated batch on a stream, three repeats")
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    out_g = torch.empty_like(exact)
+    for rep in range(3):
+        with torch.cuda.stream(st):
+            out_g.fill_(-7.0)
+        n_sub_g, n_fb_g = sur.lightcurve(d, out_g, tol=1e-6, stream=st)
+        st.synchronize()
+        assert (n_sub_g, n_fb_g) == (n_sub, n_fb)
+        assert torch.equal(out_g, out), f"repeat {rep}"
     # a saved and reloaded surrogate gives the same light curves bit for bit
     say("case: surrogate saved and loaded back")
     path = str(tmp_path / "walker.glsur")
